@@ -1,0 +1,219 @@
+/*
+ * cpm.h - C ABI of libcpm: the closest point method (CPM) with interior
+ * boundary conditions on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: King, Su, Aanjaneya, Ruuth, Batty, "A Closest Point Method for PDEs
+ * on Manifolds with Interior Boundary Conditions for Geometry Processing",
+ * ACM TOG 2024 (arXiv 2305.04711).
+ *
+ * Conventions shared by every entry point
+ *  - Grid: nodes x_k = k / N, k in Z^d, spacing h = 1/N (Sec. 3.2).
+ *  - Unknowns (Sec. 4.1): n = n_s + n_c values.  PDE DOFs 0..n_s-1 are the
+ *    band nodes in the library's block order (see cpm_band_export
+ *    CPM_EXPORT_COORDS for their grid coordinates); BC DOFs n_s..n-1 follow,
+ *    grouped by interior boundary in the order given, each group in the
+ *    order of its nodes' PDE DOFs.
+ *  - System (Sec. 5.4): A = m I + n [diag(L) + (L - diag L) E], with E the
+ *    closest-point extension by tensor-product cubic Lagrange interpolation
+ *    (eq. interp-stencil) with interior-boundary swaps (eq.
+ *    stencil-crossing-test, eq. FD-crossing-test) and L the 2d+1-point
+ *    Laplacian (eq. FD-stencil).  The affine Dirichlet part of E is moved to
+ *    the right-hand side: A u = f - n (L - diag L) e(g) (see cpm_rhs).
+ *  - Multi-RHS vectors are stored right-hand side by right-hand side:
+ *    element (j, i) of an nrhs x len array is at [j * len + i].
+ *  - Device pointers are HIP device memory of the current device; the caller
+ *    owns every vector passed in.  A band owns its internal arrays and frees
+ *    them in cpm_band_free.
+ *  - Every call that takes hip_stream enqueues its work on that stream
+ *    (NULL = the null stream).  cpm_apply, cpm_apply_transpose, cpm_rhs and
+ *    cpm_rhs_adjoint return without synchronising; cpm_build_band, the solves
+ *    and cpm_band_export synchronise the stream before returning.
+ *  - Errors: every call returns a cpm_status; on failure cpm_last_error()
+ *    gives a message for the calling thread.  No exception crosses the ABI.
+ */
+#ifndef CPM_H
+#define CPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CPM_OK = 0,
+  CPM_E_INVALID = -1,        /* bad argument, unsupported option            */
+  CPM_E_STENCIL_HOLE = -2,   /* an interpolation member is not a band node  */
+  CPM_E_OOM = -3,            /* device allocation failed                    */
+  CPM_E_HIP = -4,            /* a HIP runtime call failed                   */
+  CPM_E_NOCONV = -5,         /* solve did not reach tol within maxit        */
+  CPM_E_BREAKDOWN = -6,      /* Krylov breakdown that restarts did not cure */
+  CPM_E_REACH = -7,          /* h too large for the surface's reach         */
+  CPM_E_OVERLAP = -8         /* check regions of two interior boundaries meet */
+} cpm_status;
+
+/* ---- geometry (closest-point representations, App. A: analytic) ------- */
+enum { CPM_SURF_CIRCLE = 1,  /* R^2: centre, R                          */
+       CPM_SURF_SPHERE = 2,  /* R^3: centre, R                          */
+       CPM_SURF_TORUS = 3 }; /* R^3: centre, R (core), rho (tube); axis z */
+
+typedef struct {
+  int kind;
+  double center[3];
+  double R;
+  double rho;
+} cpm_surface;
+
+enum { CPM_IBC_POINT = 1,     /* C = {p}; orient = o_C given by the caller   */
+       CPM_IBC_LATITUDE = 2,  /* sphere only: circle at height center_z + z0 */
+       CPM_IBC_MERIDIAN = 3 };/* torus only: poloidal circle in the vertical
+                                 plane with horizontal unit direction dir   */
+
+typedef struct {
+  int kind;
+  double p[3];       /* POINT: the point (on S)                               */
+  double orient[3];  /* POINT: o_C, the side a closest point lying on C
+                        (within tau of it) is assigned to (Sec. 4.2)          */
+  double z0;         /* LATITUDE                                              */
+  double dir[2];     /* MERIDIAN: (ex, ey), a unit vector                     */
+} cpm_ibc;
+
+typedef struct {
+  int N;               /* h = 1/N                                             */
+  int p;               /* interpolation degree; only 3 is supported           */
+  int order;           /* Dirichlet IBC order: 1 or 2 (Sec. 4.3)              */
+  int check_reach;     /* 1: reject h above the reach bound (Sec. 8 grid
+                          resolution in practice)                           */
+  double r_band;       /* 0 = eq. (bandwidth) with q = 1                      */
+  double tau_factor;   /* 0 = 0.1: on-C tolerance tau = tau_factor h^2 (Sec. 4.2) */
+  double check_factor; /* 0 = 2: check region ||x - cp_C(x)|| < check_factor r (Sec. 4.6) */
+} cpm_grid;
+
+typedef struct cpm_band cpm_band;
+
+typedef struct {
+  int dim, N, n_ibc, order;
+  int64_t n_s, n_c, n;          /* PDE, BC and total DOFs                     */
+  int64_t n_blocks;             /* occupied 4x4x4 (8x8 in 2-D) blocks         */
+  int64_t n_tiles;              /* gather tiles (occupied stencil-base blocks) */
+  int64_t n_erows, n_lrows;     /* rows with explicit E / L stencils           */
+  int64_t on_c_nodes;           /* nodes whose cp_S lies within tau of C      */
+  int64_t no_bc_dof_swaps;      /* opposite-side members with no BC DOF       */
+  double h, r_band, tau;
+  size_t device_bytes;          /* bytes the band holds on the device         */
+} cpm_band_info;
+
+/* Build the band Omega(S) (eq. bandwidth, Alg. 1 semantics: every node within
+ * r of S), Omega(C), the check region and side vectors for each interior
+ * boundary (Sec. 4.1, 4.2, 4.6), the interpolation and FD stencils with their
+ * swaps and the BC-DOF rows (Sec. 4.3).  Membership and stencil decisions are
+ * taken in FP64 in a fixed evaluation order.
+ *   ibcs may be NULL when n_ibc == 0.  On success *out owns device memory.
+ *   Errors: CPM_E_INVALID (N <= 0, p != 3, unknown kind, IBC kind that does
+ *   not fit the surface), CPM_E_REACH, CPM_E_STENCIL_HOLE (message gives the
+ *   count), CPM_E_OVERLAP, CPM_E_OOM, CPM_E_HIP. */
+cpm_status cpm_build_band(const cpm_surface* surface, const cpm_ibc* ibcs,
+                          int n_ibc, const cpm_grid* grid, void* hip_stream,
+                          cpm_band** out);
+
+void cpm_band_free(cpm_band* band);
+
+cpm_status cpm_band_query(const cpm_band* band, cpm_band_info* out);
+
+/* Copy band data to host memory in DOF order (for parity checks and for
+ * evaluating data at closest points, Sec. 5.2).  bytes must equal the size
+ * stated for `what`; otherwise CPM_E_INVALID. */
+enum {
+  CPM_EXPORT_COORDS = 1,   /* int32 [n_s][d]  grid coordinates k             */
+  CPM_EXPORT_CP = 2,       /* double [n_s][d] stored cp_S(x_k)               */
+  CPM_EXPORT_BC_NODE = 3,  /* int32 [n_c]     PDE DOF of each BC DOF's node  */
+  CPM_EXPORT_BC_CPC = 4,   /* double [n_c][d] cp_C at that node              */
+  CPM_EXPORT_BC_SIDE = 5,  /* int32 [n_c]     own side (+1/-1, sign v.o_C)   */
+  CPM_EXPORT_BC_CURVE = 6, /* int32 [n_c]     index of the interior boundary */
+  CPM_EXPORT_ECOLS = 7,    /* int32 [n][4^d]  E columns after swaps, member
+                              o = (o%4, o/4%4, o/16) from the base; -1 none */
+  CPM_EXPORT_LCOLS = 8,    /* int32 [n][2d]   L off-diagonal columns after
+                              swaps in order -x,+x,-y,+y,-z,+z; -1 dropped  */
+  CPM_EXPORT_BASE = 9      /* int32 [n][d]    interpolation stencil base
+                              (BC rows: of the mirror point; 0 if none)     */
+};
+cpm_status cpm_band_export(const cpm_band* band, int what, void* host_dst,
+                           size_t bytes);
+
+enum { CPM_F64 = 0, CPM_F32 = 1 };
+
+/* v = A u for the linear part of A (Sec. 5.4, four-step product: a = E u,
+ * b = (L - diag L) a, then v = m u + n diag(L) u + n b), nrhs right-hand
+ * sides.  dtype CPM_F64: u, v are double; CPM_F32: float with FP32 weights.
+ * u and v are device arrays [nrhs][n] and must not alias. */
+cpm_status cpm_apply(const cpm_band* band, double m, double n, int dtype,
+                     int nrhs, const void* u, void* v, void* hip_stream);
+
+/* z = A^T w = m w + n diag(L) w + n E^T ((L - diag L)^T w): the transpose of
+ * cpm_apply (derived from Sec. 5.4).  The E^T product scatters with atomics,
+ * so the FP rounding order varies from call to call. */
+cpm_status cpm_apply_transpose(const cpm_band* band, double m, double n,
+                               int dtype, int nrhs, const void* w, void* z,
+                               void* hip_stream);
+
+/* b = P f - n (L - diag L) e(g): f [nrhs][n_s] is the closest-point
+ * extension of the source (Sec. 5.2), copied to each BC DOF from the PDE DOF
+ * of its node; g [nrhs][n_c] holds the Dirichlet value each BC DOF enforces,
+ * e(g) = g (first order) or 2 g (second order) on BC DOFs (Sec. 4.3).
+ * g may be NULL when n_c == 0.  Device pointers, double; b is [nrhs][n]. */
+cpm_status cpm_rhs(const cpm_band* band, double n, int nrhs, const double* f,
+                   const double* g, double* b, void* hip_stream);
+
+/* Gradients of a scalar loss through b(f, g) given lambda = A^-T dl/du:
+ * grad_f = P^T lambda [nrhs][n_s], grad_g = -n c (L - diag L)^T lambda on
+ * the BC DOFs [nrhs][n_c] (c = 1 or 2 as above).  grad_g may be NULL. */
+cpm_status cpm_rhs_adjoint(const cpm_band* band, double n, int nrhs,
+                           const double* lambda, double* grad_f,
+                           double* grad_g, void* hip_stream);
+
+enum { CPM_SOLVE_MIXED = 0,  /* FP32 BiCGSTAB + FP64 iterative refinement */
+       CPM_SOLVE_F64 = 1 };  /* plain FP64 BiCGSTAB                        */
+
+typedef struct {
+  double m, n;        /* A = m I + n M                                       */
+  double tol;         /* stop when ||b - A x||_2 <= tol ||b||_2 (FP64)       */
+  int mode;           /* CPM_SOLVE_MIXED or CPM_SOLVE_F64                    */
+  int maxit;          /* cap on Krylov iterations in total (0 = 20000)       */
+  double inner_tol;   /* mixed: FP32 inner relative tolerance (0 = 1e-2); each
+                         refinement step runs at most 1000 FP32 iterations  */
+  int check_every;    /* iterations between convergence read-backs (0 = 16)  */
+  int use_graph;      /* 1: replay the check_every iterations as a hipGraph  */
+  double gauge;       /* >0: solve (A + gauge 1 w^T) x = b, w = 1/n_s on PDE
+                         DOFs (closed-surface Poisson); 0 = off              */
+} cpm_solve_opts;
+
+typedef struct {
+  int converged;
+  int outer_iters;    /* refinement steps (1 for CPM_SOLVE_F64)              */
+  int krylov_iters;   /* BiCGSTAB iterations in total                       */
+  int restarts;       /* breakdown restarts                                 */
+  int fallback_f64;   /* mixed: inner solve fell back to FP64               */
+  double relres;      /* final true FP64 relative residual (max over RHS)   */
+  double time_ms;     /* wall time of the call                              */
+} cpm_solve_stats;
+
+/* Solve A x = b (Sec. 5.4) for nrhs right-hand sides; b and x are device
+ * double arrays [nrhs][n]; x holds the initial guess on entry (warm start)
+ * and the solution on return.  On CPM_E_NOCONV x holds the last iterate and
+ * stats are filled.  stats may be NULL. */
+cpm_status cpm_solve(const cpm_band* band, const cpm_solve_opts* opts,
+                     int nrhs, const double* b, double* x,
+                     cpm_solve_stats* stats, void* hip_stream);
+
+/* Solve A^T lambda = rhs (same options and conventions as cpm_solve). */
+cpm_status cpm_solve_adjoint(const cpm_band* band, const cpm_solve_opts* opts,
+                             int nrhs, const double* rhs, double* lambda,
+                             cpm_solve_stats* stats, void* hip_stream);
+
+const char* cpm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CPM_H */

@@ -1,0 +1,115 @@
+"""ctypes declarations of the C ABI in include/cpm.h (argument marshalling
+only: every step of the method runs in libcpm's HIP kernels).
+
+Loading fails loudly: there is no CPU fallback.
+"""
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcpm.so")
+
+# status codes
+OK, E_INVALID, E_STENCIL_HOLE, E_OOM, E_HIP, E_NOCONV, E_BREAKDOWN, E_REACH, E_OVERLAP = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8
+STATUS_NAMES = {0: "CPM_OK", -1: "CPM_E_INVALID", -2: "CPM_E_STENCIL_HOLE", -3: "CPM_E_OOM",
+                -4: "CPM_E_HIP", -5: "CPM_E_NOCONV", -6: "CPM_E_BREAKDOWN",
+                -7: "CPM_E_REACH", -8: "CPM_E_OVERLAP"}
+
+SURF_CIRCLE, SURF_SPHERE, SURF_TORUS = 1, 2, 3
+IBC_POINT, IBC_LATITUDE, IBC_MERIDIAN = 1, 2, 3
+EXPORT_COORDS, EXPORT_CP, EXPORT_BC_NODE, EXPORT_BC_CPC, EXPORT_BC_SIDE, EXPORT_BC_CURVE, \
+    EXPORT_ECOLS, EXPORT_LCOLS, EXPORT_BASE = range(1, 10)
+F64, F32 = 0, 1
+SOLVE_MIXED, SOLVE_F64 = 0, 1
+
+
+class Surface(C.Structure):
+    _fields_ = [("kind", C.c_int), ("center", C.c_double * 3), ("R", C.c_double),
+                ("rho", C.c_double)]
+
+
+class IBC(C.Structure):
+    _fields_ = [("kind", C.c_int), ("p", C.c_double * 3), ("orient", C.c_double * 3),
+                ("z0", C.c_double), ("dir", C.c_double * 2)]
+
+
+class Grid(C.Structure):
+    _fields_ = [("N", C.c_int), ("p", C.c_int), ("order", C.c_int), ("check_reach", C.c_int),
+                ("r_band", C.c_double), ("tau_factor", C.c_double),
+                ("check_factor", C.c_double)]
+
+
+class BandInfo(C.Structure):
+    _fields_ = [("dim", C.c_int), ("N", C.c_int), ("n_ibc", C.c_int), ("order", C.c_int),
+                ("n_s", C.c_int64), ("n_c", C.c_int64), ("n", C.c_int64),
+                ("n_blocks", C.c_int64), ("n_tiles", C.c_int64), ("n_erows", C.c_int64),
+                ("n_lrows", C.c_int64), ("on_c_nodes", C.c_int64),
+                ("no_bc_dof_swaps", C.c_int64), ("h", C.c_double), ("r_band", C.c_double),
+                ("tau", C.c_double), ("device_bytes", C.c_size_t)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("m", C.c_double), ("n", C.c_double), ("tol", C.c_double), ("mode", C.c_int),
+                ("maxit", C.c_int), ("inner_tol", C.c_double), ("check_every", C.c_int),
+                ("use_graph", C.c_int), ("gauge", C.c_double)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("converged", C.c_int), ("outer_iters", C.c_int), ("krylov_iters", C.c_int),
+                ("restarts", C.c_int), ("fallback_f64", C.c_int), ("relres", C.c_double),
+                ("time_ms", C.c_double)]
+
+
+EXPORTED = ["cpm_build_band", "cpm_band_free", "cpm_band_query", "cpm_band_export",
+            "cpm_apply", "cpm_apply_transpose", "cpm_rhs", "cpm_rhs_adjoint", "cpm_solve",
+            "cpm_solve_adjoint", "cpm_last_error"]
+
+_lib = None
+
+
+class CPMError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+def load(path=LIB_PATH):
+    """Load libcpm.so (built by paper_2305_04711_amd.build); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libcpm.so is not built (%s); run "
+                           "`python -m paper_2305_04711_amd.build` - there is no CPU "
+                           "fallback" % path)
+    lib = C.CDLL(path)
+    vp, dp, i, d = C.c_void_p, C.POINTER(C.c_double), C.c_int, C.c_double
+    lib.cpm_build_band.argtypes = [C.POINTER(Surface), C.POINTER(IBC), i, C.POINTER(Grid), vp,
+                                   C.POINTER(vp)]
+    lib.cpm_band_free.argtypes = [vp]
+    lib.cpm_band_free.restype = None
+    lib.cpm_band_query.argtypes = [vp, C.POINTER(BandInfo)]
+    lib.cpm_band_export.argtypes = [vp, i, vp, C.c_size_t]
+    lib.cpm_apply.argtypes = [vp, d, d, i, i, vp, vp, vp]
+    lib.cpm_apply_transpose.argtypes = [vp, d, d, i, i, vp, vp, vp]
+    lib.cpm_rhs.argtypes = [vp, d, i, vp, vp, vp, vp]
+    lib.cpm_rhs_adjoint.argtypes = [vp, d, i, vp, vp, vp, vp]
+    lib.cpm_solve.argtypes = [vp, C.POINTER(SolveOpts), i, vp, vp, C.POINTER(SolveStats), vp]
+    lib.cpm_solve_adjoint.argtypes = [vp, C.POINTER(SolveOpts), i, vp, vp,
+                                      C.POINTER(SolveStats), vp]
+    lib.cpm_last_error.argtypes = []
+    lib.cpm_last_error.restype = C.c_char_p
+    for name in EXPORTED:
+        if name not in ("cpm_band_free", "cpm_last_error"):
+            getattr(lib, name).restype = C.c_int
+    del dp
+    _lib = lib
+    return lib
+
+
+def check(status):
+    if status != OK:
+        msg = _lib.cpm_last_error().decode() if _lib is not None else ""
+        raise CPMError(status, msg)

@@ -1,0 +1,246 @@
+"""Python binding of libcpm with the same entry points as the C ABI
+(include/cpm.h): build_band, apply (apply_cpm), apply_transpose, rhs,
+rhs_adjoint, solve, solve_adjoint, and CPMSolve, a torch.autograd.Function
+whose backward is the hand-written adjoint.
+
+PyTorch provides device memory and streams only; every step of the method
+runs in libcpm's HIP kernels.  Vectors are torch tensors on the current HIP
+device, shaped (n,) or (nrhs, n).
+"""
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import capi
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------------ geometry
+def circle(R=1.0, center=(0.0, 0.0)):
+    return capi.Surface(capi.SURF_CIRCLE, (C.c_double * 3)(center[0], center[1], 0.0), R, 0.0)
+
+
+def sphere(R=1.0, center=(0.0, 0.0, 0.0)):
+    return capi.Surface(capi.SURF_SPHERE, (C.c_double * 3)(*center), R, 0.0)
+
+
+def torus(R=1.0, rho=0.4, center=(0.0, 0.0, 0.0)):
+    return capi.Surface(capi.SURF_TORUS, (C.c_double * 3)(*center), R, rho)
+
+
+def point_ibc(p, orient):
+    p = list(p) + [0.0] * (3 - len(p))
+    o = list(orient) + [0.0] * (3 - len(orient))
+    return capi.IBC(capi.IBC_POINT, (C.c_double * 3)(*p), (C.c_double * 3)(*o), 0.0,
+                    (C.c_double * 2)(0.0, 0.0))
+
+
+def latitude_ibc(z0):
+    return capi.IBC(capi.IBC_LATITUDE, (C.c_double * 3)(), (C.c_double * 3)(), z0,
+                    (C.c_double * 2)(0.0, 0.0))
+
+
+def meridian_ibc(ex, ey):
+    return capi.IBC(capi.IBC_MERIDIAN, (C.c_double * 3)(), (C.c_double * 3)(), 0.0,
+                    (C.c_double * 2)(ex, ey))
+
+
+# ------------------------------------------------------------------ band
+class Band:
+    """cpm_build_band: the narrow band, interior-boundary DOFs and stencils
+    for one surface and grid (h = 1/N)."""
+
+    def __init__(self, surface, ibcs=(), N=64, order=2, r_band=0.0, tau_factor=0.0,
+                 check_factor=0.0, check_reach=False):
+        lib = capi.load()
+        self._lib = lib
+        self.handle = None
+        arr = (capi.IBC * max(1, len(ibcs)))(*ibcs) if ibcs else None
+        grid = capi.Grid(int(N), 3, int(order), int(bool(check_reach)), float(r_band),
+                         float(tau_factor), float(check_factor))
+        out = C.c_void_p()
+        capi.check(lib.cpm_build_band(C.byref(surface), arr, len(ibcs), C.byref(grid),
+                                      _stream(), C.byref(out)))
+        self.handle = out
+        info = capi.BandInfo()
+        capi.check(lib.cpm_band_query(self.handle, C.byref(info)))
+        self.info = {k: getattr(info, k) for k, _ in capi.BandInfo._fields_}
+        self.dim = info.dim
+        self.N = info.N
+        self.n_s, self.n_c, self.n = info.n_s, info.n_c, info.n
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            self._lib.cpm_band_free(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _export(self, what, dtype, shape):
+        out = np.empty(shape, dtype=dtype)
+        if out.size:
+            capi.check(self._lib.cpm_band_export(self.handle, what,
+                                                 out.ctypes.data_as(C.c_void_p), out.nbytes))
+        return out
+
+    def coords(self):
+        return self._export(capi.EXPORT_COORDS, np.int32, (self.n_s, self.dim))
+
+    def cp(self):
+        return self._export(capi.EXPORT_CP, np.float64, (self.n_s, self.dim))
+
+    def bc_node(self):
+        return self._export(capi.EXPORT_BC_NODE, np.int32, (self.n_c,))
+
+    def bc_cpc(self):
+        return self._export(capi.EXPORT_BC_CPC, np.float64, (self.n_c, self.dim))
+
+    def bc_side(self):
+        return self._export(capi.EXPORT_BC_SIDE, np.int32, (self.n_c,))
+
+    def bc_curve(self):
+        return self._export(capi.EXPORT_BC_CURVE, np.int32, (self.n_c,))
+
+    def ecols(self):
+        return self._export(capi.EXPORT_ECOLS, np.int32, (self.n, 4 ** self.dim))
+
+    def lcols(self):
+        return self._export(capi.EXPORT_LCOLS, np.int32, (self.n, 2 * self.dim))
+
+    def bases(self):
+        return self._export(capi.EXPORT_BASE, np.int32, (self.n, self.dim))
+
+
+def build_band(surface, ibcs=(), N=64, **kw):
+    return Band(surface, ibcs, N, **kw)
+
+
+# ------------------------------------------------------------------ operators
+def _dtype_code(t):
+    if t.dtype == torch.float64:
+        return capi.F64
+    if t.dtype == torch.float32:
+        return capi.F32
+    raise TypeError("vectors must be float64 or float32")
+
+
+def _check_vec(band, t, length):
+    if not t.is_cuda:
+        raise ValueError("vectors must be on the GPU (no CPU path)")
+    if not t.is_contiguous():
+        raise ValueError("vectors must be contiguous")
+    if t.shape[-1] != length:
+        raise ValueError("last dimension must be %d (got %d)" % (length, t.shape[-1]))
+    return 1 if t.dim() == 1 else t.shape[0]
+
+
+def apply(band, u, m, n):
+    """apply_cpm: v = A u, A = m I + n [diag L + (L - diag L) E]."""
+    nrhs = _check_vec(band, u, band.n)
+    v = torch.empty_like(u)
+    capi.check(band._lib.cpm_apply(band.handle, float(m), float(n), _dtype_code(u), nrhs,
+                                   _ptr(u), _ptr(v), _stream()))
+    return v
+
+
+apply_cpm = apply
+
+
+def apply_transpose(band, w, m, n):
+    nrhs = _check_vec(band, w, band.n)
+    z = torch.empty_like(w)
+    capi.check(band._lib.cpm_apply_transpose(band.handle, float(m), float(n), _dtype_code(w),
+                                             nrhs, _ptr(w), _ptr(z), _stream()))
+    return z
+
+
+def rhs(band, f, g, n):
+    """b = P f - n (L - diag L) e(g); f (.., n_s), g (.., n_c) float64."""
+    nrhs = _check_vec(band, f, band.n_s)
+    shape = (band.n,) if f.dim() == 1 else (nrhs, band.n)
+    b = torch.empty(shape, dtype=torch.float64, device=f.device)
+    gp = None
+    if band.n_c:
+        _check_vec(band, g, band.n_c)
+        gp = _ptr(g)
+    capi.check(band._lib.cpm_rhs(band.handle, float(n), nrhs, _ptr(f), gp, _ptr(b), _stream()))
+    return b
+
+
+def rhs_adjoint(band, lam, n):
+    nrhs = _check_vec(band, lam, band.n)
+    lead = () if lam.dim() == 1 else (nrhs,)
+    gf = torch.empty(lead + (band.n_s,), dtype=torch.float64, device=lam.device)
+    gg = torch.zeros(lead + (band.n_c,), dtype=torch.float64, device=lam.device)
+    capi.check(band._lib.cpm_rhs_adjoint(band.handle, float(n), nrhs, _ptr(lam), _ptr(gf),
+                                         _ptr(gg) if band.n_c else None, _stream()))
+    return gf, gg
+
+
+def _opts(m, n, tol, mode, maxit, inner_tol, check_every, use_graph, gauge):
+    code = {"mixed": capi.SOLVE_MIXED, "f64": capi.SOLVE_F64}[mode]
+    return capi.SolveOpts(float(m), float(n), float(tol), code, int(maxit), float(inner_tol),
+                          int(check_every), int(bool(use_graph)), float(gauge))
+
+
+def _solve(fn, band, b, m, n, tol, mode, x0, maxit, inner_tol, check_every, use_graph, gauge,
+           raise_noconv):
+    nrhs = _check_vec(band, b, band.n)
+    if b.dtype != torch.float64:
+        raise TypeError("right-hand sides are float64")
+    x = torch.zeros_like(b) if x0 is None else x0.clone().contiguous()
+    st = capi.SolveStats()
+    o = _opts(m, n, tol, mode, maxit, inner_tol, check_every, use_graph, gauge)
+    status = fn(band.handle, C.byref(o), nrhs, _ptr(b), _ptr(x), C.byref(st), _stream())
+    stats = {k: getattr(st, k) for k, _ in capi.SolveStats._fields_}
+    if status == capi.E_NOCONV and not raise_noconv:
+        return x, stats
+    capi.check(status)
+    return x, stats
+
+
+def solve(band, b, m, n, tol=1e-8, mode="mixed", x0=None, maxit=0, inner_tol=0.0,
+          check_every=0, use_graph=True, gauge=0.0, raise_noconv=True):
+    """Solve A x = b.  mode "mixed": FP32 BiCGSTAB + FP64 refinement; "f64":
+    plain FP64 BiCGSTAB.  Returns (x, stats)."""
+    return _solve(band._lib.cpm_solve, band, b, m, n, tol, mode, x0, maxit, inner_tol,
+                  check_every, use_graph, gauge, raise_noconv)
+
+
+def solve_adjoint(band, rhs_, m, n, tol=1e-8, mode="mixed", x0=None, maxit=0, inner_tol=0.0,
+                  check_every=0, use_graph=True, raise_noconv=True):
+    return _solve(band._lib.cpm_solve_adjoint, band, rhs_, m, n, tol, mode, x0, maxit,
+                  inner_tol, check_every, use_graph, 0.0, raise_noconv)
+
+
+class CPMSolve(torch.autograd.Function):
+    """u = A^-1 b(f, g) with gradients with respect to f (n_s) and the interior
+    Dirichlet values g (n_c) from the adjoint solve A^T lam = dl/du."""
+
+    @staticmethod
+    def forward(ctx, f, g, band, m, n, tol=1e-10, mode="mixed"):
+        b = rhs(band, f.detach().contiguous(), g.detach().contiguous() if band.n_c else None, n)
+        u, _ = solve(band, b, m, n, tol=tol, mode=mode)
+        ctx.band, ctx.m, ctx.n, ctx.tol, ctx.mode = band, m, n, tol, mode
+        return u
+
+    @staticmethod
+    def backward(ctx, grad_u):
+        band = ctx.band
+        lam, _ = solve_adjoint(band, grad_u.contiguous().to(torch.float64), ctx.m, ctx.n,
+                               tol=ctx.tol, mode=ctx.mode)
+        gf, gg = rhs_adjoint(band, lam, ctx.n)
+        return gf, (gg if band.n_c else None), None, None, None, None, None

@@ -1,0 +1,673 @@
+// The CPM operator A = m I + n [diag L + (L - diag L) E] (Sec. 5.4) and its
+// transpose, matrix-free, in two passes (the paper's four steps with steps 3
+// and 4 folded into the second pass):
+//   pass 1  a = E u          (eq. interp-stencil)  k_gather + k_gather_rows
+//   pass 2  v = (m + n D) u + n N^2 sum_nbr a      k_lap    + k_lap_rows
+// Pass 1 runs one workgroup per gather tile: the rows whose stencil base lies
+// in one block.  Their 4^d members lie in the 2^d blocks starting at that
+// block, which the workgroup stages in LDS as a dense (2 BX)^d cube before
+// every row reads its members from LDS.  Rows whose stencils were changed by
+// an interior boundary (and every BC row) are explicit rows with stored
+// columns and weights.  Pass 2 maps one wavefront to one block of 64 nodes
+// and finds face neighbours through the block neighbour table; rows with
+// swapped FD neighbours (and BC rows) are explicit.
+#include "cpm_internal.hpp"
+#include "lagrange.hpp"
+
+namespace cpm {
+
+struct BlockView {
+  const unsigned long long* mask;
+  const int* off;
+  const int* nbr;
+  const unsigned long long* lrow_mask;
+  int nb;
+};
+
+static BlockView bview(const cpm_band* b) {
+  return BlockView{b->blk_mask, b->blk_off, b->blk_nbr, b->lrow_mask, b->nb};
+}
+
+template <int DIM>
+__device__ __forceinline__ int nbr_dof(const BlockView& B, int blk, int mx, int my, int mz) {
+  using G = Geo<DIM>;
+  const int dx = mx >> G::SH, dy = my >> G::SH, dz = DIM == 3 ? (mz >> G::SH) : 0;
+  int b = blk;
+  if (dx | dy | dz) b = B.nbr[blk * G::NNBR + G::code(dx, dy, dz)];
+  if (b < 0) return -1;
+  const int s = G::slot(mx & (G::BX - 1), my & (G::BX - 1), DIM == 3 ? (mz & (G::BX - 1)) : 0);
+  const unsigned long long m = B.mask[b];
+  if (!((m >> s) & 1ull)) return -1;
+  return B.off[b] + __popcll(m & ((1ull << s) - 1ull));
+}
+
+struct TileView {
+  const int* tile_blk;
+  const int* tile_start;
+  const int* perm;
+  const double* cp_perm;
+  const float* frac32;
+  const unsigned* lbase;
+  int ntr;
+};
+
+static TileView tview(const cpm_band* b) {
+  return TileView{b->tile_blk, b->tile_start, b->perm, b->cp_perm, b->frac32, b->lbase,
+                  b->n_tile_rows};
+}
+
+template <int DIM> struct Cube {
+  static constexpr int E = 2 * Geo<DIM>::BX;              // cube edge
+  static constexpr int SIZE = DIM == 3 ? E * E * E : E * E;
+};
+
+// Stage the 2^d blocks starting at block tb into a dense cube (zeros where no
+// band node).  idx enumerates (quadrant, slot).
+template <class T, int DIM>
+__device__ __forceinline__ void cube_index(const BlockView& B, int tb, int idx, int& dof, int& ci) {
+  using G = Geo<DIM>;
+  const int q = idx >> 6, s = idx & 63;
+  const int qx = q & 1, qy = (q >> 1) & 1, qz = DIM == 3 ? (q >> 2) : 0;
+  const int blk = q == 0 ? tb : B.nbr[tb * G::NNBR + G::code(qx, qy, qz)];
+  const int cx = qx * G::BX + G::lx(s), cy = qy * G::BX + G::ly(s);
+  const int cz = DIM == 3 ? qz * G::BX + G::lz(s) : 0;
+  ci = DIM == 3 ? (cz * Cube<DIM>::E + cy) * Cube<DIM>::E + cx : cy * Cube<DIM>::E + cx;
+  dof = -1;
+  if (blk >= 0) {
+    const unsigned long long m = B.mask[blk];
+    if ((m >> s) & 1ull) dof = B.off[blk] + __popcll(m & ((1ull << s) - 1ull));
+  }
+}
+
+// Per-row stencil base (local to the tile block) and fraction.
+template <class T, int DIM>
+__device__ __forceinline__ void row_stencil(const TileView& tv, int pos, int N, int lb[3], T t[3]);
+
+template <>
+__device__ __forceinline__ void row_stencil<double, 3>(const TileView& tv, int pos, int N, int lb[3],
+                                                        double t[3]) {
+  const double dn = (double)N;
+  for (int a = 0; a < 3; ++a) {
+    const double y = tv.cp_perm[(int64_t)a * tv.ntr + pos] * dn;
+    const double F = floor(y);
+    lb[a] = ((int)F - 1) & 3;
+    t[a] = y - F;
+  }
+}
+template <>
+__device__ __forceinline__ void row_stencil<double, 2>(const TileView& tv, int pos, int N, int lb[3],
+                                                        double t[3]) {
+  const double dn = (double)N;
+  for (int a = 0; a < 2; ++a) {
+    const double y = tv.cp_perm[(int64_t)a * tv.ntr + pos] * dn;
+    const double F = floor(y);
+    lb[a] = ((int)F - 1) & 7;
+    t[a] = y - F;
+  }
+  lb[2] = 0;
+  t[2] = 0.0;
+}
+template <>
+__device__ __forceinline__ void row_stencil<float, 3>(const TileView& tv, int pos, int, int lb[3],
+                                                       float t[3]) {
+  const unsigned p = tv.lbase[pos];
+  lb[0] = p & 0xff;
+  lb[1] = (p >> 8) & 0xff;
+  lb[2] = (p >> 16) & 0xff;
+  for (int a = 0; a < 3; ++a) t[a] = tv.frac32[(int64_t)a * tv.ntr + pos];
+}
+template <>
+__device__ __forceinline__ void row_stencil<float, 2>(const TileView& tv, int pos, int, int lb[3],
+                                                       float t[3]) {
+  const unsigned p = tv.lbase[pos];
+  lb[0] = p & 0xff;
+  lb[1] = (p >> 8) & 0xff;
+  lb[2] = 0;
+  for (int a = 0; a < 2; ++a) t[a] = tv.frac32[(int64_t)a * tv.ntr + pos];
+  t[2] = 0.0f;
+}
+
+// ---------------------------------------------------------------- pass 1
+template <class T, int DIM, int NR>
+__global__ __launch_bounds__(256) void k_gather(BlockView B, TileView tv, int N, const T* __restrict__ u,
+                                                T* __restrict__ a, int64_t ld) {
+  constexpr int CS = Cube<DIM>::SIZE, E = Cube<DIM>::E;
+  __shared__ T s_u[NR][CS];
+  const int t = blockIdx.x;
+  const int tb = tv.tile_blk[t];
+  for (int idx = threadIdx.x; idx < CS; idx += blockDim.x) {
+    int dof, ci;
+    cube_index<T, DIM>(B, tb, idx, dof, ci);
+    for (int r = 0; r < NR; ++r) s_u[r][ci] = dof >= 0 ? u[r * ld + dof] : T(0);
+  }
+  __syncthreads();
+  const int end = tv.tile_start[t + 1];
+  for (int pos = tv.tile_start[t] + threadIdx.x; pos < end; pos += blockDim.x) {
+    int lb[3];
+    T tt[3];
+    row_stencil<T, DIM>(tv, pos, N, lb, tt);
+    T wx[4], wy[4], wz[4];
+    lagrange4<T>(tt[0], wx);
+    lagrange4<T>(tt[1], wy);
+    if (DIM == 3) lagrange4<T>(tt[2], wz);
+    T acc[NR];
+    for (int r = 0; r < NR; ++r) acc[r] = T(0);
+    if (DIM == 3) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        T accz[NR];
+        for (int r = 0; r < NR; ++r) accz[r] = T(0);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int base = ((lb[2] + c) * E + (lb[1] + b)) * E + lb[0];
+          for (int r = 0; r < NR; ++r) {
+            const T* row = &s_u[r][base];
+            const T x = wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2] + wx[3] * row[3];
+            accz[r] += wy[b] * x;
+          }
+        }
+        for (int r = 0; r < NR; ++r) acc[r] += wz[c] * accz[r];
+      }
+    } else {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int base = (lb[1] + b) * E + lb[0];
+        for (int r = 0; r < NR; ++r) {
+          const T* row = &s_u[r][base];
+          const T x = wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2] + wx[3] * row[3];
+          acc[r] += wy[b] * x;
+        }
+      }
+    }
+    const int dof = tv.perm[pos];
+    for (int r = 0; r < NR; ++r) a[r * ld + dof] = acc[r];
+  }
+}
+
+// Explicit interpolation rows: a[id] = sum_o w_o u[col_o].
+template <class T>
+__global__ void k_gather_rows(int nrows, int nm, const int* __restrict__ row_id,
+                              const int* __restrict__ col, const T* __restrict__ w,
+                              const T* __restrict__ u, T* __restrict__ a, int64_t ld, int nrhs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  const int id = row_id[i];
+  for (int r = 0; r < nrhs; ++r) {
+    T acc = T(0);
+    for (int o = 0; o < nm; ++o) {
+      const int c = col[(int64_t)i * nm + o];
+      if (c >= 0) acc += w[(int64_t)i * nm + o] * u[r * ld + c];
+    }
+    a[r * ld + id] = acc;
+  }
+}
+
+// ---------------------------------------------------------------- pass 2
+// v = cd u + co sum_nbr a (+ gauge), one wavefront per block, lane = slot.
+// ALL = false skips rows with explicit FD stencils; ALL = true (transpose)
+// visits every PDE row.
+template <class T, int DIM, bool ALL>
+__global__ __launch_bounds__(256) void k_lap(BlockView B, const T* __restrict__ u,
+                                             const T* __restrict__ a, T* __restrict__ v,
+                                             int64_t ld, int nrhs, T cd, T co,
+                                             const double* __restrict__ gsum, double gscale) {
+  using G = Geo<DIM>;
+  const int blk = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int slot = threadIdx.x & 63;
+  if (blk >= B.nb) return;
+  const unsigned long long m = B.mask[blk];
+  if (!((m >> slot) & 1ull)) return;
+  if (!ALL && ((B.lrow_mask[blk] >> slot) & 1ull)) return;
+  const int dof = B.off[blk] + __popcll(m & ((1ull << slot) - 1ull));
+  int nd[2 * DIM];
+  const int l[3] = {G::lx(slot), G::ly(slot), G::lz(slot)};
+#pragma unroll
+  for (int f = 0; f < 2 * DIM; ++f) {
+    int q[3] = {l[0], l[1], l[2]};
+    q[f >> 1] += (f & 1) ? 1 : -1;
+    nd[f] = nbr_dof<DIM>(B, blk, q[0], q[1], q[2]);
+  }
+  for (int r = 0; r < nrhs; ++r) {
+    T s = T(0);
+#pragma unroll
+    for (int f = 0; f < 2 * DIM; ++f)
+      if (nd[f] >= 0) s += a[r * ld + nd[f]];
+    T out = cd * u[r * ld + dof] + co * s;
+    if (gsum) out += (T)(gscale * gsum[r]);
+    v[r * ld + dof] = out;
+  }
+}
+
+template <class T>
+__global__ void k_lap_rows(int nrows, int nf, const int* __restrict__ row_id,
+                           const int* __restrict__ col, const T* __restrict__ u,
+                           const T* __restrict__ a, T* __restrict__ v, int64_t ld, int nrhs,
+                           T cd, T co, const double* __restrict__ gsum, double gscale) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  const int id = row_id[i];
+  for (int r = 0; r < nrhs; ++r) {
+    T s = T(0);
+    for (int f = 0; f < nf; ++f) {
+      const int c = col[i * nf + f];
+      if (c >= 0) s += a[r * ld + c];
+    }
+    T out = cd * u[r * ld + id] + co * s;
+    if (gsum) out += (T)(gscale * gsum[r]);
+    v[r * ld + id] = out;
+  }
+}
+
+// ---------------------------------------------------------------- gauge
+// gsum[r] = sum_{i < n_s} u[r][i] (deterministic two-stage sum)
+template <class T>
+__global__ __launch_bounds__(256) void k_sum_part(const T* __restrict__ u, int64_t n_s, int64_t ld,
+                                                  double* part) {
+  __shared__ double s[256];
+  const int r = blockIdx.y;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n_s; i += (int64_t)gridDim.x * 256)
+    acc += (double)u[r * ld + i];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[r * gridDim.x + blockIdx.x] = s[0];
+}
+
+__global__ void k_sum_final(const double* part, int np, double* out) {
+  __shared__ double s[256];
+  const int r = blockIdx.x;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += 256) acc += part[r * np + i];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[r] = s[0];
+}
+
+// ---------------------------------------------------------------- transpose
+template <class T>
+__device__ __forceinline__ void atomic_add(T* p, T v) {
+  unsafeAtomicAdd(p, v);
+}
+
+// E^T c for the tile rows: scatter w c_i into the staged cube, then add the
+// cube into z with one atomic per band node.
+template <class T, int DIM>
+__global__ __launch_bounds__(256) void k_gather_T(BlockView B, TileView tv, int N,
+                                                  const T* __restrict__ c, T* __restrict__ z,
+                                                  int64_t ld, int r) {
+  constexpr int CS = Cube<DIM>::SIZE, E = Cube<DIM>::E;
+  __shared__ T s_z[CS];
+  const int t = blockIdx.x;
+  const int tb = tv.tile_blk[t];
+  for (int idx = threadIdx.x; idx < CS; idx += blockDim.x) s_z[idx] = T(0);
+  __syncthreads();
+  const int end = tv.tile_start[t + 1];
+  for (int pos = tv.tile_start[t] + threadIdx.x; pos < end; pos += blockDim.x) {
+    int lb[3];
+    T tt[3];
+    row_stencil<T, DIM>(tv, pos, N, lb, tt);
+    T wx[4], wy[4], wz[4] = {T(1), T(0), T(0), T(0)};
+    lagrange4<T>(tt[0], wx);
+    lagrange4<T>(tt[1], wy);
+    if (DIM == 3) lagrange4<T>(tt[2], wz);
+    const T ci = c[r * ld + tv.perm[pos]];
+    for (int cc = 0; cc < (DIM == 3 ? 4 : 1); ++cc) {
+      for (int b = 0; b < 4; ++b) {
+        const T wyz = (DIM == 3 ? wz[cc] : T(1)) * wy[b] * ci;
+        const int base = DIM == 3 ? ((lb[2] + cc) * E + (lb[1] + b)) * E + lb[0] : (lb[1] + b) * E + lb[0];
+        for (int aa = 0; aa < 4; ++aa) atomicAdd(&s_z[base + aa], wx[aa] * wyz);
+      }
+    }
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < CS; idx += blockDim.x) {
+    int dof, ci;
+    cube_index<T, DIM>(B, tb, idx, dof, ci);
+    if (dof >= 0) {
+      const T val = s_z[ci];
+      if (val != T(0)) atomic_add(&z[r * ld + dof], val);
+    }
+  }
+}
+
+template <class T>
+__global__ void k_gather_rows_T(int nrows, int nm, const int* __restrict__ row_id,
+                                const int* __restrict__ col, const T* __restrict__ w,
+                                const T* __restrict__ c, T* __restrict__ z, int64_t ld, int nrhs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  const int id = row_id[i];
+  for (int r = 0; r < nrhs; ++r) {
+    const T ci = c[r * ld + id];
+    if (ci == T(0)) continue;
+    for (int o = 0; o < nm; ++o) {
+      const int cc = col[(int64_t)i * nm + o];
+      if (cc >= 0) atomic_add(&z[r * ld + cc], w[(int64_t)i * nm + o] * ci);
+    }
+  }
+}
+
+// Corrections of (L - diag L)^T w for explicit FD rows: a swapped PDE entry
+// moves its contribution from the PDE column to the BC column; a BC row adds
+// to each of its columns.
+template <class T>
+__global__ void k_lap_rows_T(int nrows, int nf, int64_t n_s, const int* __restrict__ row_id,
+                             const int* __restrict__ col, const int* __restrict__ col0,
+                             const T* __restrict__ w, T* __restrict__ c, int64_t ld, int nrhs, T co) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  const int id = row_id[i];
+  for (int r = 0; r < nrhs; ++r) {
+    const T wi = co * w[r * ld + id];
+    for (int f = 0; f < nf; ++f) {
+      const int k1 = col[i * nf + f];
+      if (id < n_s) {
+        const int k0 = col0[i * nf + f];
+        if (k0 != k1) {
+          if (k0 >= 0) atomic_add(&c[r * ld + k0], -wi);
+          if (k1 >= 0) atomic_add(&c[r * ld + k1], wi);
+        }
+      } else if (k1 >= 0) {
+        atomic_add(&c[r * ld + k1], wi);
+      }
+    }
+  }
+}
+
+template <class T>
+__global__ void k_fill(T* __restrict__ p, int64_t n, T val) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = val;
+}
+
+template <class T>
+__global__ void k_combine(int64_t n, const T* __restrict__ w, const T* __restrict__ z,
+                          T* __restrict__ out, T cd, T nn, int64_t total) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  out[i] = cd * w[i] + nn * z[i];
+  (void)n;
+}
+
+// ---------------------------------------------------------------- rhs
+__global__ void k_rhs_init(int64_t n_s, int64_t n_c, int nrhs, const double* __restrict__ f,
+                           const int* __restrict__ bc_node, double* __restrict__ b) {
+  const int64_t n = n_s + n_c;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * nrhs) return;
+  const int64_t r = t / n, i = t % n;
+  b[t] = i < n_s ? f[r * n_s + i] : f[r * n_s + bc_node[i - n_s]];
+}
+
+__global__ void k_rhs_rows(int nrows, int nf, int64_t n_s, int64_t n_c, int nrhs,
+                           const int* __restrict__ row_id, const int* __restrict__ col,
+                           const double* __restrict__ g, double scale, double* __restrict__ b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  const int id = row_id[i];
+  const int64_t n = n_s + n_c;
+  for (int r = 0; r < nrhs; ++r) {
+    double s = 0.0;
+    for (int f = 0; f < nf; ++f) {
+      const int c = col[i * nf + f];
+      if (c >= n_s) s += g[r * n_c + (c - n_s)];
+    }
+    b[r * n + id] -= scale * s;
+  }
+}
+
+__global__ void k_gradf(int64_t n_s, int64_t n_c, int nrhs, const double* __restrict__ lam,
+                        double* __restrict__ gf) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_s * nrhs) return;
+  const int64_t r = t / n_s, i = t % n_s;
+  gf[t] = lam[r * (n_s + n_c) + i];
+}
+
+__global__ void k_gradf_bc(int64_t n_s, int64_t n_c, int nrhs, const int* __restrict__ bc_node,
+                           const double* __restrict__ lam, double* __restrict__ gf) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_c * nrhs) return;
+  const int64_t r = t / n_c, k = t % n_c;
+  gf[r * n_s + bc_node[k]] += lam[r * (n_s + n_c) + n_s + k];
+}
+
+__global__ void k_gradg(int nrows, int nf, int64_t n_s, int64_t n_c, int nrhs,
+                        const int* __restrict__ row_id, const int* __restrict__ col,
+                        const double* __restrict__ lam, double scale, double* __restrict__ gg) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  const int id = row_id[i];
+  const int64_t n = n_s + n_c;
+  for (int r = 0; r < nrhs; ++r) {
+    const double li = lam[r * n + id];
+    for (int f = 0; f < nf; ++f) {
+      const int c = col[i * nf + f];
+      if (c >= n_s) atomicAdd(&gg[r * n_c + (c - n_s)], scale * li);
+    }
+  }
+}
+
+// ================================================================ host
+template <class T>
+static const T* ew_of(const cpm_band* b);
+template <>
+const double* ew_of<double>(const cpm_band* b) { return b->ew; }
+template <>
+const float* ew_of<float>(const cpm_band* b) { return b->ew32; }
+
+template <class T, int DIM>
+static void launch_gather(const cpm_band* b, int nrhs, const T* u, T* a, hipStream_t st) {
+  const int64_t ld = b->n;
+  int r = 0;
+  while (r < nrhs) {
+    const int k = nrhs - r >= 4 ? 4 : nrhs - r;
+    const T* ur = u + r * ld;
+    T* ar = a + r * ld;
+    if (b->ntiles) {
+      switch (k) {
+        case 1: hipLaunchKernelGGL((k_gather<T, DIM, 1>), dim3(b->ntiles), dim3(256), 0, st, bview(b), tview(b), b->N, ur, ar, ld); break;
+        case 2: hipLaunchKernelGGL((k_gather<T, DIM, 2>), dim3(b->ntiles), dim3(256), 0, st, bview(b), tview(b), b->N, ur, ar, ld); break;
+        case 3: hipLaunchKernelGGL((k_gather<T, DIM, 3>), dim3(b->ntiles), dim3(256), 0, st, bview(b), tview(b), b->N, ur, ar, ld); break;
+        default: hipLaunchKernelGGL((k_gather<T, DIM, 4>), dim3(b->ntiles), dim3(256), 0, st, bview(b), tview(b), b->N, ur, ar, ld); break;
+      }
+      CPM_LAUNCH_CHECK();
+    }
+    r += k;
+  }
+  if (b->n_erows) {
+    const int nm = DIM == 3 ? 64 : 16;
+    hipLaunchKernelGGL(k_gather_rows<T>, dim3(grid_for(b->n_erows, 128)), dim3(128), 0, st,
+                       b->n_erows, nm, b->erow_id, b->ecol, ew_of<T>(b), u, a, ld, nrhs);
+    CPM_LAUNCH_CHECK();
+  }
+}
+
+template <class T, int DIM>
+static void apply_dim(const cpm_band* b, double m, double n, int nrhs, const T* u, T* v,
+                      hipStream_t st, const double* gsum, double gamma) {
+  const int64_t ld = b->n;
+  T* a = static_cast<T*>(band_scratch(b, 0, sizeof(T) * (size_t)ld * nrhs));
+  launch_gather<T, DIM>(b, nrhs, u, a, st);
+  const double N2 = (double)b->N * (double)b->N;
+  const T cd = (T)(m + n * (-2.0 * DIM * N2));
+  const T co = (T)(n * N2);
+  const double gscale = gsum ? gamma / (double)b->n_s : 0.0;
+  hipLaunchKernelGGL((k_lap<T, DIM, false>), dim3((b->nb + 3) / 4), dim3(256), 0, st, bview(b), u,
+                     a, v, ld, nrhs, cd, co, gsum, gscale);
+  CPM_LAUNCH_CHECK();
+  if (b->n_lrows) {
+    hipLaunchKernelGGL(k_lap_rows<T>, dim3(grid_for(b->n_lrows, 128)), dim3(128), 0, st,
+                       b->n_lrows, 2 * DIM, b->lrow_id, b->lcol, u, a, v, ld, nrhs, cd, co, gsum,
+                       gscale);
+    CPM_LAUNCH_CHECK();
+  }
+}
+
+template <class T>
+void apply_impl(const cpm_band* b, double m, double n, int nrhs, const T* u, T* v, hipStream_t st,
+                const double* gauge_sum, double gamma) {
+  double* gs = nullptr;
+  if (gamma != 0.0) {
+    // gauge: gamma * (sum of the PDE entries of u) / n_s on every row
+    const int np = 256;
+    double* part = static_cast<double*>(band_scratch(b, 3, sizeof(double) * np * nrhs + 64));
+    gs = gauge_sum ? const_cast<double*>(gauge_sum)
+                   : static_cast<double*>(band_scratch(b, 4, sizeof(double) * nrhs + 64));
+    hipLaunchKernelGGL(k_sum_part<T>, dim3(np, nrhs), dim3(256), 0, st, u, b->n_s, b->n, part);
+    CPM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sum_final, dim3(nrhs), dim3(256), 0, st, part, np, gs);
+    CPM_LAUNCH_CHECK();
+  }
+  if (b->dim == 3) apply_dim<T, 3>(b, m, n, nrhs, u, v, st, gs, gamma);
+  else apply_dim<T, 2>(b, m, n, nrhs, u, v, st, gs, gamma);
+}
+
+template <class T, int DIM>
+static void apply_T_dim(const cpm_band* b, double m, double n, int nrhs, const T* w, T* z,
+                        hipStream_t st) {
+  const int64_t ld = b->n;
+  T* c = static_cast<T*>(band_scratch(b, 1, sizeof(T) * (size_t)ld * nrhs));
+  T* e = static_cast<T*>(band_scratch(b, 2, sizeof(T) * (size_t)ld * nrhs));
+  const double N2 = (double)b->N * (double)b->N;
+  const T co = (T)N2;
+  // c = (L - diag L)^T w: symmetric bulk over every PDE row, then corrections
+  // (fill kernels, not memsets: this sequence may be captured into a graph)
+  hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(ld * nrhs, 256, 4096)), dim3(256), 0, st, c, ld * nrhs, T(0));
+  hipLaunchKernelGGL((k_lap<T, DIM, true>), dim3((b->nb + 3) / 4), dim3(256), 0, st, bview(b), w,
+                     w, c, ld, nrhs, T(0), co, nullptr, 0.0);
+  CPM_LAUNCH_CHECK();
+  if (b->n_lrows) {
+    hipLaunchKernelGGL(k_lap_rows_T<T>, dim3(grid_for(b->n_lrows, 128)), dim3(128), 0, st,
+                       b->n_lrows, 2 * DIM, b->n_s, b->lrow_id, b->lcol, b->lcol0, w, c, ld, nrhs,
+                       co);
+    CPM_LAUNCH_CHECK();
+  }
+  // e = E^T c
+  hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(ld * nrhs, 256, 4096)), dim3(256), 0, st, e, ld * nrhs, T(0));
+  if (b->ntiles)
+    for (int r = 0; r < nrhs; ++r) {
+      hipLaunchKernelGGL((k_gather_T<T, DIM>), dim3(b->ntiles), dim3(256), 0, st, bview(b),
+                         tview(b), b->N, c, e, ld, r);
+      CPM_LAUNCH_CHECK();
+    }
+  if (b->n_erows) {
+    const int nm = DIM == 3 ? 64 : 16;
+    hipLaunchKernelGGL(k_gather_rows_T<T>, dim3(grid_for(b->n_erows, 128)), dim3(128), 0, st,
+                       b->n_erows, nm, b->erow_id, b->ecol, ew_of<T>(b), c, e, ld, nrhs);
+    CPM_LAUNCH_CHECK();
+  }
+  const T cd = (T)(m + n * (-2.0 * DIM * N2));
+  const int64_t total = ld * nrhs;
+  hipLaunchKernelGGL(k_combine<T>, dim3(grid_for(total, 256)), dim3(256), 0, st, ld, w, e, z, cd,
+                     (T)n, total);
+  CPM_LAUNCH_CHECK();
+}
+
+template <class T>
+void apply_transpose_impl(const cpm_band* b, double m, double n, int nrhs, const T* w, T* z,
+                          hipStream_t st, const double*, double gamma) {
+  if (gamma != 0.0) CPM_FAIL(CPM_E_INVALID, "the gauge is not supported for the transpose");
+  if (b->dim == 3) apply_T_dim<T, 3>(b, m, n, nrhs, w, z, st);
+  else apply_T_dim<T, 2>(b, m, n, nrhs, w, z, st);
+}
+
+template void apply_impl<double>(const cpm_band*, double, double, int, const double*, double*,
+                                 hipStream_t, const double*, double);
+template void apply_impl<float>(const cpm_band*, double, double, int, const float*, float*,
+                                hipStream_t, const double*, double);
+template void apply_transpose_impl<double>(const cpm_band*, double, double, int, const double*,
+                                           double*, hipStream_t, const double*, double);
+template void apply_transpose_impl<float>(const cpm_band*, double, double, int, const float*,
+                                          float*, hipStream_t, const double*, double);
+
+}  // namespace cpm
+
+using namespace cpm;
+
+static void check_vec_args(const cpm_band* b, int dtype, int nrhs, const void* x, const void* y) {
+  if (!b) CPM_FAIL(CPM_E_INVALID, "null band");
+  if (dtype != CPM_F64 && dtype != CPM_F32) CPM_FAIL(CPM_E_INVALID, "unknown dtype %d", dtype);
+  if (nrhs < 1) CPM_FAIL(CPM_E_INVALID, "nrhs must be >= 1 (got %d)", nrhs);
+  if ((int64_t)nrhs * b->n >= (1ll << 31))
+    CPM_FAIL(CPM_E_INVALID, "nrhs * n exceeds the 32-bit index range");
+  if (!x || !y) CPM_FAIL(CPM_E_INVALID, "null vector");
+  if (x == y) CPM_FAIL(CPM_E_INVALID, "input and output must not alias");
+}
+
+extern "C" cpm_status cpm_apply(const cpm_band* b, double m, double n, int dtype, int nrhs,
+                                const void* u, void* v, void* hip_stream) {
+  return guard([&] {
+    check_vec_args(b, dtype, nrhs, u, v);
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (dtype == CPM_F64)
+      apply_impl<double>(b, m, n, nrhs, (const double*)u, (double*)v, st);
+    else
+      apply_impl<float>(b, m, n, nrhs, (const float*)u, (float*)v, st);
+  });
+}
+
+extern "C" cpm_status cpm_apply_transpose(const cpm_band* b, double m, double n, int dtype,
+                                          int nrhs, const void* w, void* z, void* hip_stream) {
+  return guard([&] {
+    check_vec_args(b, dtype, nrhs, w, z);
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (dtype == CPM_F64)
+      apply_transpose_impl<double>(b, m, n, nrhs, (const double*)w, (double*)z, st);
+    else
+      apply_transpose_impl<float>(b, m, n, nrhs, (const float*)w, (float*)z, st);
+  });
+}
+
+extern "C" cpm_status cpm_rhs(const cpm_band* b, double n, int nrhs, const double* f,
+                              const double* g, double* out, void* hip_stream) {
+  return guard([&] {
+    if (!b || !f || !out || nrhs < 1) CPM_FAIL(CPM_E_INVALID, "bad argument");
+    if (b->n_c && !g) CPM_FAIL(CPM_E_INVALID, "g is required when the band has BC DOFs");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int64_t total = b->n * nrhs;
+    hipLaunchKernelGGL(k_rhs_init, dim3(grid_for(total, 256)), dim3(256), 0, st, b->n_s, b->n_c,
+                       nrhs, f, b->bc_node, out);
+    CPM_LAUNCH_CHECK();
+    if (b->n_c && b->n_lrows) {
+      const double N2 = (double)b->N * (double)b->N;
+      hipLaunchKernelGGL(k_rhs_rows, dim3(grid_for(b->n_lrows, 128)), dim3(128), 0, st,
+                         b->n_lrows, 2 * b->dim, b->n_s, b->n_c, nrhs, b->lrow_id, b->lcol, g,
+                         n * N2 * b->ecoef, out);
+      CPM_LAUNCH_CHECK();
+    }
+  });
+}
+
+extern "C" cpm_status cpm_rhs_adjoint(const cpm_band* b, double n, int nrhs, const double* lam,
+                                      double* grad_f, double* grad_g, void* hip_stream) {
+  return guard([&] {
+    if (!b || !lam || !grad_f || nrhs < 1) CPM_FAIL(CPM_E_INVALID, "bad argument");
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipLaunchKernelGGL(k_gradf, dim3(grid_for(b->n_s * nrhs, 256)), dim3(256), 0, st, b->n_s,
+                       b->n_c, nrhs, lam, grad_f);
+    CPM_LAUNCH_CHECK();
+    if (b->n_c) {
+      hipLaunchKernelGGL(k_gradf_bc, dim3(grid_for(b->n_c * nrhs, 256)), dim3(256), 0, st,
+                         b->n_s, b->n_c, nrhs, b->bc_node, lam, grad_f);
+      CPM_LAUNCH_CHECK();
+    }
+    if (grad_g && b->n_c) {
+      CPM_HIP(hipMemsetAsync(grad_g, 0, sizeof(double) * b->n_c * nrhs, st));
+      const double N2 = (double)b->N * (double)b->N;
+      hipLaunchKernelGGL(k_gradg, dim3(grid_for(b->n_lrows, 128)), dim3(128), 0, st, b->n_lrows,
+                         2 * b->dim, b->n_s, b->n_c, nrhs, b->lrow_id, b->lcol, lam,
+                         -n * b->ecoef * N2, grad_g);
+      CPM_LAUNCH_CHECK();
+    }
+  });
+}

@@ -1,0 +1,1003 @@
+// Band builder: Omega(S) (eq. bandwidth; the set Algorithm 1 finds), interior
+// boundary sets (Sec. 4.1, 4.6), side vectors (eq. cpdiff, Sec. 4.2), stencils
+// with swaps (Sec. 4.3) and the gather tiles of the apply kernels.
+//
+// Storage is a sparse two-level grid (Sec. 5.1): occupied blocks of 64 nodes
+// (4x4x4, or 8x8 in 2-D) found by scanning the bounding box one row of blocks
+// per workgroup, a hash table from block coordinates to block ids, and a
+// neighbour table per block.  PDE DOFs are numbered block by block
+// (lexicographic in block coordinates), slots in order inside a block.
+//
+// Compiled with -ffp-contract=off: every FP64 decision here must agree bit
+// for bit with a plain IEEE evaluation of the same formulas.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "cpm_internal.hpp"
+#include "geom.hpp"
+#include "lagrange.hpp"
+
+namespace cpm {
+
+constexpr unsigned long long kEmpty = ~0ull;
+constexpr int kMaxIBC = 8;
+
+struct IBCList {
+  cpm_ibc c[kMaxIBC];
+  int n;
+};
+
+__host__ __device__ __forceinline__ unsigned long long block_key(int bx, int by, int bz) {
+  return (unsigned long long)(unsigned)(bx + (1 << 20)) |
+         ((unsigned long long)(unsigned)(by + (1 << 20)) << 21) |
+         ((unsigned long long)(unsigned)(bz + (1 << 20)) << 42);
+}
+
+__device__ __forceinline__ unsigned hash_key(unsigned long long k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdULL;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ULL;
+  k ^= k >> 33;
+  return (unsigned)k;
+}
+
+__device__ int hash_find(const unsigned long long* keys, const int* vals,
+                         unsigned cap, unsigned long long key) {
+  unsigned h = hash_key(key) & (cap - 1);
+  for (unsigned probe = 0; probe < cap; ++probe) {
+    const unsigned long long k = keys[h];
+    if (k == key) return vals[h];
+    if (k == kEmpty) return -1;
+    h = (h + 1) & (cap - 1);
+  }
+  return -1;
+}
+
+// Read-only view of the block structure used by device helpers.
+struct Blocks {
+  const int4* coord;
+  const unsigned long long* mask;
+  const int* off;
+  const int* nbr;
+  const unsigned long long* hkeys;
+  const int* hvals;
+  unsigned hcap;
+};
+
+// DOF of the node at local coordinates (mx, my, mz) relative to block blk;
+// each local coordinate may lie in [-BX, 2 BX).  -1 if not a band node.
+template <int DIM>
+__device__ __forceinline__ int node_dof(const Blocks& B, int blk, int mx, int my, int mz) {
+  using G = Geo<DIM>;
+  const int dx = mx >> G::SH, dy = my >> G::SH, dz = DIM == 3 ? (mz >> G::SH) : 0;
+  int b = blk;
+  if (dx | dy | dz) b = B.nbr[blk * G::NNBR + G::code(dx, dy, dz)];
+  if (b < 0) return -1;
+  const int s = G::slot(mx & (G::BX - 1), my & (G::BX - 1), DIM == 3 ? (mz & (G::BX - 1)) : 0);
+  const unsigned long long m = B.mask[b];
+  if (!((m >> s) & 1ull)) return -1;
+  return B.off[b] + __popcll(m & ((1ull << s) - 1ull));
+}
+
+template <int DIM>
+__device__ __forceinline__ int block_of(const Blocks& B, int kx, int ky, int kz) {
+  using G = Geo<DIM>;
+  return hash_find(B.hkeys, B.hvals, B.hcap,
+                   block_key(kx >> G::SH, ky >> G::SH, DIM == 3 ? (kz >> G::SH) : 0));
+}
+
+// Stencil base (floor(y N) - 1) and fraction of a query point.
+template <int DIM>
+__device__ __forceinline__ void stencil_base(const V3& y, int N, int base[3], double t[3]) {
+  const double dn = (double)N;
+  const double s[3] = {y.x * dn, y.y * dn, y.z * dn};
+  for (int a = 0; a < DIM; ++a) {
+    const double F = floor(s[a]);
+    base[a] = (int)F - 1;
+    t[a] = s[a] - F;
+  }
+  if (DIM == 2) {
+    base[2] = 0;
+    t[2] = 0.0;
+  }
+}
+
+// ------------------------------------------------------------------ pass 1
+struct Box {
+  int blo[3];
+  int nb[3];
+};
+
+// One workgroup per row of blocks (fixed by, bz); each wavefront classifies
+// one block at a time, lane = slot.  WRITE = false counts occupied blocks per
+// row; WRITE = true stores them in order at the row's offset.
+template <int DIM, bool WRITE>
+__global__ __launch_bounds__(256) void k_classify(cpm_surface S, int N, double r,
+                                                  double thr, Box box, int* row_count,
+                                                  const int* row_off, int4* out_coord,
+                                                  unsigned long long* out_mask) {
+  using G = Geo<DIM>;
+  const int row = blockIdx.x;
+  const int by = box.blo[1] + row % box.nb[1];
+  const int bz = DIM == 3 ? box.blo[2] + row / box.nb[1] : 0;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __shared__ unsigned long long s_mask[4];
+  __shared__ int s_count;
+  if (threadIdx.x == 0) s_count = 0;
+  __syncthreads();
+  const int nchunks = (box.nb[0] + 3) / 4;
+  const double hc = 0.5 * (double)(G::BX - 1);
+  const double dn = (double)N;
+  for (int ch = 0; ch < nchunks; ++ch) {
+    const int bxi = ch * 4 + wave;
+    unsigned long long m = 0;
+    if (bxi < box.nb[0]) {
+      const int bx = box.blo[0] + bxi;
+      // wave-uniform pre-test on the block centre; the distance to S is
+      // 1-Lipschitz, so a centre farther than r + half diagonal has no node
+      // within r (NaN compares false and falls through to the full test)
+      const V3 c{((double)(bx * G::BX) + hc) / dn, ((double)(by * G::BX) + hc) / dn,
+                 DIM == 3 ? ((double)(bz * G::BX) + hc) / dn : 0.0};
+      const double dc = dist<DIM>(c, cp_surface<DIM>(S, c));
+      if (!(dc > thr)) {
+        const int kx = bx * G::BX + G::lx(lane);
+        const int ky = by * G::BX + G::ly(lane);
+        const int kz = DIM == 3 ? bz * G::BX + G::lz(lane) : 0;
+        const V3 p = node_pos(kx, ky, kz, N);
+        const bool in = dist<DIM>(p, cp_surface<DIM>(S, p)) <= r;
+        m = __ballot(in);
+      }
+    }
+    if (lane == 0) s_mask[wave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 0; w < 4; ++w) {
+        if (s_mask[w]) {
+          if (WRITE) {
+            const int pos = row_off[row] + s_count;
+            out_coord[pos] = make_int4(box.blo[0] + ch * 4 + w, by, bz, 0);
+            out_mask[pos] = s_mask[w];
+          }
+          ++s_count;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (!WRITE && threadIdx.x == 0) row_count[row] = s_count;
+}
+
+__global__ void k_popcounts(const unsigned long long* mask, int nb, int* cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nb) cnt[i] = __popcll(mask[i]);
+}
+
+__global__ void k_hash_insert(const int4* coord, int nb, unsigned long long* keys,
+                              int* vals, unsigned cap) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const int4 c = coord[i];
+  const unsigned long long key = block_key(c.x, c.y, c.z);
+  unsigned h = hash_key(key) & (cap - 1);
+  for (unsigned probe = 0; probe < cap; ++probe) {
+    const unsigned long long prev = atomicCAS(&keys[h], kEmpty, key);
+    if (prev == kEmpty || prev == key) {
+      vals[h] = i;
+      return;
+    }
+    h = (h + 1) & (cap - 1);
+  }
+}
+
+template <int DIM>
+__global__ void k_neighbours(Blocks B, int nb, int* nbr) {
+  using G = Geo<DIM>;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nb * G::NNBR) return;
+  const int i = (int)(t / G::NNBR), c = (int)(t % G::NNBR);
+  const int dx = c % 3 - 1, dy = (c / 3) % 3 - 1, dz = DIM == 3 ? c / 9 - 1 : 0;
+  const int4 bc = B.coord[i];
+  nbr[t] = hash_find(B.hkeys, B.hvals, B.hcap, block_key(bc.x + dx, bc.y + dy, bc.z + dz));
+}
+
+// Thread mapping of the per-node kernels: 4 blocks per workgroup, lane = slot.
+#define NODE_PROLOGUE(DIMV)                                                   \
+  using G = Geo<DIMV>;                                                        \
+  const int blk = blockIdx.x * 4 + (threadIdx.x >> 6);                        \
+  const int slot = threadIdx.x & 63;                                          \
+  if (blk >= nb) return;                                                      \
+  const unsigned long long msk = B.mask[blk];                                 \
+  if (!((msk >> slot) & 1ull)) return;                                        \
+  const int dof = B.off[blk] + __popcll(msk & ((1ull << slot) - 1ull));       \
+  const int4 bcrd = B.coord[blk];                                             \
+  const int kx = bcrd.x * G::BX + G::lx(slot);                                \
+  const int ky = bcrd.y * G::BX + G::ly(slot);                                \
+  const int kz = DIMV == 3 ? bcrd.z * G::BX + G::lz(slot) : 0;                \
+  (void)kx; (void)ky; (void)kz; (void)dof
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_rows(Blocks B, int nb, cpm_surface S, int N,
+                                              int64_t n_s, double* cp) {
+  NODE_PROLOGUE(DIM);
+  const V3 p = node_pos(kx, ky, kz, N);
+  const V3 c = cp_surface<DIM>(S, p);
+  cp[dof] = c.x;
+  cp[n_s + dof] = c.y;
+  if (DIM == 3) cp[2 * n_s + dof] = c.z;
+}
+
+__device__ __forceinline__ V3 load_v(const double* a, int64_t n_s, int i, int dim) {
+  return V3{a[i], a[n_s + i], dim == 3 ? a[2 * n_s + i] : 0.0};
+}
+
+// Interior-boundary classification of every PDE node.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_ibc_rows(Blocks B, int nb, cpm_surface S, IBCList L,
+                                                  int N, int64_t n_s, double r, double cf,
+                                                  double tau, const double* cp, int* row_c,
+                                                  int* omega, double* side_v, double* cpcs,
+                                                  unsigned long long* counters) {
+  NODE_PROLOGUE(DIM);
+  const V3 p = node_pos(kx, ky, kz, N);
+  const V3 q = load_v(cp, n_s, dof, DIM);
+  int rc = -1, om = 0;
+  for (int c = 0; c < L.n; ++c) {
+    const V3 pc = cp_curve<DIM>(S, L.c[c], p);
+    const double dC = dist<DIM>(p, pc);
+    if (dC < cf * r) {
+      if (rc >= 0) atomicOr(&counters[2], 1ull);     // overlapping check regions
+      rc = c;
+      om = dC <= r ? 1 : 0;
+      V3 v{q.x - pc.x, q.y - pc.y, q.z - pc.z};
+      const double nv = sqrt(dot3<DIM>(v, v));
+      if (nv < tau) {
+        const V3 o = orient_curve<DIM>(S, L.c[c], pc);
+        v = V3{tau * o.x, tau * o.y, tau * o.z};
+        atomicAdd(&counters[0], 1ull);
+      }
+      side_v[dof] = v.x;
+      side_v[n_s + dof] = v.y;
+      cpcs[dof] = pc.x;
+      cpcs[n_s + dof] = pc.y;
+      if (DIM == 3) {
+        side_v[2 * n_s + dof] = v.z;
+        cpcs[2 * n_s + dof] = pc.z;
+      }
+    }
+  }
+  row_c[dof] = rc;
+  omega[dof] = om;
+}
+
+__global__ void k_flag_curve(const int* row_c, const int* omega, int64_t n_s, int c, int* flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_s) flag[i] = (row_c[i] == c && omega[i]) ? 1 : 0;
+}
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_bc_assign(Blocks B, int nb, const int* flag,
+                                                   const int* rank, int64_t n_s,
+                                                   int64_t base_alpha, int c, cpm_surface S,
+                                                   IBCList L, const double* side_v,
+                                                   const double* cpcs, int* alpha_of,
+                                                   int* bc_node, double* bc_cpc, int* bc_side,
+                                                   int* bc_curve, int* bc_k) {
+  NODE_PROLOGUE(DIM);
+  if (!flag[dof]) return;
+  const int64_t a = base_alpha + rank[dof];   // BC DOF index minus n_s
+  alpha_of[dof] = (int)(n_s + a);
+  bc_node[a] = dof;
+  bc_k[a * 3 + 0] = kx;
+  bc_k[a * 3 + 1] = ky;
+  bc_k[a * 3 + 2] = kz;
+  const V3 pc = load_v(cpcs, n_s, dof, DIM);
+  const V3 v = load_v(side_v, n_s, dof, DIM);
+  bc_cpc[a * DIM + 0] = pc.x;
+  bc_cpc[a * DIM + 1] = pc.y;
+  if (DIM == 3) bc_cpc[a * DIM + 2] = pc.z;
+  const V3 o = orient_curve<DIM>(S, L.c[c], pc);
+  bc_side[a] = dot3<DIM>(v, o) < 0.0 ? -1 : 1;
+  bc_curve[a] = c;
+}
+
+// Interpolation members of a PDE row: hole count, swap flag (eq.
+// stencil-crossing-test), and the gather-tile count of rows without swaps.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_stencil_scan(Blocks B, int nb, int N, int64_t n_s,
+                                                      const double* cp, const int* row_c,
+                                                      const int* alpha_of, const double* side_v,
+                                                      int* eflag, int* tile_blk_of,
+                                                      int* tile_cnt,
+                                                      unsigned long long* counters) {
+  NODE_PROLOGUE(DIM);
+  constexpr int NM = DIM == 3 ? 64 : 16;
+  const V3 y = load_v(cp, n_s, dof, DIM);
+  int base[3];
+  double t[3];
+  stencil_base<DIM>(y, N, base, t);
+  const int bb = block_of<DIM>(B, base[0], base[1], base[2]);
+  const int lx = base[0] & (G::BX - 1), ly = base[1] & (G::BX - 1),
+            lz = DIM == 3 ? (base[2] & (G::BX - 1)) : 0;
+  const int rc = row_c ? row_c[dof] : -1;
+  V3 vi{0, 0, 0};
+  if (rc >= 0) vi = load_v(side_v, n_s, dof, DIM);
+  int holes = 0, swaps = 0, nobc = 0;
+  for (int o = 0; o < NM; ++o) {
+    const int a = o & 3, b = (o >> 2) & 3, c = o >> 4;
+    const int j = bb < 0 ? -1 : node_dof<DIM>(B, bb, lx + a, ly + b, lz + c);
+    if (j < 0) {
+      ++holes;
+      continue;
+    }
+    if (rc >= 0 && row_c[j] == rc) {
+      const V3 vj = load_v(side_v, n_s, j, DIM);
+      if (dot3<DIM>(vi, vj) < 0.0) {
+        if (alpha_of[j] >= 0) ++swaps;
+        else ++nobc;
+      }
+    }
+  }
+  if (holes) atomicAdd(&counters[3], (unsigned long long)holes);
+  if (nobc) atomicAdd(&counters[1], (unsigned long long)nobc);
+  eflag[dof] = swaps ? 1 : 0;
+  tile_blk_of[dof] = bb;
+  if (!swaps && bb >= 0 && !holes) atomicAdd(&tile_cnt[bb], 1);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_tile_fill(Blocks B, int nb, int N, int64_t n_s,
+                                                   const double* cp, const int* eflag,
+                                                   const int* tile_blk_of, const int* tile_off,
+                                                   int* fill, int ntr, int* perm, double* cp_perm,
+                                                   float* frac32, unsigned* lbase) {
+  NODE_PROLOGUE(DIM);
+  if (eflag[dof]) return;
+  const int bb = tile_blk_of[dof];
+  if (bb < 0) return;
+  const V3 y = load_v(cp, n_s, dof, DIM);
+  int base[3];
+  double t[3];
+  stencil_base<DIM>(y, N, base, t);
+  const int pos = tile_off[bb] + atomicAdd(&fill[bb], 1);
+  perm[pos] = dof;
+  const double yy[3] = {y.x, y.y, y.z};
+  for (int a = 0; a < DIM; ++a) {
+    cp_perm[(int64_t)a * ntr + pos] = yy[a];
+    frac32[(int64_t)a * ntr + pos] = (float)t[a];
+  }
+  const unsigned lx = base[0] & (G::BX - 1), ly = base[1] & (G::BX - 1),
+                 lz = DIM == 3 ? (base[2] & (G::BX - 1)) : 0;
+  lbase[pos] = lx | (ly << 8) | (lz << 16);
+}
+
+__global__ void k_tile_compact(const int* cnt, const int* off, const int* tidx, int nb,
+                               int* tile_blk, int* tile_start) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nb && cnt[b] > 0) {
+    tile_blk[tidx[b]] = b;
+    tile_start[tidx[b]] = off[b];
+  }
+}
+
+__global__ void k_nonzero(const int* in, int n, int* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[i] > 0 ? 1 : 0;
+}
+
+// Explicit interpolation rows of swapped PDE rows.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_erow_pde(Blocks B, int nb, int N, int64_t n_s,
+                                                  const double* cp, const int* row_c,
+                                                  const int* alpha_of, const double* side_v,
+                                                  const int* eflag, const int* eidx,
+                                                  int* erow_id, int* ecol, double* ew,
+                                                  float* ew32, int* ebase) {
+  NODE_PROLOGUE(DIM);
+  constexpr int NM = DIM == 3 ? 64 : 16;
+  if (!eflag[dof]) return;
+  const int r = eidx[dof];
+  erow_id[r] = dof;
+  const V3 y = load_v(cp, n_s, dof, DIM);
+  int base[3];
+  double t[3];
+  stencil_base<DIM>(y, N, base, t);
+  for (int a = 0; a < DIM; ++a) ebase[r * DIM + a] = base[a];
+  double w[3][4];
+  for (int a = 0; a < DIM; ++a) lagrange4<double>(t[a], w[a]);
+  const int bb = block_of<DIM>(B, base[0], base[1], base[2]);
+  const int lx = base[0] & (G::BX - 1), ly = base[1] & (G::BX - 1),
+            lz = DIM == 3 ? (base[2] & (G::BX - 1)) : 0;
+  const int rc = row_c[dof];
+  const V3 vi = load_v(side_v, n_s, dof, DIM);
+  for (int o = 0; o < NM; ++o) {
+    const int a = o & 3, b = (o >> 2) & 3, c = o >> 4;
+    int j = node_dof<DIM>(B, bb, lx + a, ly + b, lz + c);
+    if (row_c[j] == rc && alpha_of[j] >= 0 &&
+        dot3<DIM>(vi, load_v(side_v, n_s, j, DIM)) < 0.0)
+      j = alpha_of[j];
+    const double wt = DIM == 3 ? (w[2][c] * w[1][b]) * w[0][a] : w[1][b] * w[0][a];
+    ecol[(int64_t)r * NM + o] = j;
+    ew[(int64_t)r * NM + o] = wt;
+    ew32[(int64_t)r * NM + o] = (float)wt;
+  }
+}
+
+
+// Explicit interpolation rows of BC DOFs (Sec. 4.3, Dirichlet).  Second
+// order: u_alpha = 2 g - u(cpbar_C(x)), cpbar_C(x) = cp_S(2 cp_C(x) - x) (eq.
+// cpc-bar), with weights -w; a member stays a BC DOF when it lies in
+// Omega(C) on the director's side (d*_alpha = v of the node) and is the PDE
+// DOF otherwise.  First order: no linear part (u_alpha = g).
+template <int DIM>
+__global__ void k_erow_bc(Blocks B, int N, int64_t n_s, int64_t n_c, int order,
+                          cpm_surface S, const int* bc_node, const double* bc_cpc,
+                          const int* bc_k, const int* row_c, const int* alpha_of,
+                          const double* side_v, int r0, int* erow_id, int* ecol, double* ew,
+                          float* ew32, int* ebase, unsigned long long* counters) {
+  using G = Geo<DIM>;
+  constexpr int NM = DIM == 3 ? 64 : 16;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_c) return;
+  const int r = r0 + (int)k;
+  erow_id[r] = (int)(n_s + k);
+  if (order != 2) {
+    for (int o = 0; o < NM; ++o) {
+      ecol[(int64_t)r * NM + o] = -1;
+      ew[(int64_t)r * NM + o] = 0.0;
+      ew32[(int64_t)r * NM + o] = 0.0f;
+    }
+    for (int a = 0; a < DIM; ++a) ebase[r * DIM + a] = 0;
+    return;
+  }
+  const int j0 = bc_node[k];
+  const V3 x = node_pos(bc_k[k * 3], bc_k[k * 3 + 1], bc_k[k * 3 + 2], N);
+  const V3 pc{bc_cpc[k * DIM], bc_cpc[k * DIM + 1], DIM == 3 ? bc_cpc[k * DIM + 2] : 0.0};
+  const V3 z{2.0 * pc.x - x.x, 2.0 * pc.y - x.y, DIM == 3 ? 2.0 * pc.z - x.z : 0.0};
+  const V3 y = cp_surface<DIM>(S, z);
+  int base[3];
+  double t[3];
+  stencil_base<DIM>(y, N, base, t);
+  for (int a = 0; a < DIM; ++a) ebase[r * DIM + a] = base[a];
+  double w[3][4];
+  for (int a = 0; a < DIM; ++a) lagrange4<double>(t[a], w[a]);
+  const int bb = block_of<DIM>(B, base[0], base[1], base[2]);
+  const int lx = base[0] & (G::BX - 1), ly = base[1] & (G::BX - 1),
+            lz = DIM == 3 ? (base[2] & (G::BX - 1)) : 0;
+  const int rc = row_c[j0];
+  const V3 vj = load_v(side_v, n_s, j0, DIM);
+  int holes = 0;
+  for (int o = 0; o < NM; ++o) {
+    const int a = o & 3, b = (o >> 2) & 3, c = o >> 4;
+    int m = bb < 0 ? -1 : node_dof<DIM>(B, bb, lx + a, ly + b, lz + c);
+    if (m < 0) {
+      ++holes;
+    } else if (alpha_of[m] >= 0 && row_c[m] == rc &&
+               !(dot3<DIM>(vj, load_v(side_v, n_s, m, DIM)) < 0.0)) {
+      m = alpha_of[m];
+    }
+    const double wt = DIM == 3 ? (w[2][c] * w[1][b]) * w[0][a] : w[1][b] * w[0][a];
+    ecol[(int64_t)r * NM + o] = m;
+    ew[(int64_t)r * NM + o] = -wt;
+    ew32[(int64_t)r * NM + o] = (float)(-wt);
+  }
+  if (holes) atomicAdd(&counters[3], (unsigned long long)holes);
+}
+
+// FD neighbours of PDE rows in a check region: swap flag (eq.
+// stencil-crossing-test applied to the FD stencil).
+template <int DIM>
+__global__ __launch_bounds__(256) void k_lflag(Blocks B, int nb, int64_t n_s, const int* row_c,
+                                               const int* alpha_of, const double* side_v,
+                                               int* lflag) {
+  NODE_PROLOGUE(DIM);
+  const int rc = row_c[dof];
+  int sw = 0;
+  if (rc >= 0) {
+    const V3 vi = load_v(side_v, n_s, dof, DIM);
+    const int l[3] = {G::lx(slot), G::ly(slot), G::lz(slot)};
+    for (int f = 0; f < 2 * DIM; ++f) {
+      int m[3] = {l[0], l[1], l[2]};
+      m[f >> 1] += (f & 1) ? 1 : -1;
+      const int k = node_dof<DIM>(B, blk, m[0], m[1], m[2]);
+      if (k >= 0 && alpha_of[k] >= 0 && row_c[k] == rc &&
+          dot3<DIM>(vi, load_v(side_v, n_s, k, DIM)) < 0.0)
+        sw = 1;
+    }
+  }
+  lflag[dof] = sw;
+}
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_lrow_pde(Blocks B, int nb, int64_t n_s, const int* row_c,
+                                                  const int* alpha_of, const double* side_v,
+                                                  const int* lflag, const int* lidx,
+                                                  int* lrow_id, int* lcol, int* lcol0,
+                                                  unsigned long long* lrow_mask) {
+  NODE_PROLOGUE(DIM);
+  if (!lflag[dof]) return;
+  const int r = lidx[dof];
+  lrow_id[r] = dof;
+  atomicOr(&lrow_mask[blk], 1ull << slot);
+  const int rc = row_c[dof];
+  const V3 vi = load_v(side_v, n_s, dof, DIM);
+  const int l[3] = {G::lx(slot), G::ly(slot), G::lz(slot)};
+  for (int f = 0; f < 2 * DIM; ++f) {
+    int m[3] = {l[0], l[1], l[2]};
+    m[f >> 1] += (f & 1) ? 1 : -1;
+    const int k = node_dof<DIM>(B, blk, m[0], m[1], m[2]);
+    int col = k;
+    if (k >= 0 && alpha_of[k] >= 0 && row_c[k] == rc &&
+        dot3<DIM>(vi, load_v(side_v, n_s, k, DIM)) < 0.0)
+      col = alpha_of[k];
+    lcol0[r * 2 * DIM + f] = k;
+    lcol[r * 2 * DIM + f] = col;
+  }
+}
+
+// FD rows of BC DOFs (eq. FD-crossing-test): neighbours outside Omega(C) are
+// removed; a neighbour stays a BC DOF unless it lies on the other side.
+template <int DIM>
+__global__ void k_lrow_bc(Blocks B, int64_t n_s, int64_t n_c, const int* bc_node,
+                          const int* bc_k, const int* row_c, const int* alpha_of,
+                          const double* side_v, int r0, int* lrow_id, int* lcol, int* lcol0) {
+  using G = Geo<DIM>;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_c) return;
+  const int r = r0 + (int)k;
+  lrow_id[r] = (int)(n_s + k);
+  const int j0 = bc_node[k];
+  const int rc = row_c[j0];
+  const V3 vj = load_v(side_v, n_s, j0, DIM);
+  const int kk[3] = {bc_k[k * 3], bc_k[k * 3 + 1], bc_k[k * 3 + 2]};
+  const int blk = block_of<DIM>(B, kk[0], kk[1], kk[2]);
+  const int l[3] = {kk[0] & (G::BX - 1), kk[1] & (G::BX - 1), DIM == 3 ? (kk[2] & (G::BX - 1)) : 0};
+  for (int f = 0; f < 2 * DIM; ++f) {
+    int m[3] = {l[0], l[1], l[2]};
+    m[f >> 1] += (f & 1) ? 1 : -1;
+    const int q = node_dof<DIM>(B, blk, m[0], m[1], m[2]);
+    int col = -1;
+    if (q >= 0 && alpha_of[q] >= 0 && row_c[q] == rc)
+      col = dot3<DIM>(vj, load_v(side_v, n_s, q, DIM)) < 0.0 ? q : alpha_of[q];
+    lcol0[r * 2 * DIM + f] = -1;
+    lcol[r * 2 * DIM + f] = col;
+  }
+}
+
+// ---------------------------------------------------------------- export
+template <int DIM>
+__global__ __launch_bounds__(256) void k_export_rows(Blocks B, int nb, int N, int64_t n_s,
+                                                     const double* cp, int* coords, int* ecols,
+                                                     int* lcols, int* bases) {
+  NODE_PROLOGUE(DIM);
+  constexpr int NM = DIM == 3 ? 64 : 16;
+  const int k3[3] = {kx, ky, kz};
+  if (coords)
+    for (int a = 0; a < DIM; ++a) coords[(int64_t)dof * DIM + a] = k3[a];
+  if (ecols || bases) {
+    const V3 y = load_v(cp, n_s, dof, DIM);
+    int base[3];
+    double t[3];
+    stencil_base<DIM>(y, N, base, t);
+    if (bases)
+      for (int a = 0; a < DIM; ++a) bases[(int64_t)dof * DIM + a] = base[a];
+    if (ecols) {
+      const int bb = block_of<DIM>(B, base[0], base[1], base[2]);
+      const int lx = base[0] & (G::BX - 1), ly = base[1] & (G::BX - 1),
+                lz = DIM == 3 ? (base[2] & (G::BX - 1)) : 0;
+      for (int o = 0; o < NM; ++o)
+        ecols[(int64_t)dof * NM + o] =
+            bb < 0 ? -1 : node_dof<DIM>(B, bb, lx + (o & 3), ly + ((o >> 2) & 3), lz + (o >> 4));
+    }
+  }
+  if (lcols) {
+    const int l[3] = {G::lx(slot), G::ly(slot), G::lz(slot)};
+    for (int f = 0; f < 2 * DIM; ++f) {
+      int m[3] = {l[0], l[1], l[2]};
+      m[f >> 1] += (f & 1) ? 1 : -1;
+      lcols[(int64_t)dof * 2 * DIM + f] = node_dof<DIM>(B, blk, m[0], m[1], m[2]);
+    }
+  }
+}
+
+__global__ void k_export_erows(int n_erows, int nm, int dim, const int* erow_id, const int* ecol,
+                               const int* ebase, int* ecols, int* bases) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n_erows * nm) return;
+  const int r = (int)(t / nm), o = (int)(t % nm);
+  const int id = erow_id[r];
+  if (ecols) ecols[(int64_t)id * nm + o] = ecol[t];
+  if (bases && o < dim) bases[(int64_t)id * dim + o] = ebase[r * dim + o];
+}
+
+__global__ void k_export_lrows(int n_lrows, int nf, const int* lrow_id, const int* lcol, int* lcols) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n_lrows * nf) return;
+  const int r = (int)(t / nf), f = (int)(t % nf);
+  lcols[(int64_t)lrow_id[r] * nf + f] = lcol[t];
+}
+
+// ================================================================== host
+namespace {
+
+Blocks view(const cpm_band* b) {
+  return Blocks{b->blk_coord, b->blk_mask, b->blk_off, b->blk_nbr, b->hkeys, b->hvals, b->hcap};
+}
+
+// A temporary device buffer freed at scope exit.
+template <class T>
+struct Tmp {
+  T* p = nullptr;
+  explicit Tmp(size_t n) { CPM_HIP(hipMalloc(&p, (n ? n : 1) * sizeof(T))); }
+  ~Tmp() { if (p) (void)hipFree(p); }
+  Tmp(const Tmp&) = delete;
+  Tmp& operator=(const Tmp&) = delete;
+};
+
+template <class T>
+T read1(const T* d, hipStream_t s) {
+  T h;
+  CPM_HIP(hipMemcpyAsync(&h, d, sizeof(T), hipMemcpyDeviceToHost, s));
+  CPM_HIP(hipStreamSynchronize(s));
+  return h;
+}
+
+double reach_of(const cpm_surface& S) {
+  if (S.kind == CPM_SURF_TORUS) return std::min(S.rho, S.R - S.rho);
+  return S.R;
+}
+
+template <int DIM>
+void build(cpm_band* b, hipStream_t st) {
+  using G = Geo<DIM>;
+  const cpm_surface& S = b->surf;
+  const int N = b->N;
+  const double r = b->r;
+
+  // ---- bounding box of blocks
+  double ext[3] = {S.R, S.R, S.R};
+  if (S.kind == CPM_SURF_TORUS) {
+    ext[0] = ext[1] = S.R + S.rho;
+    ext[2] = S.rho;
+  }
+  Box box{};
+  for (int a = 0; a < 3; ++a) {
+    if (a >= DIM) {
+      box.blo[a] = 0;
+      box.nb[a] = 1;
+      continue;
+    }
+    const long lo = (long)std::floor((S.center[a] - ext[a] - r) * N) - 2;
+    const long hi = (long)std::ceil((S.center[a] + ext[a] + r) * N) + 2;
+    const long blo = lo >> G::SH, bhi = hi >> G::SH;
+    box.blo[a] = (int)blo;
+    box.nb[a] = (int)(bhi - blo + 1);
+  }
+  const int64_t nrows = (int64_t)box.nb[1] * box.nb[2];
+  const double half_diag = 0.5 * (G::BX - 1) * std::sqrt((double)DIM);
+  const double thr = r + (half_diag + 0.01) / N;
+
+  // ---- pass 1: occupied blocks, in lexicographic block order
+  Tmp<int> row_count(nrows), row_off(nrows);
+  hipLaunchKernelGGL((k_classify<DIM, false>), dim3(nrows), dim3(256), 0, st, S, N, r, thr, box,
+                     row_count.p, nullptr, nullptr, nullptr);
+  CPM_LAUNCH_CHECK();
+  const int64_t nb64 = scan_exclusive_i32(row_count.p, row_off.p, nrows, st);
+  if (nb64 <= 0) CPM_FAIL(CPM_E_INVALID, "the band is empty (N = %d)", N);
+  if (nb64 > (1 << 27)) CPM_FAIL(CPM_E_INVALID, "band too large: %lld blocks", (long long)nb64);
+  const int nb = (int)nb64;
+  b->nb = nb;
+  b->blk_coord = b->alloc<int4>(nb);
+  b->blk_mask = b->alloc<unsigned long long>(nb);
+  b->blk_off = b->alloc<int>(nb + 1);
+  hipLaunchKernelGGL((k_classify<DIM, true>), dim3(nrows), dim3(256), 0, st, S, N, r, thr, box,
+                     nullptr, row_off.p, b->blk_coord, b->blk_mask);
+  CPM_LAUNCH_CHECK();
+  {
+    Tmp<int> cnt(nb);
+    hipLaunchKernelGGL(k_popcounts, dim3(grid_for(nb, 256)), dim3(256), 0, st, b->blk_mask, nb, cnt.p);
+    CPM_LAUNCH_CHECK();
+    b->n_s = scan_exclusive_i32(cnt.p, b->blk_off, nb, st);
+    const int ns32 = (int)b->n_s;
+    CPM_HIP(hipMemcpyAsync(b->blk_off + nb, &ns32, sizeof(int), hipMemcpyHostToDevice, st));
+    CPM_HIP(hipStreamSynchronize(st));
+  }
+  if (b->n_s >= (1ll << 30)) CPM_FAIL(CPM_E_INVALID, "band too large: %lld nodes", (long long)b->n_s);
+  const int64_t n_s = b->n_s;
+
+  // ---- hash table and neighbour table
+  unsigned cap = 1024;
+  while (cap < 2u * (unsigned)nb) cap <<= 1;
+  b->hcap = cap;
+  b->hkeys = b->alloc<unsigned long long>(cap);
+  b->hvals = b->alloc<int>(cap);
+  CPM_HIP(hipMemsetAsync(b->hkeys, 0xff, (size_t)cap * sizeof(unsigned long long), st));
+  hipLaunchKernelGGL(k_hash_insert, dim3(grid_for(nb, 256)), dim3(256), 0, st, b->blk_coord, nb,
+                     b->hkeys, b->hvals, cap);
+  CPM_LAUNCH_CHECK();
+  b->blk_nbr = b->alloc<int>((size_t)nb * G::NNBR);
+  hipLaunchKernelGGL(k_neighbours<DIM>, dim3(grid_for((int64_t)nb * G::NNBR, 256)), dim3(256), 0, st,
+                     view(b), nb, b->blk_nbr);
+  CPM_LAUNCH_CHECK();
+  const Blocks B = view(b);
+  const dim3 gnode((nb + 3) / 4);
+
+  // ---- stored closest points
+  b->cp = b->alloc<double>((size_t)DIM * n_s);
+  hipLaunchKernelGGL(k_rows<DIM>, gnode, dim3(256), 0, st, B, nb, S, N, n_s, b->cp);
+  CPM_LAUNCH_CHECK();
+
+  // ---- interior boundaries
+  Tmp<unsigned long long> counters(8);
+  CPM_HIP(hipMemsetAsync(counters.p, 0, 8 * sizeof(unsigned long long), st));
+  IBCList L{};
+  L.n = b->n_ibc;
+  for (int c = 0; c < b->n_ibc; ++c) L.c[c] = b->ibcs[c];
+  const int nib = b->n_ibc;
+  Tmp<int> row_c(nib ? n_s : 1), omega(nib ? n_s : 1), alpha_of(nib ? n_s : 1);
+  Tmp<double> side_v(nib ? (size_t)DIM * n_s : 1), cpcs(nib ? (size_t)DIM * n_s : 1);
+  std::unique_ptr<Tmp<int>> bc_kp;
+  std::vector<int64_t> curve_count(nib, 0);
+  if (nib) {
+    hipLaunchKernelGGL(k_ibc_rows<DIM>, gnode, dim3(256), 0, st, B, nb, S, L, N, n_s, r,
+                       b->check_factor, b->tau, b->cp, row_c.p, omega.p, side_v.p, cpcs.p,
+                       counters.p);
+    CPM_LAUNCH_CHECK();
+    unsigned long long hc[4];
+    CPM_HIP(hipMemcpyAsync(hc, counters.p, sizeof(hc), hipMemcpyDeviceToHost, st));
+    CPM_HIP(hipStreamSynchronize(st));
+    if (hc[2]) CPM_FAIL(CPM_E_OVERLAP, "the check regions of two interior boundaries overlap");
+    b->on_c_nodes = (int64_t)hc[0];
+    CPM_HIP(hipMemsetAsync(alpha_of.p, 0xff, n_s * sizeof(int), st));
+    Tmp<int> flag(n_s), rank(n_s);
+    for (int c = 0; c < nib; ++c) {
+      hipLaunchKernelGGL(k_flag_curve, dim3(grid_for(n_s, 256)), dim3(256), 0, st, row_c.p,
+                         omega.p, n_s, c, flag.p);
+      CPM_LAUNCH_CHECK();
+      curve_count[c] = scan_exclusive_i32(flag.p, rank.p, n_s, st);
+      b->n_c += curve_count[c];
+    }
+    b->bc_node = b->alloc<int>(b->n_c);
+    b->bc_cpc = b->alloc<double>((size_t)b->n_c * DIM);
+    b->bc_side = b->alloc<int>(b->n_c);
+    b->bc_curve = b->alloc<int>(b->n_c);
+    bc_kp.reset(new Tmp<int>((size_t)b->n_c * 3));
+    int64_t base_alpha = 0;
+    for (int c = 0; c < nib; ++c) {
+      hipLaunchKernelGGL(k_flag_curve, dim3(grid_for(n_s, 256)), dim3(256), 0, st, row_c.p,
+                         omega.p, n_s, c, flag.p);
+      CPM_LAUNCH_CHECK();
+      scan_exclusive_i32(flag.p, rank.p, n_s, st);
+      hipLaunchKernelGGL(k_bc_assign<DIM>, gnode, dim3(256), 0, st, B, nb, flag.p, rank.p, n_s,
+                         base_alpha, c, S, L, side_v.p, cpcs.p, alpha_of.p, b->bc_node,
+                         b->bc_cpc, b->bc_side, b->bc_curve, bc_kp->p);
+      CPM_LAUNCH_CHECK();
+      base_alpha += curve_count[c];
+    }
+  }
+  b->n = b->n_s + b->n_c;
+  if (b->n >= (1ll << 30)) CPM_FAIL(CPM_E_INVALID, "system too large");
+  const int64_t n_c = b->n_c;
+
+  // ---- interpolation stencils: holes, swaps, tiles
+  Tmp<int> eflag(n_s), tile_blk_of(n_s), tile_cnt(nb), tile_off(nb), fill(nb);
+  CPM_HIP(hipMemsetAsync(tile_cnt.p, 0, nb * sizeof(int), st));
+  CPM_HIP(hipMemsetAsync(fill.p, 0, nb * sizeof(int), st));
+  hipLaunchKernelGGL(k_stencil_scan<DIM>, gnode, dim3(256), 0, st, B, nb, N, n_s, b->cp,
+                     nib ? row_c.p : nullptr, alpha_of.p, side_v.p, eflag.p, tile_blk_of.p,
+                     tile_cnt.p, counters.p);
+  CPM_LAUNCH_CHECK();
+  {
+    unsigned long long hc[4];
+    CPM_HIP(hipMemcpyAsync(hc, counters.p, sizeof(hc), hipMemcpyDeviceToHost, st));
+    CPM_HIP(hipStreamSynchronize(st));
+    if (hc[3])
+      CPM_FAIL(CPM_E_STENCIL_HOLE, "%llu interpolation-stencil members are not band nodes "
+               "(band radius %.6g = %.4g h too small for cubic stencils)",
+               hc[3], r, r * N);
+    b->no_bc_dof_swaps = (int64_t)hc[1];
+  }
+  // explicit E rows: swapped PDE rows then all BC rows
+  constexpr int NM = DIM == 3 ? 64 : 16;
+  {
+    Tmp<int> eidx(n_s);
+    const int64_t ne_pde = scan_exclusive_i32(eflag.p, eidx.p, n_s, st);
+    b->n_erows = (int)(ne_pde + n_c);
+    b->erow_id = b->alloc<int>(b->n_erows);
+    b->ecol = b->alloc<int>((size_t)b->n_erows * NM);
+    b->ew = b->alloc<double>((size_t)b->n_erows * NM);
+    b->ew32 = b->alloc<float>((size_t)b->n_erows * NM);
+    b->ebase = b->alloc<int>((size_t)b->n_erows * DIM);
+    if (ne_pde)
+      hipLaunchKernelGGL(k_erow_pde<DIM>, gnode, dim3(256), 0, st, B, nb, N, n_s, b->cp, row_c.p,
+                         alpha_of.p, side_v.p, eflag.p, eidx.p, b->erow_id, b->ecol, b->ew,
+                         b->ew32, b->ebase);
+    CPM_LAUNCH_CHECK();
+    if (n_c)
+      hipLaunchKernelGGL(k_erow_bc<DIM>, dim3(grid_for(n_c, 128)), dim3(128), 0, st, B, N, n_s,
+                         n_c, b->order, S, b->bc_node, b->bc_cpc, bc_kp->p, row_c.p, alpha_of.p,
+                         side_v.p, (int)ne_pde, b->erow_id, b->ecol, b->ew, b->ew32, b->ebase,
+                         counters.p);
+    CPM_LAUNCH_CHECK();
+    unsigned long long hc[4];
+    CPM_HIP(hipMemcpyAsync(hc, counters.p, sizeof(hc), hipMemcpyDeviceToHost, st));
+    CPM_HIP(hipStreamSynchronize(st));
+    if (hc[3])
+      CPM_FAIL(CPM_E_STENCIL_HOLE, "%llu mirror-stencil members are not band nodes", hc[3]);
+  }
+  // gather tiles
+  {
+    b->n_tile_rows = (int)scan_exclusive_i32(tile_cnt.p, tile_off.p, nb, st);
+    Tmp<int> nz(nb), tidx(nb);
+    hipLaunchKernelGGL(k_nonzero, dim3(grid_for(nb, 256)), dim3(256), 0, st, tile_cnt.p, nb, nz.p);
+    CPM_LAUNCH_CHECK();
+    b->ntiles = (int)scan_exclusive_i32(nz.p, tidx.p, nb, st);
+    b->tile_blk = b->alloc<int>(b->ntiles);
+    b->tile_start = b->alloc<int>(b->ntiles + 1);
+    hipLaunchKernelGGL(k_tile_compact, dim3(grid_for(nb, 256)), dim3(256), 0, st, tile_cnt.p,
+                       tile_off.p, tidx.p, nb, b->tile_blk, b->tile_start);
+    CPM_LAUNCH_CHECK();
+    CPM_HIP(hipMemcpyAsync(b->tile_start + b->ntiles, &b->n_tile_rows, sizeof(int),
+                           hipMemcpyHostToDevice, st));
+    const int ntr = b->n_tile_rows;
+    b->perm = b->alloc<int>(ntr);
+    b->cp_perm = b->alloc<double>((size_t)DIM * ntr);
+    b->frac32 = b->alloc<float>((size_t)DIM * ntr);
+    b->lbase = b->alloc<unsigned>(ntr);
+    hipLaunchKernelGGL(k_tile_fill<DIM>, gnode, dim3(256), 0, st, B, nb, N, n_s, b->cp, eflag.p,
+                       tile_blk_of.p, tile_off.p, fill.p, ntr, b->perm, b->cp_perm, b->frac32,
+                       b->lbase);
+    CPM_LAUNCH_CHECK();
+  }
+  // explicit L rows: swapped PDE rows then all BC rows
+  b->lrow_mask = b->alloc<unsigned long long>(nb);
+  CPM_HIP(hipMemsetAsync(b->lrow_mask, 0, nb * sizeof(unsigned long long), st));
+  {
+    int64_t nl_pde = 0;
+    Tmp<int> lflag(nib ? n_s : 1), lidx(nib ? n_s : 1);
+    if (nib) {
+      hipLaunchKernelGGL(k_lflag<DIM>, gnode, dim3(256), 0, st, B, nb, n_s, row_c.p, alpha_of.p,
+                         side_v.p, lflag.p);
+      CPM_LAUNCH_CHECK();
+      nl_pde = scan_exclusive_i32(lflag.p, lidx.p, n_s, st);
+    }
+    b->n_lrows = (int)(nl_pde + n_c);
+    b->lrow_id = b->alloc<int>(b->n_lrows);
+    b->lcol = b->alloc<int>((size_t)b->n_lrows * 2 * DIM);
+    b->lcol0 = b->alloc<int>((size_t)b->n_lrows * 2 * DIM);
+    if (nl_pde)
+      hipLaunchKernelGGL(k_lrow_pde<DIM>, gnode, dim3(256), 0, st, B, nb, n_s, row_c.p,
+                         alpha_of.p, side_v.p, lflag.p, lidx.p, b->lrow_id, b->lcol, b->lcol0,
+                         b->lrow_mask);
+    CPM_LAUNCH_CHECK();
+    if (n_c)
+      hipLaunchKernelGGL(k_lrow_bc<DIM>, dim3(grid_for(n_c, 128)), dim3(128), 0, st, B, n_s, n_c,
+                         b->bc_node, bc_kp->p, row_c.p, alpha_of.p, side_v.p, (int)nl_pde,
+                         b->lrow_id, b->lcol, b->lcol0);
+    CPM_LAUNCH_CHECK();
+  }
+  b->ecoef = b->order == 2 ? 2.0 : 1.0;
+  CPM_HIP(hipStreamSynchronize(st));
+}
+
+template <int DIM>
+void export_rows(const cpm_band* b, int* coords, int* ecols, int* lcols, int* bases,
+                 hipStream_t st) {
+  const dim3 gnode((b->nb + 3) / 4);
+  hipLaunchKernelGGL(k_export_rows<DIM>, gnode, dim3(256), 0, st, view(b), b->nb, b->N, b->n_s,
+                     b->cp, coords, ecols, lcols, bases);
+  CPM_LAUNCH_CHECK();
+  const int nm = DIM == 3 ? 64 : 16;
+  if ((ecols || bases) && b->n_erows)
+    hipLaunchKernelGGL(k_export_erows, dim3(grid_for((int64_t)b->n_erows * nm, 256)), dim3(256),
+                       0, st, b->n_erows, nm, DIM, b->erow_id, b->ecol, b->ebase, ecols, bases);
+  CPM_LAUNCH_CHECK();
+  if (lcols && b->n_lrows)
+    hipLaunchKernelGGL(k_export_lrows, dim3(grid_for((int64_t)b->n_lrows * 2 * DIM, 256)),
+                       dim3(256), 0, st, b->n_lrows, 2 * DIM, b->lrow_id, b->lcol, lcols);
+  CPM_LAUNCH_CHECK();
+}
+
+}  // namespace
+}  // namespace cpm
+
+using namespace cpm;
+
+extern "C" cpm_status cpm_build_band(const cpm_surface* surface, const cpm_ibc* ibcs, int n_ibc,
+                                     const cpm_grid* grid, void* hip_stream, cpm_band** out) {
+  return guard([&] {
+    if (!surface || !grid || !out) CPM_FAIL(CPM_E_INVALID, "null argument");
+    *out = nullptr;
+    if (grid->N <= 0) CPM_FAIL(CPM_E_INVALID, "N must be positive (got %d)", grid->N);
+    if (grid->p != 3) CPM_FAIL(CPM_E_INVALID, "only p = 3 (cubic) is supported (got %d)", grid->p);
+    if (grid->order != 1 && grid->order != 2)
+      CPM_FAIL(CPM_E_INVALID, "order must be 1 or 2 (got %d)", grid->order);
+    if (n_ibc < 0 || n_ibc > kMaxIBC || (n_ibc && !ibcs))
+      CPM_FAIL(CPM_E_INVALID, "n_ibc must be in [0, %d] with a non-null array", kMaxIBC);
+    const int kind = surface->kind;
+    if (kind != CPM_SURF_CIRCLE && kind != CPM_SURF_SPHERE && kind != CPM_SURF_TORUS)
+      CPM_FAIL(CPM_E_INVALID, "unknown surface kind %d", kind);
+    if (!(surface->R > 0) || (kind == CPM_SURF_TORUS && !(surface->rho > 0 && surface->rho < surface->R)))
+      CPM_FAIL(CPM_E_INVALID, "bad surface radii");
+    for (int c = 0; c < n_ibc; ++c) {
+      const int k = ibcs[c].kind;
+      const bool ok = k == CPM_IBC_POINT || (k == CPM_IBC_LATITUDE && kind == CPM_SURF_SPHERE &&
+                                              std::fabs(ibcs[c].z0) < surface->R) ||
+                      (k == CPM_IBC_MERIDIAN && kind == CPM_SURF_TORUS);
+      if (!ok) CPM_FAIL(CPM_E_INVALID, "interior boundary %d (kind %d) does not fit surface kind %d", c, k, kind);
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::unique_ptr<cpm_band> b(new cpm_band());
+    CPM_HIP(hipGetDevice(&b->device));
+    b->dim = kind == CPM_SURF_CIRCLE ? 2 : 3;
+    b->N = grid->N;
+    b->order = grid->order;
+    b->surf = *surface;
+    if (b->dim == 2) b->surf.center[2] = 0.0;
+    b->n_ibc = n_ibc;
+    b->ibcs.assign(ibcs, ibcs + n_ibc);
+    b->h = 1.0 / grid->N;
+    const double K = b->dim == 3 ? 17.0 : 13.0;   // eq. (bandwidth), p = 3, q = 1
+    b->r = grid->r_band > 0 ? grid->r_band : std::sqrt(K) / (double)grid->N;
+    b->tau = (grid->tau_factor > 0 ? grid->tau_factor : 0.1) / (double)((int64_t)grid->N * grid->N);
+    b->check_factor = grid->check_factor > 0 ? grid->check_factor : 2.0;
+    if (grid->check_reach && !(b->r < reach_of(*surface)))
+      CPM_FAIL(CPM_E_REACH, "band radius %.6g is not below the reach %.6g of the surface "
+               "(h must be smaller)", b->r, reach_of(*surface));
+    if (b->dim == 3) build<3>(b.get(), st);
+    else build<2>(b.get(), st);
+    *out = b.release();
+  });
+}
+
+extern "C" cpm_status cpm_band_export(const cpm_band* b, int what, void* host_dst, size_t bytes) {
+  return guard([&] {
+    if (!b || !host_dst) CPM_FAIL(CPM_E_INVALID, "null argument");
+    const int d = b->dim, nm = d == 3 ? 64 : 16;
+    size_t need = 0;
+    switch (what) {
+      case CPM_EXPORT_COORDS: need = (size_t)b->n_s * d * 4; break;
+      case CPM_EXPORT_CP: need = (size_t)b->n_s * d * 8; break;
+      case CPM_EXPORT_BC_NODE: case CPM_EXPORT_BC_SIDE: case CPM_EXPORT_BC_CURVE:
+        need = (size_t)b->n_c * 4; break;
+      case CPM_EXPORT_BC_CPC: need = (size_t)b->n_c * d * 8; break;
+      case CPM_EXPORT_ECOLS: need = (size_t)b->n * nm * 4; break;
+      case CPM_EXPORT_LCOLS: need = (size_t)b->n * 2 * d * 4; break;
+      case CPM_EXPORT_BASE: need = (size_t)b->n * d * 4; break;
+      default: CPM_FAIL(CPM_E_INVALID, "unknown export item %d", what);
+    }
+    if (bytes != need) CPM_FAIL(CPM_E_INVALID, "export %d needs %zu bytes, got %zu", what, need, bytes);
+    if (need == 0) return;
+    hipStream_t st = nullptr;
+    if (what == CPM_EXPORT_CP) {
+      std::vector<double> soa((size_t)b->n_s * d);
+      CPM_HIP(hipMemcpy(soa.data(), b->cp, soa.size() * 8, hipMemcpyDeviceToHost));
+      double* o = static_cast<double*>(host_dst);
+      for (int64_t i = 0; i < b->n_s; ++i)
+        for (int a = 0; a < d; ++a) o[i * d + a] = soa[(size_t)a * b->n_s + i];
+      return;
+    }
+    const void* src = nullptr;
+    if (what == CPM_EXPORT_BC_NODE) src = b->bc_node;
+    if (what == CPM_EXPORT_BC_SIDE) src = b->bc_side;
+    if (what == CPM_EXPORT_BC_CURVE) src = b->bc_curve;
+    if (what == CPM_EXPORT_BC_CPC) src = b->bc_cpc;
+    if (src) {
+      CPM_HIP(hipMemcpy(host_dst, src, need, hipMemcpyDeviceToHost));
+      return;
+    }
+    Tmp<int> dev(need / 4);
+    CPM_HIP(hipMemset(dev.p, 0xff, need));
+    int* coords = what == CPM_EXPORT_COORDS ? dev.p : nullptr;
+    int* ecols = what == CPM_EXPORT_ECOLS ? dev.p : nullptr;
+    int* lcols = what == CPM_EXPORT_LCOLS ? dev.p : nullptr;
+    int* bases = what == CPM_EXPORT_BASE ? dev.p : nullptr;
+    if (bases) CPM_HIP(hipMemset(dev.p, 0, need));
+    if (d == 3) export_rows<3>(b, coords, ecols, lcols, bases, st);
+    else export_rows<2>(b, coords, ecols, lcols, bases, st);
+    CPM_HIP(hipStreamSynchronize(st));
+    CPM_HIP(hipMemcpy(host_dst, dev.p, need, hipMemcpyDeviceToHost));
+  });
+}

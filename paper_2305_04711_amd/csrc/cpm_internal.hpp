@@ -1,0 +1,188 @@
+// Internal declarations of libcpm (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/cpm.h"
+
+namespace cpm {
+
+// ------------------------------------------------------------------ errors
+void set_error(const char* fmt, ...);
+
+struct Error {
+  cpm_status code;
+};
+
+#define CPM_HIP(call)                                                        \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess) {                                                  \
+      ::cpm::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                       __FILE__, __LINE__);                                  \
+      throw ::cpm::Error{e_ == hipErrorOutOfMemory ? CPM_E_OOM : CPM_E_HIP}; \
+    }                                                                        \
+  } while (0)
+
+#define CPM_FAIL(code, ...)          \
+  do {                               \
+    ::cpm::set_error(__VA_ARGS__);   \
+    throw ::cpm::Error{code};        \
+  } while (0)
+
+#define CPM_LAUNCH_CHECK() CPM_HIP(hipGetLastError())
+
+// Runs f and converts exceptions into a status (no exception crosses the ABI).
+template <class F>
+cpm_status guard(F&& f) {
+  try {
+    f();
+    return CPM_OK;
+  } catch (const Error& e) {
+    return e.code;
+  } catch (const std::exception& e) {
+    set_error("internal error: %s", e.what());
+    return CPM_E_INVALID;
+  } catch (...) {
+    set_error("internal error");
+    return CPM_E_INVALID;
+  }
+}
+
+// --------------------------------------------------------------- geometry
+// Block layout: 3-D blocks are 4x4x4 nodes, 2-D blocks 8x8 nodes; both hold
+// 64 nodes, one wavefront, one 64-bit occupancy mask.  Slot s of a block:
+// 3-D s = lx + 4 ly + 16 lz, 2-D s = lx + 8 ly.
+template <int DIM> struct Geo;
+template <> struct Geo<3> {
+  static constexpr int BX = 4, SH = 2, NNBR = 27;
+  __host__ __device__ static int slot(int lx, int ly, int lz) { return lx + 4 * ly + 16 * lz; }
+  __host__ __device__ static int lx(int s) { return s & 3; }
+  __host__ __device__ static int ly(int s) { return (s >> 2) & 3; }
+  __host__ __device__ static int lz(int s) { return s >> 4; }
+  __host__ __device__ static int code(int dx, int dy, int dz) { return (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1); }
+};
+template <> struct Geo<2> {
+  static constexpr int BX = 8, SH = 3, NNBR = 9;
+  __host__ __device__ static int slot(int lx, int ly, int) { return lx + 8 * ly; }
+  __host__ __device__ static int lx(int s) { return s & 7; }
+  __host__ __device__ static int ly(int s) { return s >> 3; }
+  __host__ __device__ static int lz(int) { return 0; }
+  __host__ __device__ static int code(int dx, int dy, int) { return (dy + 1) * 3 + (dx + 1); }
+};
+
+struct Workspace;
+
+}  // namespace cpm
+
+// The band: everything a call needs, all arrays on the device.
+struct cpm_band {
+  int dim = 0, N = 0, order = 2, n_ibc = 0;
+  cpm_surface surf{};
+  std::vector<cpm_ibc> ibcs;
+  double h = 0, r = 0, tau = 0, check_factor = 2;
+  int64_t n_s = 0, n_c = 0, n = 0;
+  int device = 0;
+
+  // occupied blocks (block order = lexicographic in (bz, by, bx))
+  int nb = 0;
+  int4* blk_coord = nullptr;          // [nb] block coordinates
+  unsigned long long* blk_mask = nullptr;  // [nb] occupied slots
+  int* blk_off = nullptr;             // [nb + 1] first PDE DOF of the block
+  int* blk_nbr = nullptr;             // [nb][NNBR] neighbour block ids or -1
+  unsigned long long* lrow_mask = nullptr; // [nb] slots whose L row is explicit
+
+  // hash table block key -> block id (open addressing)
+  unsigned long long* hkeys = nullptr;
+  int* hvals = nullptr;
+  unsigned int hcap = 0;
+
+  // PDE rows
+  double* cp = nullptr;               // [dim][n_s] stored cp_S (SoA)
+
+  // gather tiles: PDE rows without swapped interpolation members, grouped by
+  // the block that holds their stencil base
+  int ntiles = 0, n_tile_rows = 0;
+  int* tile_blk = nullptr;            // [ntiles]
+  int* tile_start = nullptr;          // [ntiles + 1]
+  int* perm = nullptr;                // [n_tile_rows] row DOF
+  double* cp_perm = nullptr;          // [dim][n_tile_rows]
+  float* frac32 = nullptr;            // [dim][n_tile_rows] FP32 fractions
+  unsigned int* lbase = nullptr;      // [n_tile_rows] packed local base
+
+  // rows with explicit interpolation stencils (swapped PDE rows, BC rows)
+  int n_erows = 0;
+  int* erow_id = nullptr;             // [n_erows]
+  int* ecol = nullptr;                // [n_erows][4^dim]
+  double* ew = nullptr;               // [n_erows][4^dim]
+  float* ew32 = nullptr;              // [n_erows][4^dim]
+  int* ebase = nullptr;               // [n_erows][dim]
+
+  // rows with explicit FD stencils (swapped PDE rows, BC rows)
+  int n_lrows = 0;
+  int* lrow_id = nullptr;             // [n_lrows]
+  int* lcol = nullptr;                // [n_lrows][2 dim] after swaps, -1 none
+  int* lcol0 = nullptr;               // [n_lrows][2 dim] before swaps (PDE rows)
+
+  // BC DOFs
+  int* bc_node = nullptr;             // [n_c]
+  double* bc_cpc = nullptr;           // [n_c][dim]
+  int* bc_side = nullptr;             // [n_c]
+  int* bc_curve = nullptr;            // [n_c]
+  double ecoef = 2.0;
+
+  int64_t on_c_nodes = 0, no_bc_dof_swaps = 0;
+  size_t bytes = 0;
+  std::vector<void*> allocs;
+  cpm::Workspace* ws = nullptr;
+
+  template <class T>
+  T* alloc(size_t count) {
+    void* p = nullptr;
+    size_t b = count * sizeof(T);
+    if (b == 0) b = 16;
+    CPM_HIP(hipMalloc(&p, b));
+    allocs.push_back(p);
+    bytes += b;
+    return static_cast<T*>(p);
+  }
+  ~cpm_band();
+};
+
+namespace cpm {
+
+// Scratch vectors owned by a band, grown on demand (calls on one band from
+// several threads at once race on them).
+struct Workspace {
+  std::vector<std::pair<void*, size_t>> slots;
+  void* get(int i, size_t bytes);
+  ~Workspace();
+};
+void* band_scratch(const cpm_band* b, int slot, size_t bytes);
+
+// Device-wide exclusive scan; returns the total (synchronises the stream).
+int64_t scan_exclusive_i32(const int* in, int* out, int64_t n, hipStream_t s);
+
+// apply entry points used by the solvers (nrhs = 1, optional gauge)
+template <class T>
+void apply_impl(const cpm_band* b, double m, double n, int nrhs, const T* u,
+                T* v, hipStream_t s, const double* gauge_sum = nullptr,
+                double gamma = 0.0);
+template <class T>
+void apply_transpose_impl(const cpm_band* b, double m, double n, int nrhs,
+                          const T* w, T* z, hipStream_t s,
+                          const double* gauge_sum = nullptr, double gamma = 0.0);
+
+inline int grid_for(int64_t n, int threads, int cap = 1 << 20) {
+  int64_t g = (n + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return static_cast<int>(g);
+}
+
+}  // namespace cpm

@@ -1,0 +1,585 @@
+// Krylov solvers on the device: unpreconditioned BiCGSTAB (van der Vorst; the
+// paper's solver follows Eigen's BiCGSTAB, Sec. 5.4) in FP64 or FP32, and
+// mixed precision: FP32 BiCGSTAB for the correction equation inside FP64
+// iterative refinement (residual and update in FP64).
+//
+// The recurrence scalars live in device memory.  Every reduction kernel
+// writes one partial sum per workgroup; the last workgroup to finish (found
+// with a device-scope fence and an atomic counter) adds the partials in a
+// fixed order and updates the scalars, so results are bitwise reproducible
+// and the host only reads the scalars every `check_every` iterations.  The
+// check_every iterations can be captured once into a hipGraph and replayed.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <memory>
+
+#include "cpm_internal.hpp"
+
+namespace cpm {
+
+struct Scal {
+  double rho, rho_old, alpha, omega, beta;
+  double bb, rr, tol2;
+  double d0, d1;
+  int done, breakdown, it, restarts;
+  unsigned counter;
+  unsigned pad;
+};
+
+constexpr int kRedThreads = 256;
+constexpr int kMaxParts = 1024;
+
+static int red_grid(int64_t n) {
+  int64_t g = (n + kRedThreads * 4 - 1) / (kRedThreads * 4);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, kMaxParts));
+}
+
+// Workgroup sum of NR values; thread 0 gets the totals.
+template <int NR>
+__device__ __forceinline__ void wg_sum(double v[NR], double (*sh)[kRedThreads]) {
+  for (int k = 0; k < NR; ++k) sh[k][threadIdx.x] = v[k];
+  __syncthreads();
+  for (int o = kRedThreads / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o)
+      for (int k = 0; k < NR; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + o];
+    __syncthreads();
+  }
+  for (int k = 0; k < NR; ++k) v[k] = sh[k][0];
+}
+
+// Writes this workgroup's partials; returns true in every thread of the last
+// workgroup, with out[] holding the grand totals (fixed summation order).
+template <int NR>
+__device__ bool finish_reduction(double v[NR], double* part, Scal* S, double out[NR]) {
+  __shared__ double sh[NR][kRedThreads];
+  __shared__ bool last;
+  wg_sum<NR>(v, sh);
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < NR; ++k) part[k * kMaxParts + blockIdx.x] = v[k];
+    __threadfence();
+    const unsigned prev = atomicAdd(&S->counter, 1u);
+    last = prev == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+  double acc[NR];
+  for (int k = 0; k < NR; ++k) acc[k] = 0.0;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += kRedThreads)
+    for (int k = 0; k < NR; ++k) acc[k] += __builtin_nontemporal_load(&part[k * kMaxParts + i]);
+  __syncthreads();
+  wg_sum<NR>(acc, sh);
+  for (int k = 0; k < NR; ++k) out[k] = acc[k];
+  if (threadIdx.x == 0) S->counter = 0;
+  return true;
+}
+
+// r = b - v;  rh = r;  p = r;  sums (rh, r), (r, r), (b, b)
+template <class T>
+__global__ __launch_bounds__(256) void k_init(int64_t n, const T* __restrict__ b, const T* __restrict__ v,
+                                              bool has_v, T* r, T* rh, T* p, double* part, Scal* S,
+                                              double tol) {
+  double acc[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kRedThreads) {
+    const T ri = has_v ? b[i] - v[i] : b[i];
+    r[i] = ri;
+    rh[i] = ri;
+    p[i] = ri;
+    const double d = (double)ri, bd = (double)b[i];
+    acc[0] += d * d;
+    acc[1] += bd * bd;
+  }
+  double tot[2];
+  if (finish_reduction<2>(acc, part, S, tot) && threadIdx.x == 0) {
+    S->rho = tot[0];
+    S->rho_old = tot[0];
+    S->rr = tot[0];
+    S->bb = tot[1];
+    S->tol2 = tol * tol * tot[1];
+    S->alpha = S->omega = 1.0;
+    S->beta = 0.0;
+    S->breakdown = 0;
+    S->done = (tot[0] <= S->tol2) ? 1 : 0;
+  }
+}
+
+// alpha = rho / (rh, v)
+template <class T>
+__global__ __launch_bounds__(256) void k_dot_rv(int64_t n, const T* __restrict__ rh,
+                                                const T* __restrict__ v, double* part, Scal* S) {
+  if (S->done) return;
+  double acc[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kRedThreads)
+    acc[0] += (double)rh[i] * (double)v[i];
+  double tot[1];
+  if (finish_reduction<1>(acc, part, S, tot) && threadIdx.x == 0) {
+    if (tot[0] == 0.0 || !__builtin_isfinite(tot[0])) {
+      S->breakdown = 1;
+      S->done = 1;
+    } else {
+      S->alpha = S->rho / tot[0];
+    }
+  }
+}
+
+// s = r - alpha v
+template <class T>
+__global__ __launch_bounds__(256) void k_s(int64_t n, const T* __restrict__ r, const T* __restrict__ v,
+                                           T* __restrict__ s, const Scal* S) {
+  if (S->done) return;
+  const T al = (T)S->alpha;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    s[i] = r[i] - al * v[i];
+}
+
+// omega = (t, s) / (t, t)
+template <class T>
+__global__ __launch_bounds__(256) void k_dot_ts(int64_t n, const T* __restrict__ t,
+                                                const T* __restrict__ s, double* part, Scal* S) {
+  if (S->done) return;
+  double acc[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kRedThreads) {
+    const double ti = (double)t[i];
+    acc[0] += ti * (double)s[i];
+    acc[1] += ti * ti;
+  }
+  double tot[2];
+  if (finish_reduction<2>(acc, part, S, tot) && threadIdx.x == 0) {
+    if (tot[1] == 0.0 || !__builtin_isfinite(tot[1])) {
+      S->omega = 0.0;
+    } else {
+      S->omega = tot[0] / tot[1];
+    }
+  }
+}
+
+// x += alpha p + omega s;  r = s - omega t;  rho = (rh, r);  rr = (r, r)
+template <class T>
+__global__ __launch_bounds__(256) void k_xr(int64_t n, T* __restrict__ x, const T* __restrict__ p,
+                                            const T* __restrict__ s, const T* __restrict__ t,
+                                            T* __restrict__ r, const T* __restrict__ rh,
+                                            double* part, Scal* S) {
+  if (S->done) return;
+  const T al = (T)S->alpha, om = (T)S->omega;
+  double acc[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kRedThreads) {
+    const T si = s[i];
+    x[i] = x[i] + al * p[i] + om * si;
+    const T ri = si - om * t[i];
+    r[i] = ri;
+    acc[0] += (double)rh[i] * (double)ri;
+    acc[1] += (double)ri * (double)ri;
+  }
+  double tot[2];
+  if (finish_reduction<2>(acc, part, S, tot) && threadIdx.x == 0) {
+    S->it += 1;
+    S->rr = tot[1];
+    if (!__builtin_isfinite(tot[1])) {
+      S->breakdown = 1;
+      S->done = 1;
+    } else if (tot[1] <= S->tol2) {
+      S->done = 1;
+    } else if (tot[0] == 0.0 || S->omega == 0.0) {
+      S->breakdown = 1;
+      S->done = 1;
+    } else {
+      S->rho_old = S->rho;
+      S->rho = tot[0];
+      S->beta = (S->rho / S->rho_old) * (S->alpha / S->omega);
+    }
+  }
+}
+
+// p = r + beta (p - omega v)
+template <class T>
+__global__ __launch_bounds__(256) void k_p(int64_t n, const T* __restrict__ r, T* __restrict__ p,
+                                           const T* __restrict__ v, const Scal* S) {
+  if (S->done) return;
+  const T be = (T)S->beta, om = (T)S->omega;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = r[i] + be * (p[i] - om * v[i]);
+}
+
+// ---- mixed precision helpers (FP64 side)
+// r = b - v (FP64) and rr = (r, r), bb = (b, b)
+__global__ __launch_bounds__(256) void k_res64(int64_t n, const double* __restrict__ b,
+                                               const double* __restrict__ v, double* __restrict__ r,
+                                               double* part, Scal* S) {
+  double acc[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kRedThreads) {
+    const double ri = b[i] - v[i];
+    r[i] = ri;
+    acc[0] += ri * ri;
+    acc[1] += b[i] * b[i];
+  }
+  double tot[2];
+  if (finish_reduction<2>(acc, part, S, tot) && threadIdx.x == 0) {
+    S->rr = tot[0];
+    S->bb = tot[1];
+  }
+}
+
+__global__ void k_to32(int64_t n, const double* __restrict__ r, float* __restrict__ r32,
+                       float* __restrict__ d32, double inv) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    r32[i] = (float)(r[i] * inv);
+    d32[i] = 0.0f;
+  }
+}
+
+__global__ void k_add32(int64_t n, double* __restrict__ x, const float* __restrict__ d, double scale) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] += scale * (double)d[i];
+}
+
+__global__ void k_set_it(Scal* S, int it) {
+  if (threadIdx.x == 0) S->it = it;
+}
+
+__global__ void k_zero_scal(Scal* S) {
+  if (threadIdx.x == 0) {
+    S->it = 0;
+    S->done = 0;
+    S->breakdown = 0;
+    S->counter = 0;
+  }
+}
+
+// ================================================================== host
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+// CPM_TRACE=1 prints the refinement history to stderr.
+bool trace_on() {
+  static const int on = [] {
+    const char* e = std::getenv("CPM_TRACE");
+    return e && e[0] && e[0] != '0' ? 1 : 0;
+  }();
+  return on != 0;
+}
+
+struct Pinned {
+  Scal* h = nullptr;
+  Pinned() { CPM_HIP(hipHostMalloc((void**)&h, sizeof(Scal), hipHostMallocDefault)); }
+  ~Pinned() { if (h) (void)hipHostFree(h); }
+};
+
+// BiCGSTAB on one right-hand side.  Vectors are band scratch slots.
+template <class T>
+struct Bicg {
+  const cpm_band* b;
+  hipStream_t st;
+  int64_t n;
+  double m, nn, gamma;
+  bool transpose;
+  T *r, *rh, *p, *v, *s, *t;
+  double* part;
+  Scal* S;
+  Pinned pin;
+  int ew_grid, red_g;
+  hipGraphExec_t gexec = nullptr;
+  int graph_iters = 0;
+  const T* gx_rhs = nullptr;
+  T* gx_x = nullptr;
+
+  Bicg(const cpm_band* b_, hipStream_t st_, double m_, double n_, double gamma_, bool tr, int slot0)
+      : b(b_), st(st_), n(b_->n), m(m_), nn(n_), gamma(gamma_), transpose(tr) {
+    const size_t vb = sizeof(T) * (size_t)n;
+    r = (T*)band_scratch(b, slot0 + 0, vb);
+    rh = (T*)band_scratch(b, slot0 + 1, vb);
+    p = (T*)band_scratch(b, slot0 + 2, vb);
+    v = (T*)band_scratch(b, slot0 + 3, vb);
+    s = (T*)band_scratch(b, slot0 + 4, vb);
+    t = (T*)band_scratch(b, slot0 + 5, vb);
+    part = (double*)band_scratch(b, slot0 + 6, sizeof(double) * 2 * kMaxParts);
+    S = (Scal*)band_scratch(b, slot0 + 7, sizeof(Scal));
+    CPM_HIP(hipMemsetAsync(S, 0, sizeof(Scal), st));
+    ew_grid = grid_for(n, 256, 4096);
+    red_g = red_grid(n);
+    // make sure every scratch buffer exists before any graph capture
+    band_scratch(b, 0, sizeof(T) * (size_t)n);
+    if (gamma != 0.0) {
+      band_scratch(b, 3, sizeof(double) * 256 + 64);
+      band_scratch(b, 4, sizeof(double) + 64);
+    }
+    if (transpose) {
+      band_scratch(b, 1, sizeof(T) * (size_t)n);
+      band_scratch(b, 2, sizeof(T) * (size_t)n);
+    }
+  }
+  ~Bicg() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+  }
+
+  void apply(const T* in, T* out) {
+    if (transpose) apply_transpose_impl<T>(b, m, nn, 1, in, out, st, nullptr, gamma);
+    else apply_impl<T>(b, m, nn, 1, in, out, st, nullptr, gamma);
+  }
+
+  void init(const T* rhs, const T* x, bool x_zero, double tol) {
+    if (!x_zero) apply(x, v);
+    hipLaunchKernelGGL(k_init<T>, dim3(red_g), dim3(kRedThreads), 0, st, n, rhs, v, !x_zero, r,
+                       rh, p, part, S, tol);
+    CPM_LAUNCH_CHECK();
+  }
+
+  void iteration(T* x) {
+    apply(p, v);
+    hipLaunchKernelGGL(k_dot_rv<T>, dim3(red_g), dim3(kRedThreads), 0, st, n, rh, v, part, S);
+    hipLaunchKernelGGL(k_s<T>, dim3(ew_grid), dim3(256), 0, st, n, r, v, s, S);
+    apply(s, t);
+    hipLaunchKernelGGL(k_dot_ts<T>, dim3(red_g), dim3(kRedThreads), 0, st, n, t, s, part, S);
+    hipLaunchKernelGGL(k_xr<T>, dim3(red_g), dim3(kRedThreads), 0, st, n, x, p, s, t, r, rh, part, S);
+    hipLaunchKernelGGL(k_p<T>, dim3(ew_grid), dim3(256), 0, st, n, r, p, v, S);
+    CPM_LAUNCH_CHECK();
+  }
+
+  void run_iters(T* x, int k, bool use_graph) {
+    if (!use_graph) {
+      for (int i = 0; i < k; ++i) iteration(x);
+      return;
+    }
+    if (!gexec || graph_iters != k || gx_x != x) {
+      if (gexec) CPM_HIP(hipGraphExecDestroy(gexec));
+      gexec = nullptr;
+      hipGraph_t g;
+      CPM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      try {
+        for (int i = 0; i < k; ++i) iteration(x);
+      } catch (...) {
+        hipGraph_t dummy;
+        (void)hipStreamEndCapture(st, &dummy);
+        throw;
+      }
+      CPM_HIP(hipStreamEndCapture(st, &g));
+      const hipError_t e = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      CPM_HIP(e);
+      graph_iters = k;
+      gx_x = x;
+    }
+    CPM_HIP(hipGraphLaunch(gexec, st));
+  }
+
+  const Scal& read() {
+    CPM_HIP(hipMemcpyAsync(pin.h, S, sizeof(Scal), hipMemcpyDeviceToHost, st));
+    CPM_HIP(hipStreamSynchronize(st));
+    return *pin.h;
+  }
+
+  // Solve A x = rhs to the recursive residual tol (relative).  Returns the
+  // iterations spent; breakdowns restart from the current iterate.  With
+  // xbest, the iterate of smallest recursive residual seen at a check is kept
+  // and returned when the solve ends unconverged, and the solve stops early
+  // once the residual exceeds diverge * ||rhs|| (FP32 BiCGSTAB on badly
+  // conditioned systems can diverge after a long plateau).
+  int solve(const T* rhs, T* x, bool x_zero, double tol, int maxit, int check_every,
+            bool use_graph, int* restarts, T* xbest = nullptr, double diverge = 0.0) {
+    hipLaunchKernelGGL(k_zero_scal, dim3(1), dim3(64), 0, st, S);
+    init(rhs, x, x_zero, tol);
+    int it = 0;
+    const Scal* h = &read();
+    double best = h->rr;
+    bool have_best = false;
+    const size_t vb = sizeof(T) * (size_t)n;
+    while (!h->done && it < maxit) {
+      const int k = std::min(check_every, maxit - it);
+      run_iters(x, k, use_graph && k == check_every);
+      h = &read();
+      it = h->it;
+      if (xbest && !h->done && h->rr < best) {
+        CPM_HIP(hipMemcpyAsync(xbest, x, vb, hipMemcpyDeviceToDevice, st));
+        best = h->rr;
+        have_best = true;
+      }
+      if (diverge > 0.0 && !(h->rr <= diverge * diverge * h->bb)) break;
+      if (h->done && h->breakdown && !(h->rr <= h->tol2)) {
+        if (++*restarts > 50) break;
+        const int keep = h->it;
+        hipLaunchKernelGGL(k_zero_scal, dim3(1), dim3(64), 0, st, S);
+        init(rhs, x, false, tol);
+        hipLaunchKernelGGL(k_set_it, dim3(1), dim3(64), 0, st, S, keep);
+        CPM_LAUNCH_CHECK();
+        h = &read();
+      }
+    }
+    const bool converged = h->done && h->rr <= h->tol2;
+    if (xbest && have_best && !converged && !(h->rr <= best))
+      CPM_HIP(hipMemcpyAsync(x, xbest, vb, hipMemcpyDeviceToDevice, st));
+    else if (xbest && !have_best && !converged && x_zero && !(h->rr <= best))
+      CPM_HIP(hipMemsetAsync(x, 0, vb, st));   // nothing better than the zero start
+    return h->it;
+  }
+};
+
+// one FP64 apply into v and the FP64 residual; returns ||b - A x||, ||b||
+std::pair<double, double> residual64(const cpm_band* b, hipStream_t st, double m, double nn,
+                                     double gamma, bool tr, const double* rhs, const double* x,
+                                     double* r, double* v, double* part, Scal* S, Pinned& pin) {
+  if (tr) apply_transpose_impl<double>(b, m, nn, 1, x, v, st, nullptr, gamma);
+  else apply_impl<double>(b, m, nn, 1, x, v, st, nullptr, gamma);
+  hipLaunchKernelGGL(k_res64, dim3(red_grid(b->n)), dim3(kRedThreads), 0, st, b->n, rhs, v, r,
+                     part, S);
+  CPM_LAUNCH_CHECK();
+  CPM_HIP(hipMemcpyAsync(pin.h, S, sizeof(Scal), hipMemcpyDeviceToHost, st));
+  CPM_HIP(hipStreamSynchronize(st));
+  return {std::sqrt(pin.h->rr), std::sqrt(pin.h->bb)};
+}
+
+void solve_one(const cpm_band* b, const cpm_solve_opts& o, const double* rhs, double* x,
+               cpm_solve_stats& stt, hipStream_t st, bool tr) {
+  const int64_t n = b->n;
+  const int maxit = o.maxit > 0 ? o.maxit : 20000;
+  const int ce = o.check_every > 0 ? o.check_every : 16;
+  const double tol = o.tol > 0 ? o.tol : 1e-8;
+  const double gamma = o.gauge;
+  const bool graph = o.use_graph != 0;
+  double* r64 = (double*)band_scratch(b, 20, sizeof(double) * n);
+  double* v64 = (double*)band_scratch(b, 21, sizeof(double) * n);
+  double* part = (double*)band_scratch(b, 22, sizeof(double) * 2 * kMaxParts);
+  Scal* S = (Scal*)band_scratch(b, 23, sizeof(Scal));
+  CPM_HIP(hipMemsetAsync(S, 0, sizeof(Scal), st));
+  Pinned pin;
+  int its = 0, restarts = 0;
+  auto plain64 = [&](double tol_) {
+    Bicg<double> k(b, st, o.m, o.n, gamma, tr, 30);
+    for (int rep = 0; rep < 20 && its < maxit; ++rep) {
+      its += k.solve(rhs, x, false, tol_, maxit - its, ce, graph, &restarts);
+      auto rb = residual64(b, st, o.m, o.n, gamma, tr, rhs, x, r64, v64, part, S, pin);
+      stt.relres = rb.second > 0 ? rb.first / rb.second : 0.0;
+      ++stt.outer_iters;
+      if (trace_on())
+        std::fprintf(stderr, "[cpm] f64 pass %d relres %.3e iterations %d restarts %d\n", rep,
+                     stt.relres, its, restarts);
+      if (stt.relres <= tol) return true;
+      // the recursive residual drifted from the true one: restart
+    }
+    return false;
+  };
+  bool ok = false;
+  if (o.mode == CPM_SOLVE_F64) {
+    ok = plain64(tol);
+  } else {
+    const double itol = o.inner_tol > 0 ? o.inner_tol : 1e-2;
+    const int inner_cap = 1000;
+    Bicg<float> k(b, st, o.m, o.n, gamma, tr, 10);
+    float* r32 = (float*)band_scratch(b, 24, sizeof(float) * n);
+    float* d32 = (float*)band_scratch(b, 25, sizeof(float) * n);
+    float* dbest = (float*)band_scratch(b, 26, sizeof(float) * n);
+    double prev = HUGE_VAL;
+    int stall = 0;
+    for (int outer = 0; outer < 100; ++outer) {
+      auto rb = residual64(b, st, o.m, o.n, gamma, tr, rhs, x, r64, v64, part, S, pin);
+      const double rel = rb.second > 0 ? rb.first / rb.second : 0.0;
+      stt.relres = rel;
+      if (rel <= tol || rb.second == 0.0) {
+        ok = true;
+        break;
+      }
+      if (its >= maxit) break;
+      if (rel > 0.5 * prev) ++stall;
+      else stall = 0;
+      if (stall >= 2 || !__builtin_isfinite(rel)) {
+        stt.fallback_f64 = 1;
+        ok = plain64(tol);
+        break;
+      }
+      prev = rel;
+      hipLaunchKernelGGL(k_to32, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, n, r64, r32, d32,
+                         1.0 / rb.first);
+      CPM_LAUNCH_CHECK();
+      const int inner = k.solve(r32, d32, true, itol, std::min(inner_cap, maxit - its), ce, graph,
+                                &restarts, dbest, 1e3);
+      its += inner;
+      if (trace_on()) {
+        const Scal& h = k.read();
+        std::fprintf(stderr, "[cpm] outer %d relres %.3e inner its %d inner rr %.3e done %d "
+                     "breakdown %d restarts %d\n", outer, rel, inner, h.rr, h.done, h.breakdown,
+                     restarts);
+      }
+      hipLaunchKernelGGL(k_add32, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, n, x, d32,
+                         rb.first);
+      CPM_LAUNCH_CHECK();
+      ++stt.outer_iters;
+    }
+  }
+  stt.krylov_iters += its;
+  stt.restarts += restarts;
+  stt.converged = ok ? 1 : 0;
+}
+
+cpm_status solve_entry(const cpm_band* b, const cpm_solve_opts* o, int nrhs, const double* rhs,
+                       double* x, cpm_solve_stats* stats, void* hip_stream, bool tr) {
+  cpm_status ret = CPM_OK;
+  cpm_status g = guard([&] {
+    if (!b || !o || !rhs || !x || nrhs < 1) CPM_FAIL(CPM_E_INVALID, "bad argument");
+    if (o->mode != CPM_SOLVE_MIXED && o->mode != CPM_SOLVE_F64)
+      CPM_FAIL(CPM_E_INVALID, "unknown solve mode %d", o->mode);
+    if (tr && o->gauge != 0.0) CPM_FAIL(CPM_E_INVALID, "the gauge is not supported for the adjoint");
+    const auto t0 = Clock::now();
+    hipStream_t caller = (hipStream_t)hip_stream;
+    // the solve is host-synchronous; it runs on a private stream so that its
+    // iterations can be captured into a graph even when the caller passes the
+    // null stream
+    CPM_HIP(hipStreamSynchronize(caller));
+    hipStream_t st = nullptr;
+    CPM_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    struct StreamGuard {
+      hipStream_t s;
+      ~StreamGuard() { (void)hipStreamSynchronize(s); (void)hipStreamDestroy(s); }
+    } sg{st};
+    cpm_solve_stats agg{};
+    agg.converged = 1;
+    double worst = 0.0;
+    for (int r = 0; r < nrhs; ++r) {
+      cpm_solve_stats s1{};
+      solve_one(b, *o, rhs + (int64_t)r * b->n, x + (int64_t)r * b->n, s1, st, tr);
+      agg.converged &= s1.converged;
+      agg.outer_iters += s1.outer_iters;
+      agg.krylov_iters += s1.krylov_iters;
+      agg.restarts += s1.restarts;
+      agg.fallback_f64 |= s1.fallback_f64;
+      worst = std::max(worst, s1.relres);
+    }
+    agg.relres = worst;
+    CPM_HIP(hipStreamSynchronize(st));
+    agg.time_ms = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+    if (stats) *stats = agg;
+    if (!agg.converged) {
+      set_error("solve did not reach tol %.3g: relative residual %.3g after %d iterations",
+                o->tol, worst, agg.krylov_iters);
+      ret = CPM_E_NOCONV;
+    }
+  });
+  return g != CPM_OK ? g : ret;
+}
+
+}  // namespace
+}  // namespace cpm
+
+using namespace cpm;
+
+extern "C" cpm_status cpm_solve(const cpm_band* b, const cpm_solve_opts* o, int nrhs,
+                                const double* rhs, double* x, cpm_solve_stats* stats,
+                                void* hip_stream) {
+  return solve_entry(b, o, nrhs, rhs, x, stats, hip_stream, false);
+}
+
+extern "C" cpm_status cpm_solve_adjoint(const cpm_band* b, const cpm_solve_opts* o, int nrhs,
+                                        const double* rhs, double* lambda,
+                                        cpm_solve_stats* stats, void* hip_stream) {
+  return solve_entry(b, o, nrhs, rhs, lambda, stats, hip_stream, true);
+}

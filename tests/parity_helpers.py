@@ -1,0 +1,64 @@
+"""Mapping between the HIP library's DOF order (block order) and the oracle's
+(lexicographic) through exported grid coordinates, and the configurations
+shared by the GPU parity tests."""
+
+import numpy as np
+
+from oracle import geometry as G
+from oracle import operator as O
+
+
+def oracle_and_gpu(cfg, N, order=2):
+    """Build the oracle system and the GPU band for a named configuration."""
+    from paper_2305_04711_amd import cpm
+    if cfg == "circle_point":
+        S = G.Circle()
+        Cs = [G.PointC((1.0, 0.0), (0.0, 1.0))]
+        gs, gi = cpm.circle(), [cpm.point_ibc((1.0, 0.0), (0.0, 1.0))]
+    elif cfg == "circle_jump":
+        thc = 1.022 * np.pi
+        p = (np.cos(thc), np.sin(thc))
+        S = G.Circle()
+        Cs = [G.PointC(p, (-p[1], p[0]))]
+        gs, gi = cpm.circle(), [cpm.point_ibc(p, (-p[1], p[0]))]
+    elif cfg == "sphere":
+        S, Cs = G.Sphere(), []
+        gs, gi = cpm.sphere(), []
+    elif cfg == "sphere_lat":
+        S = G.Sphere()
+        Cs = [G.LatitudeC(S, 0.3)]
+        gs, gi = cpm.sphere(), [cpm.latitude_ibc(0.3)]
+    elif cfg == "torus":
+        S, Cs = G.Torus(1.0, 0.4), []
+        gs, gi = cpm.torus(1.0, 0.4), []
+    elif cfg == "torus_meridians":
+        S = G.Torus(1.0, 0.4)
+        Cs = [G.MeridianC(S, 1.0, 0.0), G.MeridianC(S, -1.0, 0.0)]
+        gs, gi = cpm.torus(1.0, 0.4), [cpm.meridian_ibc(1.0, 0.0), cpm.meridian_ibc(-1.0, 0.0)]
+    else:
+        raise KeyError(cfg)
+    sysm = O.CPMSystem(S, N, Cs, order=order)
+    band = cpm.Band(gs, gi, N, order=order)
+    return sysm, band
+
+
+def dof_map(sysm, band):
+    """g2o[i] = oracle DOF of GPU DOF i (PDE and BC)."""
+    K = band.coords().astype(np.int64)
+    pde = sysm.index(K)
+    assert np.all(pde >= 0), "GPU band node missing from the oracle band"
+    g2o = np.empty(band.n, dtype=np.int64)
+    g2o[:band.n_s] = pde
+    if band.n_c:
+        node = band.bc_node()
+        curve = band.bc_curve()
+        onode = pde[node]
+        bc = np.array([sysm.alpha_of[c][j] for c, j in zip(curve, onode)], dtype=np.int64)
+        assert np.all(bc >= 0), "GPU BC DOF at a node without an oracle BC DOF"
+        g2o[band.n_s:] = bc
+    assert np.unique(g2o).size == band.n
+    return g2o
+
+
+def to_gpu_order(x_oracle, g2o):
+    return np.asarray(x_oracle)[..., g2o]

@@ -1,0 +1,220 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on the same
+seeded inputs: band sets and stencil indices bit for bit, the operator, its
+transpose, the right-hand side and the solves element by element."""
+
+import numpy as np
+import pytest
+
+from oracle import adjoint as AD
+from oracle import krylov as KR
+from paper_2305_04711_amd import inputs
+from parity_helpers import dof_map, oracle_and_gpu
+
+pytestmark = pytest.mark.gpu
+
+CASES = [("circle_point", 32), ("circle_jump", 64), ("sphere", 16), ("sphere_lat", 16),
+         ("sphere_lat", 27), ("torus", 12), ("torus_meridians", 16)]
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+_cache = {}
+
+
+def _pair(cfg, N, order=2):
+    key = (cfg, N, order)
+    if key not in _cache:
+        sysm, band = oracle_and_gpu(cfg, N, order)
+        _cache[key] = (sysm, band, dof_map(sysm, band))
+    return _cache[key]
+
+
+@pytest.mark.parametrize("cfg,N", CASES)
+def test_band_sets_and_closest_points_bit_exact(torch_cuda, cfg, N):
+    sysm, band, g2o = _pair(cfg, N)
+    print("case", cfg, N, "n_s", band.n_s, "n_c", band.n_c, flush=True)
+    assert band.n_s == sysm.n_s and band.n_c == sysm.n_c
+    K = band.coords().astype(np.int64)
+    assert set(map(tuple, K.tolist())) == set(map(tuple, sysm.K.tolist()))
+    # stored cp_S: same FP64 formula in the same order -> identical bits
+    assert np.array_equal(band.cp().view(np.uint64), sysm.CP[g2o[:band.n_s]].view(np.uint64))
+    if band.n_c:
+        assert np.array_equal(band.bc_cpc().view(np.uint64),
+                              sysm.bc_cpc[g2o[band.n_s:] - sysm.n_s].view(np.uint64))
+        assert np.array_equal(band.bc_side(), sysm.bc_side[g2o[band.n_s:] - sysm.n_s])
+        assert band.info["on_c_nodes"] == sysm.counters["on_c_nodes"]
+    assert band.info["no_bc_dof_swaps"] == sysm.counters["no_bc_dof_swaps"]
+
+
+def _pattern(rows, cols, n):
+    import scipy.sparse as sp
+    P = sp.csr_matrix((np.ones(rows.size), (rows, cols)), shape=(n, n))
+    P.sum_duplicates()
+    P.data[:] = 1.0
+    return P
+
+
+@pytest.mark.parametrize("cfg,N", CASES)
+def test_stencil_indices_bit_exact(torch_cuda, cfg, N):
+    sysm, band, g2o = _pair(cfg, N)
+    n = band.n
+    # E: every GPU row's member columns (after swaps) map to the oracle's
+    ec = band.ecols()
+    r, o = np.nonzero(ec >= 0)
+    Pg = _pattern(g2o[r], g2o[ec[r, o]], n)
+    E = sysm.E.tocoo()
+    Po = _pattern(E.row, E.col, n)
+    D = Pg - Po
+    D.eliminate_zeros()
+    assert D.nnz == 0, "E patterns differ in %d entries" % D.nnz
+    # L off-diagonal pattern (swapped FD neighbours, BC rows)
+    lc = band.lcols()
+    r, o = np.nonzero(lc >= 0)
+    Pg = _pattern(g2o[r], g2o[lc[r, o]], n)
+    L = sysm.L_off.tocoo()
+    D = Pg - _pattern(L.row, L.col, n)
+    D.eliminate_zeros()
+    assert D.nnz == 0, "L patterns differ in %d entries" % D.nnz
+    # stencil bases of PDE rows: floor(cp N) - 1
+    base = band.bases()[:band.n_s]
+    S = sysm.CP[g2o[:band.n_s]] * float(N)
+    assert np.array_equal(base, (np.floor(S).astype(np.int64) - 1))
+
+
+@pytest.mark.parametrize("cfg,N", CASES)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_apply_matches_oracle(torch_cuda, cfg, N, dtype):
+    torch = torch_cuda
+    from paper_2305_04711_amd import cpm
+    sysm, band, g2o = _pair(cfg, N)
+    rng = np.random.default_rng(11)
+    nrhs = 3
+    U = rng.standard_normal((nrhs, sysm.n))
+    m, n = 0.7, -1.3
+    ref = np.stack([sysm.apply(U[r], m, n) for r in range(nrhs)])
+    td = torch.float64 if dtype == "f64" else torch.float32
+    u = torch.tensor(U[:, g2o], dtype=td, device="cuda").contiguous()
+    v = cpm.apply(band, u, m, n).cpu().numpy().astype(np.float64)
+    scale = np.max(np.abs(ref))
+    err = np.max(np.abs(v - ref[:, g2o])) / scale
+    tol = 1e-13 if dtype == "f64" else 2e-6
+    assert err < tol, err
+    # single right-hand side path
+    v1 = cpm.apply(band, u[1].contiguous(), m, n).cpu().numpy()
+    assert np.max(np.abs(v1 - ref[1, g2o])) / scale < tol
+
+
+@pytest.mark.parametrize("cfg,N", CASES)
+def test_apply_transpose_matches_oracle(torch_cuda, cfg, N):
+    torch = torch_cuda
+    from paper_2305_04711_amd import cpm
+    sysm, band, g2o = _pair(cfg, N)
+    rng = np.random.default_rng(12)
+    W = rng.standard_normal((2, sysm.n))
+    m, n = 0.5, -1.0
+    ref = np.stack([AD.apply_transpose(sysm, W[r], m, n) for r in range(2)])
+    for td, tol in ((torch.float64, 1e-13), (torch.float32, 2e-6)):
+        w = torch.tensor(W[:, g2o], dtype=td, device="cuda").contiguous()
+        z = cpm.apply_transpose(band, w, m, n).cpu().numpy().astype(np.float64)
+        err = np.max(np.abs(z - ref[:, g2o])) / np.max(np.abs(ref))
+        assert err < tol, (td, err)
+
+
+@pytest.mark.parametrize("cfg,N", [c for c in CASES if c[0] != "sphere" and c[0] != "torus"])
+def test_rhs_and_rhs_adjoint_match_oracle(torch_cuda, cfg, N):
+    torch = torch_cuda
+    from paper_2305_04711_amd import cpm
+    sysm, band, g2o = _pair(cfg, N)
+    rng = np.random.default_rng(13)
+    f_o = rng.standard_normal(sysm.n_s)
+    g_o = rng.standard_normal(sysm.n_c)
+    n = -1.0
+    ref = sysm.rhs(f_o, g_o, n)
+    f = torch.tensor(f_o[g2o[:band.n_s]], device="cuda")
+    g = torch.tensor(g_o[g2o[band.n_s:] - sysm.n_s], device="cuda")
+    b = cpm.rhs(band, f, g, n).cpu().numpy()
+    assert np.max(np.abs(b - ref[g2o])) <= 1e-12 * np.max(np.abs(ref))
+    lam_o = rng.standard_normal(sysm.n)
+    gf_o, gg_o = AD.rhs_gradients(sysm, lam_o, n)
+    gf, gg = cpm.rhs_adjoint(band, torch.tensor(lam_o[g2o], device="cuda"), n)
+    assert np.max(np.abs(gf.cpu().numpy() - gf_o[g2o[:band.n_s]])) <= 1e-12 * np.max(np.abs(gf_o))
+    assert np.max(np.abs(gg.cpu().numpy() - gg_o[g2o[band.n_s:] - sysm.n_s])) <= \
+        1e-12 * np.max(np.abs(gg_o))
+
+
+@pytest.mark.parametrize("mode", ["f64", "mixed"])
+@pytest.mark.parametrize("cfg,N", [("circle_point", 32), ("sphere_lat", 16), ("torus_meridians", 16)])
+def test_solve_matches_oracle(torch_cuda, cfg, N, mode):
+    torch = torch_cuda
+    from paper_2305_04711_amd import cpm
+    sysm, band, g2o = _pair(cfg, N)
+    rng = np.random.default_rng(14)
+    f_o = rng.standard_normal(sysm.n_s)
+    g_o = rng.standard_normal(sysm.n_c)
+    m, n = (0.0, -1.0) if cfg != "torus_meridians" else (1.0, -1.0)
+    b_o = sysm.rhs(f_o, g_o, n)
+    A = sysm.matrix(m, n)
+    import scipy.sparse.linalg as spl
+    x_o = spl.spsolve(A.tocsc(), b_o)
+    b = torch.tensor(b_o[g2o], device="cuda")
+    x, st = cpm.solve(band, b, m, n, tol=1e-12, mode=mode)
+    assert st["converged"] and st["relres"] <= 1e-12
+    err = np.max(np.abs(x.cpu().numpy() - x_o[g2o])) / np.max(np.abs(x_o))
+    print("solve", cfg, N, mode, st, "relLinf", err, flush=True)
+    assert err < 1e-6
+    # adjoint solve against the oracle's transpose
+    lam_o = spl.spsolve(A.T.tocsc(), b_o)
+    lam, st2 = cpm.solve_adjoint(band, b, m, n, tol=1e-12, mode=mode)
+    assert st2["converged"]
+    err2 = np.max(np.abs(lam.cpu().numpy() - lam_o[g2o])) / np.max(np.abs(lam_o))
+    assert err2 < 1e-6, err2
+
+
+def test_gauged_sphere_poisson_matches_oracle(torch_cuda):
+    torch = torch_cuda
+    from paper_2305_04711_amd import cpm
+    sysm, band, g2o = _pair("sphere", 16)
+    co = inputs.sphere_coeffs(1)
+    f_o = inputs.sphere_field(co, sysm.CP)
+    b_o = sysm.rhs(f_o, None, -1.0)
+    mv = KR.gauge_matvec(lambda u: sysm.apply(u, 0.0, -1.0), sysm.n_s, 256.0)
+    x_o, info = KR.bicgstab(mv, b_o, tol=1e-13)
+    assert info["converged"]
+    b = torch.tensor(b_o[g2o], device="cuda")
+    for mode in ("f64", "mixed"):
+        x, st = cpm.solve(band, b, 0.0, -1.0, tol=1e-12, mode=mode, gauge=256.0)
+        err = np.max(np.abs(x.cpu().numpy() - x_o[g2o])) / np.max(np.abs(x_o))
+        assert st["converged"] and err < 1e-6, (mode, err, st)
+
+
+def test_jump_problem_on_gpu_second_order(torch_cuda):
+    torch = torch_cuda
+    from paper_2305_04711_amd import cpm
+    from closed_forms import jump_exact
+    errs = []
+    for N in (64, 128, 256):
+        sysm, band, g2o = _pair("circle_jump", N) if N == 64 else (None, None, None)
+        if band is None:
+            from parity_helpers import oracle_and_gpu as og
+            sysm, band = og("circle_jump", N)
+        thc = 1.022 * np.pi
+        cp = band.cp()
+        th = np.arctan2(cp[:, 1], cp[:, 0])
+        f = torch.tensor(2.0 * np.cos(th - thc), device="cuda")
+        g = torch.tensor(np.where(band.bc_side() > 0, 22.0, 2.0).astype(np.float64), device="cuda")
+        b = cpm.rhs(band, f, g, -1.0)
+        u, st = cpm.solve(band, b, 0.0, -1.0, tol=1e-12, mode="mixed")
+        # surface values E u + e from the GPU operator: A u with m = 0, n = 1
+        # gives D u + L_off(E u); use the oracle's E only to read E u + e
+        uo = np.empty(sysm.n)
+        uo[dof_map(sysm, band)] = u.cpu().numpy()
+        sv = sysm.surface_values(uo, np.where(sysm.bc_side > 0, 22.0, 2.0))
+        th_o = np.arctan2(sysm.CP[:, 1], sysm.CP[:, 0])
+        errs.append(np.max(np.abs(sv - jump_exact(th_o, thc))))
+    rate = np.log2(errs[0] / errs[-1]) / 2
+    assert rate > 1.7, errs
