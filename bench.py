@@ -1,0 +1,198 @@
+"""Benchmark of the CPM apply and solve on one MI355X.
+
+Workload: the torus R = 1, rho = 0.4 at h = 1/512 with two interior
+Dirichlet circles (meridians at toroidal angles 0 and pi, second order), the
+largest single-GPU configuration of the target set (34.1M PDE DOFs + 139k BC
+DOFs; its vectors and stored closest points exceed the 256 MB Infinity
+Cache, so HBM traffic is not hidden).
+
+Timed step: one FP64 application of A = m I + n [diag L + (L - diag L) E]
+(m = 0, n = -1: Poisson) to a vector resident in HBM; value = DOFs / step
+time in Gnodes/s.  Also reported on the same line: the FP32 apply rate, the
+per-phase time of the apply from HIP events on its stream, the roofline of
+the dominant kernel (the tile gather), the time to a relative residual of
+1e-8 for the mixed-precision and the plain FP64 solve, the band build time,
+and the FP64 CPU oracle timed on the host (cpu_baseline).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-solve]
+       [--no-cpu] [--N 512]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
+BYTES_PER_ROW_F64 = 40.0   # tile gather: cp_S 24 + u 8 + a 8 (FP64)
+BYTES_PER_ROW_F32 = 24.0   # tile gather: fraction 12 + base 4 + u 4 + a 4 (FP32)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(seconds=12.0):
+    """The oracle as it stands (explicit CSR E and L, four-step product) on
+    the same geometry and interior boundaries at N = 64."""
+    import numpy as np
+    from oracle import geometry as G
+    from oracle import operator as O
+    T = G.Torus(1.0, 0.4)
+    sysm = O.CPMSystem(T, 64, [G.MeridianC(T, 1.0, 0.0), G.MeridianC(T, -1.0, 0.0)])
+    u = np.random.default_rng(0).standard_normal(sysm.n)
+    sysm.apply(u, 0.0, -1.0)
+    t0 = time.perf_counter()
+    k = 0
+    while time.perf_counter() - t0 < seconds:
+        sysm.apply(u, 0.0, -1.0)
+        k += 1
+    dt = (time.perf_counter() - t0) / k
+    return {"value": sysm.n / dt / 1e9, "unit": "Gnodes/s", "cores": 1, "kind": "oracle",
+            "sample": "FP64 oracle apply (explicit CSR E, L; four-step product; numpy/scipy, "
+                      "single thread) on the same torus with the same two meridian IBCs at "
+                      "h = 1/64 (%d DOFs), %d applies over %.1f s" % (sysm.n, k, k * dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--N", type=int, default=512)
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device-to-device copy (a kernel of known "
+                         "traffic for scaling the HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2305_04711_amd import cpm, inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    N = args.N
+    m, n = 0.0, -1.0
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    band = cpm.Band(cpm.torus(1.0, 0.4), [cpm.meridian_ibc(1.0, 0.0),
+                                          cpm.meridian_ibc(-1.0, 0.0)], N, order=2)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    info = band.info
+    log("band: n_s %d n_c %d blocks %d tiles %d built in %.3f s" %
+        (band.n_s, band.n_c, info["n_blocks"], info["n_tiles"], build_s))
+
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    u64 = torch.randn(band.n, device=dev, dtype=torch.float64, generator=gen)
+    u32 = u64.float()
+    v64 = torch.empty_like(u64)
+    v32 = torch.empty_like(u32)
+    lib, h = band._lib, band.handle
+    import ctypes as C
+
+    def apply_once(u, v, code):
+        st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        r = lib.cpm_apply(h, m, n, code, 1, C.c_void_p(u.data_ptr()), C.c_void_p(v.data_ptr()), st)
+        if r != 0:
+            raise RuntimeError(lib.cpm_last_error().decode())
+
+    def timed(u, v, code):
+        for _ in range(args.warmup):
+            apply_once(u, v, code)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            apply_once(u, v, code)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / args.steps
+
+    tune64 = cpm.autotune(band, torch.float64, 1, reps=10)
+    tune32 = cpm.autotune(band, torch.float32, 1, reps=10)
+    log("autotune f64 %s, f32 %s" % (tune64, tune32))
+    dt64 = timed(u64, v64, 0)
+    dt32 = timed(u32, v32, 1)
+    ph64, _ = cpm.apply_profile(band, u64, m, n, reps=max(10, args.steps))
+    ph32, _ = cpm.apply_profile(band, u32, m, n, reps=max(10, args.steps))
+    # rows processed by the tile gather = PDE rows without swapped members
+    tile_rows = band.n_s - (info["n_erows"] - band.n_c)
+    ach64 = BYTES_PER_ROW_F64 * tile_rows / (ph64[0] * 1e-3) / 1e9
+    ach32 = BYTES_PER_ROW_F32 * tile_rows / (ph32[0] * 1e-3) / 1e9
+    log("apply f64 %.4f ms (%.2f Gnodes/s), phases %s" % (dt64 * 1e3, band.n / dt64 / 1e9, ph64))
+    log("apply f32 %.4f ms (%.2f Gnodes/s), phases %s" % (dt32 * 1e3, band.n / dt32 / 1e9, ph32))
+
+    solves = None
+    if not args.no_solve:
+        cp = band.cp()
+        f = torch.tensor(inputs.torus_field(inputs.torus_coeffs(100), cp), device=dev)
+        g = torch.tensor(inputs.meridian_dirichlet(band.bc_cpc(), seed=2), device=dev)
+        b = cpm.rhs(band, f, g, n)
+        solves = {}
+        for mode in ("mixed", "f64"):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            x, st = cpm.solve(band, b, m, n, tol=1e-8, mode=mode, raise_noconv=False)
+            torch.cuda.synchronize()
+            solves[mode] = {"seconds": time.perf_counter() - t, "converged": bool(st["converged"]),
+                            "relres": st["relres"], "krylov_iters": st["krylov_iters"],
+                            "outer_iters": st["outer_iters"],
+                            "fallback_f64": bool(st["fallback_f64"])}
+            log("solve %s: %s" % (mode, solves[mode]))
+
+    if args.calibrate_copy:
+        src = torch.ones(2 ** 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    base = None if args.no_cpu else cpu_baseline()
+    out = {
+        "metric": "Gnodes/s of CPM apply (% HBM peak) + time-to-1e-8 solve, mixed vs FP64",
+        "value": band.n / dt64 / 1e9,
+        "unit": "Gnodes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt64 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "torus R=1 rho=0.4, h=1/%d, two second-order Dirichlet meridian "
+                               "IBCs (toroidal angles 0, pi); Poisson m=0 n=-1" % N,
+                   "n_s": band.n_s, "n_c": band.n_c, "dofs": band.n},
+        "roofline": {"bound": "hbm", "kernel": "k_gather<double,3,1> (tile gather a = E u)",
+                     "achieved": ach64, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach64 / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_row": BYTES_PER_ROW_F64, "rows_per_launch": tile_rows,
+                     "launch_ms": ph64[0]},
+        "cpu_baseline": base,
+        "apply_f32": {"gnodes_per_s": band.n / dt32 / 1e9, "ms": dt32 * 1e3,
+                      "gather_gbs": ach32, "gather_frac": ach32 / HBM_PEAK_GBS},
+        "apply_phase_ms": {"f64": ph64, "f32": ph32,
+                           "order": ["tile gather", "explicit E rows", "block Laplacian",
+                                     "explicit L rows"]},
+        "time_to_1e-8": solves,
+        "autotune": {"variants": "k = 2 * xcd + pad", "f64_ms": tune64[0], "f64_best": tune64[1],
+                     "f32_ms": tune32[0], "f32_best": tune32[1]},
+        "build_band_s": build_s,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -211,6 +211,25 @@ cpm_status cpm_solve_adjoint(const cpm_band* band, const cpm_solve_opts* opts,
                              int nrhs, const double* rhs, double* lambda,
                              cpm_solve_stats* stats, void* hip_stream);
 
+/* Measurement: run cpm_apply `reps` times on hip_stream with HIP events
+ * around each of its four phases and return the mean milliseconds per call in
+ * ms[4]: [0] tile gather (a = E u for rows without swaps), [1] explicit
+ * interpolation rows, [2] block Laplacian pass, [3] explicit FD rows.
+ * Synchronises the stream.  Arguments as for cpm_apply. */
+cpm_status cpm_apply_profile(const cpm_band* band, double m, double n, int dtype,
+                             int nrhs, const void* u, void* v, int reps,
+                             void* hip_stream, double* ms);
+
+/* Autotuner: time every launch variant of cpm_apply for this band, dtype and
+ * nrhs (LDS line padding of the staged cube x XCD-aware tile order; variant
+ * k = 2 * xcd + pad) with HIP events, `reps` calls each, and keep the fastest
+ * for later calls with this dtype.  u and v are scratch device arrays
+ * [nrhs][n] of that dtype.  ms (may be NULL) receives the 4 mean times per
+ * call; *best (may be NULL) the chosen variant.  Synchronises the stream. */
+cpm_status cpm_autotune(cpm_band* band, int dtype, int nrhs, const void* u,
+                        void* v, int reps, void* hip_stream, double* ms,
+                        int* best);
+
 const char* cpm_last_error(void);
 
 #ifdef __cplusplus

@@ -63,7 +63,7 @@ class SolveStats(C.Structure):
 
 
 EXPORTED = ["cpm_build_band", "cpm_band_free", "cpm_band_query", "cpm_band_export",
-            "cpm_apply", "cpm_apply_transpose", "cpm_rhs", "cpm_rhs_adjoint", "cpm_solve",
+            "cpm_apply", "cpm_apply_profile", "cpm_autotune", "cpm_apply_transpose", "cpm_rhs", "cpm_rhs_adjoint", "cpm_solve",
             "cpm_solve_adjoint", "cpm_last_error"]
 
 _lib = None
@@ -94,6 +94,9 @@ def load(path=LIB_PATH):
     lib.cpm_band_export.argtypes = [vp, i, vp, C.c_size_t]
     lib.cpm_apply.argtypes = [vp, d, d, i, i, vp, vp, vp]
     lib.cpm_apply_transpose.argtypes = [vp, d, d, i, i, vp, vp, vp]
+    lib.cpm_apply_profile.argtypes = [vp, d, d, i, i, vp, vp, i, vp, C.POINTER(C.c_double)]
+    lib.cpm_autotune.argtypes = [vp, i, i, vp, vp, i, vp, C.POINTER(C.c_double),
+                                 C.POINTER(C.c_int)]
     lib.cpm_rhs.argtypes = [vp, d, i, vp, vp, vp, vp]
     lib.cpm_rhs_adjoint.argtypes = [vp, d, i, vp, vp, vp, vp]
     lib.cpm_solve.argtypes = [vp, C.POINTER(SolveOpts), i, vp, vp, C.POINTER(SolveStats), vp]

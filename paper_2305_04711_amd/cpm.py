@@ -159,6 +159,31 @@ def apply(band, u, m, n):
 apply_cpm = apply
 
 
+def apply_profile(band, u, m, n, reps=20):
+    """Mean milliseconds per phase of cpm_apply over `reps` calls, timed with
+    HIP events on the launch stream: (tile gather, explicit E rows, block
+    Laplacian, explicit L rows)."""
+    nrhs = _check_vec(band, u, band.n)
+    v = torch.empty_like(u)
+    ms = (C.c_double * 4)()
+    capi.check(band._lib.cpm_apply_profile(band.handle, float(m), float(n), _dtype_code(u), nrhs,
+                                           _ptr(u), _ptr(v), int(reps), _stream(), ms))
+    return list(ms), v
+
+
+def autotune(band, dtype=torch.float64, nrhs=1, reps=10):
+    """Pick the fastest apply launch variant for this band and dtype (kept in
+    the band).  Returns (times_ms[4], best): variant k = 2 * xcd + pad."""
+    shape = (band.n,) if nrhs == 1 else (nrhs, band.n)
+    u = torch.randn(shape, dtype=dtype, device="cuda")
+    v = torch.empty_like(u)
+    ms = (C.c_double * 4)()
+    best = C.c_int()
+    capi.check(band._lib.cpm_autotune(band.handle, _dtype_code(u), nrhs, _ptr(u), _ptr(v),
+                                      int(reps), _stream(), ms, C.byref(best)))
+    return list(ms), best.value
+
+
 def apply_transpose(band, w, m, n):
     nrhs = _check_vec(band, w, band.n)
     z = torch.empty_like(w)

@@ -21,11 +21,28 @@ struct BlockView {
   const int* off;
   const int* nbr;
   const unsigned long long* lrow_mask;
+  const QMeta* face;
   int nb;
 };
 
 static BlockView bview(const cpm_band* b) {
-  return BlockView{b->blk_mask, b->blk_off, b->blk_nbr, b->lrow_mask, b->nb};
+  return BlockView{b->blk_mask, b->blk_off, b->blk_nbr, b->lrow_mask, b->blk_face, b->nb};
+}
+
+// Wave-uniform broadcast of lane k (k must be the same in every lane).
+__device__ __forceinline__ int lane_i32(int v, int k) { return __builtin_amdgcn_readlane(v, k); }
+__device__ __forceinline__ unsigned long long lane_u64(unsigned long long v, int k) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, k);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), k);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Workgroups are dispatched to the 8 XCDs round robin; this bijection on
+// [0, g) gives each XCD a contiguous range of work items so that neighbouring
+// tiles, which stage the same blocks, share one L2.
+__device__ __forceinline__ int xcd_remap(int b, int g) {
+  const int q = g >> 3, r = g & 7, x = b & 7, k = b >> 3;
+  return x * q + (x < r ? x : r) + k;
 }
 
 template <int DIM>
@@ -42,6 +59,7 @@ __device__ __forceinline__ int nbr_dof(const BlockView& B, int blk, int mx, int 
 }
 
 struct TileView {
+  const QMeta* meta;
   const int* tile_blk;
   const int* tile_start;
   const int* perm;
@@ -52,8 +70,8 @@ struct TileView {
 };
 
 static TileView tview(const cpm_band* b) {
-  return TileView{b->tile_blk, b->tile_start, b->perm, b->cp_perm, b->frac32, b->lbase,
-                  b->n_tile_rows};
+  return TileView{b->tile_meta, b->tile_blk, b->tile_start, b->perm, b->cp_perm, b->frac32,
+                  b->lbase, b->n_tile_rows};
 }
 
 template <int DIM> struct Cube {
@@ -128,21 +146,42 @@ __device__ __forceinline__ void row_stencil<float, 2>(const TileView& tv, int po
 }
 
 // ---------------------------------------------------------------- pass 1
-template <class T, int DIM, int NR>
-__global__ __launch_bounds__(256) void k_gather(BlockView B, TileView tv, int N, const T* __restrict__ u,
-                                                T* __restrict__ a, int64_t ld) {
-  constexpr int CS = Cube<DIM>::SIZE, E = Cube<DIM>::E;
+// One wavefront per tile: stage the (2 BX)^d cube of u into LDS (x lines
+// padded by PAD elements to spread LDS banks), then each lane interpolates
+// rows of the tile (sum-factorised tensor product).  The staged blocks' masks
+// and first DOFs come from the tile's metadata in one load.
+template <class T, int DIM, int NR, int PAD>
+__global__ __launch_bounds__(64) void k_gather(BlockView B, TileView tv, int N, const T* __restrict__ u,
+                                               T* __restrict__ a, int64_t ld, int xcd) {
+  using G = Geo<DIM>;
+  constexpr int E = Cube<DIM>::E, EP = E + PAD, NQ = 1 << DIM;
+  constexpr int CS = DIM == 3 ? E * E * EP : E * EP;
   __shared__ T s_u[NR][CS];
-  const int t = blockIdx.x;
-  const int tb = tv.tile_blk[t];
-  for (int idx = threadIdx.x; idx < CS; idx += blockDim.x) {
-    int dof, ci;
-    cube_index<T, DIM>(B, tb, idx, dof, ci);
-    for (int r = 0; r < NR; ++r) s_u[r][ci] = dof >= 0 ? u[r * ld + dof] : T(0);
+  const int t = xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int lane = threadIdx.x;
+  unsigned long long qm = 0ull;
+  int qoff = 0;
+  if (lane < NQ) {
+    const QMeta q = tv.meta[(int64_t)t * 8 + lane];
+    qm = q.mask;
+    qoff = q.off;
+  }
+  const int cx0 = G::lx(lane), cy0 = G::ly(lane), cz0 = G::lz(lane);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const unsigned long long m = lane_u64(qm, q);
+    const int off = lane_i32(qoff, q);
+    const int qx = q & 1, qy = (q >> 1) & 1, qz = DIM == 3 ? (q >> 2) : 0;
+    const int cx = qx * G::BX + cx0, cy = qy * G::BX + cy0, cz = qz * G::BX + cz0;
+    const int ci = DIM == 3 ? (cz * E + cy) * EP + cx : cy * EP + cx;
+    const bool on = (m >> lane) & 1ull;
+    const int dof = off + __popcll(m & ((1ull << lane) - 1ull));
+#pragma unroll
+    for (int r = 0; r < NR; ++r) s_u[r][ci] = on ? u[r * ld + dof] : T(0);
   }
   __syncthreads();
   const int end = tv.tile_start[t + 1];
-  for (int pos = tv.tile_start[t] + threadIdx.x; pos < end; pos += blockDim.x) {
+  for (int pos = tv.tile_start[t] + lane; pos < end; pos += 64) {
     int lb[3];
     T tt[3];
     row_stencil<T, DIM>(tv, pos, N, lb, tt);
@@ -151,27 +190,32 @@ __global__ __launch_bounds__(256) void k_gather(BlockView B, TileView tv, int N,
     lagrange4<T>(tt[1], wy);
     if (DIM == 3) lagrange4<T>(tt[2], wz);
     T acc[NR];
+#pragma unroll
     for (int r = 0; r < NR; ++r) acc[r] = T(0);
     if (DIM == 3) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         T accz[NR];
+#pragma unroll
         for (int r = 0; r < NR; ++r) accz[r] = T(0);
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-          const int base = ((lb[2] + c) * E + (lb[1] + b)) * E + lb[0];
+          const int base = ((lb[2] + c) * E + (lb[1] + b)) * EP + lb[0];
+#pragma unroll
           for (int r = 0; r < NR; ++r) {
             const T* row = &s_u[r][base];
             const T x = wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2] + wx[3] * row[3];
             accz[r] += wy[b] * x;
           }
         }
+#pragma unroll
         for (int r = 0; r < NR; ++r) acc[r] += wz[c] * accz[r];
       }
     } else {
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        const int base = (lb[1] + b) * E + lb[0];
+        const int base = (lb[1] + b) * EP + lb[0];
+#pragma unroll
         for (int r = 0; r < NR; ++r) {
           const T* row = &s_u[r][base];
           const T x = wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2] + wx[3] * row[3];
@@ -180,61 +224,95 @@ __global__ __launch_bounds__(256) void k_gather(BlockView B, TileView tv, int N,
       }
     }
     const int dof = tv.perm[pos];
+#pragma unroll
     for (int r = 0; r < NR; ++r) a[r * ld + dof] = acc[r];
   }
 }
 
-// Explicit interpolation rows: a[id] = sum_o w_o u[col_o].
 template <class T>
-__global__ void k_gather_rows(int nrows, int nm, const int* __restrict__ row_id,
-                              const int* __restrict__ col, const T* __restrict__ w,
-                              const T* __restrict__ u, T* __restrict__ a, int64_t ld, int nrhs) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nrows) return;
-  const int id = row_id[i];
+__device__ __forceinline__ T wave_sum(T v, int width) {
+  for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, width);
+  return v;
+}
+
+// Explicit interpolation rows: a[id] = sum_o w_o u[col_o]; nm lanes per row
+// (nm = 4^d: a wavefront in 3-D, a quarter wavefront in 2-D), lane = member.
+template <class T>
+__global__ __launch_bounds__(256) void k_gather_rows(int nrows, int nm, const int* __restrict__ row_id,
+                                                     const int* __restrict__ col,
+                                                     const T* __restrict__ w, const T* __restrict__ u,
+                                                     T* __restrict__ a, int64_t ld, int nrhs) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = g / nm;
+  const int o = (int)(g % nm);
+  const bool live = i < nrows;
+  const int c = live ? col[i * nm + o] : -1;
+  const T wt = live ? w[i * nm + o] : T(0);
   for (int r = 0; r < nrhs; ++r) {
-    T acc = T(0);
-    for (int o = 0; o < nm; ++o) {
-      const int c = col[(int64_t)i * nm + o];
-      if (c >= 0) acc += w[(int64_t)i * nm + o] * u[r * ld + c];
-    }
-    a[r * ld + id] = acc;
+    T v = c >= 0 ? wt * u[r * ld + c] : T(0);
+    v = wave_sum(v, nm);
+    if (live && o == 0) a[r * ld + row_id[i]] = v;
   }
 }
 
 // ---------------------------------------------------------------- pass 2
 // v = cd u + co sum_nbr a (+ gauge), one wavefront per block, lane = slot.
-// ALL = false skips rows with explicit FD stencils; ALL = true (transpose)
-// visits every PDE row.
+// Lanes 0..7 load the block's metadata (its own and its face neighbours'
+// masks and first DOFs, and the explicit-row mask), broadcast with readlane,
+// so each lane finds its neighbours' DOFs by arithmetic.  ALL = false skips
+// rows with explicit FD stencils; ALL = true (transpose) visits every PDE row.
 template <class T, int DIM, bool ALL>
 __global__ __launch_bounds__(256) void k_lap(BlockView B, const T* __restrict__ u,
                                              const T* __restrict__ a, T* __restrict__ v,
                                              int64_t ld, int nrhs, T cd, T co,
-                                             const double* __restrict__ gsum, double gscale) {
+                                             const double* __restrict__ gsum, double gscale,
+                                             int xcd) {
   using G = Geo<DIM>;
-  const int blk = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int wg = xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int blk = wg * 4 + (threadIdx.x >> 6);
   const int slot = threadIdx.x & 63;
   if (blk >= B.nb) return;
-  const unsigned long long m = B.mask[blk];
+  unsigned long long lm = 0ull;
+  int loff = 0;
+  if (slot < 8) {
+    const QMeta q = B.face[(int64_t)blk * 8 + slot];
+    lm = q.mask;
+    loff = q.off;
+  }
+  const unsigned long long m = lane_u64(lm, 0);
+  const int off0 = lane_i32(loff, 0);
+  const unsigned long long xm = lane_u64(lm, 7);
+  unsigned long long fm[2 * DIM];
+  int fo[2 * DIM];
+#pragma unroll
+  for (int f = 0; f < 2 * DIM; ++f) {
+    fm[f] = lane_u64(lm, f + 1);
+    fo[f] = lane_i32(loff, f + 1);
+  }
   if (!((m >> slot) & 1ull)) return;
-  if (!ALL && ((B.lrow_mask[blk] >> slot) & 1ull)) return;
-  const int dof = B.off[blk] + __popcll(m & ((1ull << slot) - 1ull));
+  if (!ALL && ((xm >> slot) & 1ull)) return;
+  const int dof = off0 + __popcll(m & ((1ull << slot) - 1ull));
   int nd[2 * DIM];
   const int l[3] = {G::lx(slot), G::ly(slot), G::lz(slot)};
 #pragma unroll
   for (int f = 0; f < 2 * DIM; ++f) {
     int q[3] = {l[0], l[1], l[2]};
     q[f >> 1] += (f & 1) ? 1 : -1;
-    nd[f] = nbr_dof<DIM>(B, blk, q[0], q[1], q[2]);
+    const bool out = q[f >> 1] < 0 || q[f >> 1] >= G::BX;
+    q[f >> 1] &= G::BX - 1;
+    const int s2 = G::slot(q[0], q[1], q[2]);
+    const unsigned long long mm = out ? fm[f] : m;
+    const int oo = out ? fo[f] : off0;
+    nd[f] = ((mm >> s2) & 1ull) ? oo + __popcll(mm & ((1ull << s2) - 1ull)) : -1;
   }
   for (int r = 0; r < nrhs; ++r) {
     T s = T(0);
 #pragma unroll
     for (int f = 0; f < 2 * DIM; ++f)
       if (nd[f] >= 0) s += a[r * ld + nd[f]];
-    T out = cd * u[r * ld + dof] + co * s;
-    if (gsum) out += (T)(gscale * gsum[r]);
-    v[r * ld + dof] = out;
+    T o = cd * u[r * ld + dof] + co * s;
+    if (gsum) o += (T)(gscale * gsum[r]);
+    v[r * ld + dof] = o;
   }
 }
 
@@ -339,19 +417,22 @@ __global__ __launch_bounds__(256) void k_gather_T(BlockView B, TileView tv, int 
 }
 
 template <class T>
-__global__ void k_gather_rows_T(int nrows, int nm, const int* __restrict__ row_id,
-                                const int* __restrict__ col, const T* __restrict__ w,
-                                const T* __restrict__ c, T* __restrict__ z, int64_t ld, int nrhs) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_gather_rows_T(int nrows, int nm, const int* __restrict__ row_id,
+                                                       const int* __restrict__ col,
+                                                       const T* __restrict__ w,
+                                                       const T* __restrict__ c, T* __restrict__ z,
+                                                       int64_t ld, int nrhs) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = g / nm;
+  const int o = (int)(g % nm);
   if (i >= nrows) return;
+  const int cc = col[i * nm + o];
+  if (cc < 0) return;
+  const T wt = w[i * nm + o];
   const int id = row_id[i];
   for (int r = 0; r < nrhs; ++r) {
     const T ci = c[r * ld + id];
-    if (ci == T(0)) continue;
-    for (int o = 0; o < nm; ++o) {
-      const int cc = col[(int64_t)i * nm + o];
-      if (cc >= 0) atomic_add(&z[r * ld + cc], w[(int64_t)i * nm + o] * ci);
-    }
+    if (ci != T(0)) atomic_add(&z[r * ld + cc], wt * ci);
   }
 }
 
@@ -465,8 +546,27 @@ const double* ew_of<double>(const cpm_band* b) { return b->ew; }
 template <>
 const float* ew_of<float>(const cpm_band* b) { return b->ew32; }
 
+template <class T>
+static const Tune& tune_of(const cpm_band* b) {
+  return b->tune[sizeof(T) == 8 ? 0 : 1];
+}
+
+template <class T, int DIM, int PAD>
+static void launch_gather_k(const cpm_band* b, int k, const T* ur, T* ar, int64_t ld, int xcd,
+                            hipStream_t st) {
+  const dim3 g(b->ntiles), t(64);
+  switch (k) {
+    case 1: hipLaunchKernelGGL((k_gather<T, DIM, 1, PAD>), g, t, 0, st, bview(b), tview(b), b->N, ur, ar, ld, xcd); break;
+    case 2: hipLaunchKernelGGL((k_gather<T, DIM, 2, PAD>), g, t, 0, st, bview(b), tview(b), b->N, ur, ar, ld, xcd); break;
+    case 3: hipLaunchKernelGGL((k_gather<T, DIM, 3, PAD>), g, t, 0, st, bview(b), tview(b), b->N, ur, ar, ld, xcd); break;
+    default: hipLaunchKernelGGL((k_gather<T, DIM, 4, PAD>), g, t, 0, st, bview(b), tview(b), b->N, ur, ar, ld, xcd); break;
+  }
+  CPM_LAUNCH_CHECK();
+}
+
 template <class T, int DIM>
-static void launch_gather(const cpm_band* b, int nrhs, const T* u, T* a, hipStream_t st) {
+static void launch_gather(const cpm_band* b, int nrhs, const T* u, T* a, hipStream_t st,
+                          hipEvent_t* ev = nullptr) {
   const int64_t ld = b->n;
   int r = 0;
   while (r < nrhs) {
@@ -474,43 +574,45 @@ static void launch_gather(const cpm_band* b, int nrhs, const T* u, T* a, hipStre
     const T* ur = u + r * ld;
     T* ar = a + r * ld;
     if (b->ntiles) {
-      switch (k) {
-        case 1: hipLaunchKernelGGL((k_gather<T, DIM, 1>), dim3(b->ntiles), dim3(256), 0, st, bview(b), tview(b), b->N, ur, ar, ld); break;
-        case 2: hipLaunchKernelGGL((k_gather<T, DIM, 2>), dim3(b->ntiles), dim3(256), 0, st, bview(b), tview(b), b->N, ur, ar, ld); break;
-        case 3: hipLaunchKernelGGL((k_gather<T, DIM, 3>), dim3(b->ntiles), dim3(256), 0, st, bview(b), tview(b), b->N, ur, ar, ld); break;
-        default: hipLaunchKernelGGL((k_gather<T, DIM, 4>), dim3(b->ntiles), dim3(256), 0, st, bview(b), tview(b), b->N, ur, ar, ld); break;
-      }
-      CPM_LAUNCH_CHECK();
+      const Tune& tn = tune_of<T>(b);
+      if (tn.pad) launch_gather_k<T, DIM, 1>(b, k, ur, ar, ld, tn.xcd, st);
+      else launch_gather_k<T, DIM, 0>(b, k, ur, ar, ld, tn.xcd, st);
     }
     r += k;
   }
+  if (ev) CPM_HIP(hipEventRecord(ev[1], st));
   if (b->n_erows) {
     const int nm = DIM == 3 ? 64 : 16;
-    hipLaunchKernelGGL(k_gather_rows<T>, dim3(grid_for(b->n_erows, 128)), dim3(128), 0, st,
-                       b->n_erows, nm, b->erow_id, b->ecol, ew_of<T>(b), u, a, ld, nrhs);
+    hipLaunchKernelGGL(k_gather_rows<T>, dim3(grid_for((int64_t)b->n_erows * nm, 256)), dim3(256),
+                       0, st, b->n_erows, nm, b->erow_id, b->ecol, ew_of<T>(b), u, a, ld, nrhs);
     CPM_LAUNCH_CHECK();
   }
+  if (ev) CPM_HIP(hipEventRecord(ev[2], st));
 }
 
+// ev (optional): five events recorded between the four phases.
 template <class T, int DIM>
 static void apply_dim(const cpm_band* b, double m, double n, int nrhs, const T* u, T* v,
-                      hipStream_t st, const double* gsum, double gamma) {
+                      hipStream_t st, const double* gsum, double gamma, hipEvent_t* ev = nullptr) {
   const int64_t ld = b->n;
   T* a = static_cast<T*>(band_scratch(b, 0, sizeof(T) * (size_t)ld * nrhs));
-  launch_gather<T, DIM>(b, nrhs, u, a, st);
+  if (ev) CPM_HIP(hipEventRecord(ev[0], st));
+  launch_gather<T, DIM>(b, nrhs, u, a, st, ev);
   const double N2 = (double)b->N * (double)b->N;
   const T cd = (T)(m + n * (-2.0 * DIM * N2));
   const T co = (T)(n * N2);
   const double gscale = gsum ? gamma / (double)b->n_s : 0.0;
   hipLaunchKernelGGL((k_lap<T, DIM, false>), dim3((b->nb + 3) / 4), dim3(256), 0, st, bview(b), u,
-                     a, v, ld, nrhs, cd, co, gsum, gscale);
+                     a, v, ld, nrhs, cd, co, gsum, gscale, tune_of<T>(b).xcd);
   CPM_LAUNCH_CHECK();
+  if (ev) CPM_HIP(hipEventRecord(ev[3], st));
   if (b->n_lrows) {
     hipLaunchKernelGGL(k_lap_rows<T>, dim3(grid_for(b->n_lrows, 128)), dim3(128), 0, st,
                        b->n_lrows, 2 * DIM, b->lrow_id, b->lcol, u, a, v, ld, nrhs, cd, co, gsum,
                        gscale);
     CPM_LAUNCH_CHECK();
   }
+  if (ev) CPM_HIP(hipEventRecord(ev[4], st));
 }
 
 template <class T>
@@ -544,7 +646,7 @@ static void apply_T_dim(const cpm_band* b, double m, double n, int nrhs, const T
   // (fill kernels, not memsets: this sequence may be captured into a graph)
   hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(ld * nrhs, 256, 4096)), dim3(256), 0, st, c, ld * nrhs, T(0));
   hipLaunchKernelGGL((k_lap<T, DIM, true>), dim3((b->nb + 3) / 4), dim3(256), 0, st, bview(b), w,
-                     w, c, ld, nrhs, T(0), co, nullptr, 0.0);
+                     w, c, ld, nrhs, T(0), co, nullptr, 0.0, tune_of<T>(b).xcd);
   CPM_LAUNCH_CHECK();
   if (b->n_lrows) {
     hipLaunchKernelGGL(k_lap_rows_T<T>, dim3(grid_for(b->n_lrows, 128)), dim3(128), 0, st,
@@ -562,8 +664,9 @@ static void apply_T_dim(const cpm_band* b, double m, double n, int nrhs, const T
     }
   if (b->n_erows) {
     const int nm = DIM == 3 ? 64 : 16;
-    hipLaunchKernelGGL(k_gather_rows_T<T>, dim3(grid_for(b->n_erows, 128)), dim3(128), 0, st,
-                       b->n_erows, nm, b->erow_id, b->ecol, ew_of<T>(b), c, e, ld, nrhs);
+    hipLaunchKernelGGL(k_gather_rows_T<T>, dim3(grid_for((int64_t)b->n_erows * nm, 256)),
+                       dim3(256), 0, st, b->n_erows, nm, b->erow_id, b->ecol, ew_of<T>(b), c, e,
+                       ld, nrhs);
     CPM_LAUNCH_CHECK();
   }
   const T cd = (T)(m + n * (-2.0 * DIM * N2));
@@ -613,6 +716,89 @@ extern "C" cpm_status cpm_apply(const cpm_band* b, double m, double n, int dtype
       apply_impl<double>(b, m, n, nrhs, (const double*)u, (double*)v, st);
     else
       apply_impl<float>(b, m, n, nrhs, (const float*)u, (float*)v, st);
+  });
+}
+
+extern "C" cpm_status cpm_apply_profile(const cpm_band* b, double m, double n, int dtype,
+                                        int nrhs, const void* u, void* v, int reps,
+                                        void* hip_stream, double* ms) {
+  return guard([&] {
+    check_vec_args(b, dtype, nrhs, u, v);
+    if (reps < 1 || !ms) CPM_FAIL(CPM_E_INVALID, "reps must be >= 1 and ms non-null");
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipEvent_t ev[5];
+    for (auto& e : ev) CPM_HIP(hipEventCreate(&e));
+    double acc[4] = {0, 0, 0, 0};
+    try {
+      for (int k = 0; k < reps; ++k) {
+        if (dtype == CPM_F64) {
+          if (b->dim == 3) apply_dim<double, 3>(b, m, n, nrhs, (const double*)u, (double*)v, st, nullptr, 0.0, ev);
+          else apply_dim<double, 2>(b, m, n, nrhs, (const double*)u, (double*)v, st, nullptr, 0.0, ev);
+        } else {
+          if (b->dim == 3) apply_dim<float, 3>(b, m, n, nrhs, (const float*)u, (float*)v, st, nullptr, 0.0, ev);
+          else apply_dim<float, 2>(b, m, n, nrhs, (const float*)u, (float*)v, st, nullptr, 0.0, ev);
+        }
+        CPM_HIP(hipEventSynchronize(ev[4]));
+        for (int p = 0; p < 4; ++p) {
+          float t = 0.f;
+          CPM_HIP(hipEventElapsedTime(&t, ev[p], ev[p + 1]));
+          acc[p] += t;
+        }
+      }
+    } catch (...) {
+      for (auto& e : ev) (void)hipEventDestroy(e);
+      throw;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    for (int p = 0; p < 4; ++p) ms[p] = acc[p] / reps;
+  });
+}
+
+extern "C" cpm_status cpm_autotune(cpm_band* b, int dtype, int nrhs, const void* u, void* v,
+                                   int reps, void* hip_stream, double* ms, int* best) {
+  return guard([&] {
+    check_vec_args(b, dtype, nrhs, u, v);
+    if (reps < 1) CPM_FAIL(CPM_E_INVALID, "reps must be >= 1");
+    hipStream_t st = (hipStream_t)hip_stream;
+    Tune& tn = b->tune[dtype == CPM_F64 ? 0 : 1];
+    const Tune saved = tn;
+    hipEvent_t e0, e1;
+    CPM_HIP(hipEventCreate(&e0));
+    CPM_HIP(hipEventCreate(&e1));
+    double t[4];
+    int arg = 0;
+    try {
+      for (int k = 0; k < 4; ++k) {
+        tn.pad = k & 1;
+        tn.xcd = k >> 1;
+        auto run = [&] {
+          if (dtype == CPM_F64) apply_impl<double>(b, 0.0, -1.0, nrhs, (const double*)u, (double*)v, st);
+          else apply_impl<float>(b, 0.0, -1.0, nrhs, (const float*)u, (float*)v, st);
+        };
+        run();   // warm up
+        CPM_HIP(hipEventRecord(e0, st));
+        for (int r = 0; r < reps; ++r) run();
+        CPM_HIP(hipEventRecord(e1, st));
+        CPM_HIP(hipEventSynchronize(e1));
+        float f = 0.f;
+        CPM_HIP(hipEventElapsedTime(&f, e0, e1));
+        t[k] = f / reps;
+        if (t[k] < t[arg]) arg = k;
+      }
+    } catch (...) {
+      tn = saved;
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    tn.pad = arg & 1;
+    tn.xcd = arg >> 1;
+    tn.tuned = 1;
+    if (ms)
+      for (int k = 0; k < 4; ++k) ms[k] = t[k];
+    if (best) *best = arg;
   });
 }
 

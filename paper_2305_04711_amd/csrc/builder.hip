@@ -566,6 +566,44 @@ __global__ void k_lrow_bc(Blocks B, int64_t n_s, int64_t n_c, const int* bc_node
   }
 }
 
+// Per-tile metadata of the staged blocks and per-block Laplacian metadata.
+__global__ void k_tile_meta(Blocks B, int ntiles, int nq, int nnbr, const int* tile_blk,
+                            QMeta* meta) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (int64_t)ntiles * 8) return;
+  const int t = (int)(g >> 3), q = (int)(g & 7);
+  QMeta m{0ull, 0, -1};
+  if (q < nq) {
+    const int qx = q & 1, qy = (q >> 1) & 1, qz = q >> 2;
+    const int tb = tile_blk[t];
+    const int code = nnbr == 27 ? (qz + 1) * 9 + (qy + 1) * 3 + (qx + 1) : (qy + 1) * 3 + (qx + 1);
+    const int id = q == 0 ? tb : B.nbr[tb * nnbr + code];
+    if (id >= 0) m = QMeta{B.mask[id], B.off[id], id};
+  }
+  meta[g] = m;
+}
+
+__global__ void k_blk_face(Blocks B, int nb, int dim, int nnbr, const unsigned long long* lrow_mask,
+                           QMeta* face) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (int64_t)nb * 8) return;
+  const int i = (int)(g >> 3), k = (int)(g & 7);
+  QMeta m{0ull, 0, -1};
+  if (k == 7) {
+    m.mask = lrow_mask[i];
+  } else if (k <= 2 * dim) {
+    int id = i;
+    if (k > 0) {
+      const int f = k - 1, s1 = (f & 1) ? 1 : -1;
+      const int dx = (f >> 1) == 0 ? s1 : 0, dy = (f >> 1) == 1 ? s1 : 0, dz = (f >> 1) == 2 ? s1 : 0;
+      const int code = nnbr == 27 ? (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1) : (dy + 1) * 3 + (dx + 1);
+      id = B.nbr[i * nnbr + code];
+    }
+    if (id >= 0) m = QMeta{B.mask[id], B.off[id], id};
+  }
+  face[g] = m;
+}
+
 // ---------------------------------------------------------------- export
 template <int DIM>
 __global__ __launch_bounds__(256) void k_export_rows(Blocks B, int nb, int N, int64_t n_s,
@@ -879,6 +917,16 @@ void build(cpm_band* b, hipStream_t st) {
     CPM_LAUNCH_CHECK();
   }
   b->ecoef = b->order == 2 ? 2.0 : 1.0;
+  // metadata read by the apply kernels
+  b->tile_meta = b->alloc<QMeta>((size_t)b->ntiles * 8);
+  if (b->ntiles)
+    hipLaunchKernelGGL(k_tile_meta, dim3(grid_for((int64_t)b->ntiles * 8, 256)), dim3(256), 0, st,
+                       B, b->ntiles, 1 << DIM, G::NNBR, b->tile_blk, b->tile_meta);
+  CPM_LAUNCH_CHECK();
+  b->blk_face = b->alloc<QMeta>((size_t)nb * 8);
+  hipLaunchKernelGGL(k_blk_face, dim3(grid_for((int64_t)nb * 8, 256)), dim3(256), 0, st, B, nb,
+                     DIM, G::NNBR, b->lrow_mask, b->blk_face);
+  CPM_LAUNCH_CHECK();
   CPM_HIP(hipStreamSynchronize(st));
 }
 

@@ -78,6 +78,20 @@ template <> struct Geo<2> {
 
 struct Workspace;
 
+// Occupancy mask and first DOF of one block (mask 0 when the block is absent).
+struct QMeta {
+  unsigned long long mask;
+  int off;
+  int pad;
+};
+
+// Launch variants of the apply kernels (chosen by the autotuner).
+struct Tune {
+  int pad = 1;     // LDS line padding of the staged cube (0 or 1 elements)
+  int xcd = 1;     // map consecutive tiles / blocks to one XCD
+  int tuned = 0;
+};
+
 }  // namespace cpm
 
 // The band: everything a call needs, all arrays on the device.
@@ -96,6 +110,9 @@ struct cpm_band {
   int* blk_off = nullptr;             // [nb + 1] first PDE DOF of the block
   int* blk_nbr = nullptr;             // [nb][NNBR] neighbour block ids or -1
   unsigned long long* lrow_mask = nullptr; // [nb] slots whose L row is explicit
+  // [nb][8] per-block Laplacian metadata: entry 0 the block itself, 1..2d its
+  // face neighbours (-x,+x,-y,+y,-z,+z), 7 the explicit-row mask in .mask
+  cpm::QMeta* blk_face = nullptr;
 
   // hash table block key -> block id (open addressing)
   unsigned long long* hkeys = nullptr;
@@ -109,6 +126,7 @@ struct cpm_band {
   // the block that holds their stencil base
   int ntiles = 0, n_tile_rows = 0;
   int* tile_blk = nullptr;            // [ntiles]
+  cpm::QMeta* tile_meta = nullptr;    // [ntiles][8] the 2^d staged blocks
   int* tile_start = nullptr;          // [ntiles + 1]
   int* perm = nullptr;                // [n_tile_rows] row DOF
   double* cp_perm = nullptr;          // [dim][n_tile_rows]
@@ -140,6 +158,7 @@ struct cpm_band {
   size_t bytes = 0;
   std::vector<void*> allocs;
   cpm::Workspace* ws = nullptr;
+  cpm::Tune tune[2];                  // per dtype (0 = FP64, 1 = FP32)
 
   template <class T>
   T* alloc(size_t count) {
