@@ -251,6 +251,14 @@ def solve_adjoint(band, rhs_, m, n, tol=1e-8, mode="mixed", x0=None, maxit=0, in
                   inner_tol, check_every, use_graph, 0.0, raise_noconv)
 
 
+def _check_attained(stats, tol, what):
+    # BiCGSTAB in FP64 stagnates near relres 1e-11 on these systems; a solve
+    # that ends within 100 x tol is accepted, anything worse raises.
+    if not (stats["relres"] <= 100.0 * tol):
+        raise capi.CPMError(capi.E_NOCONV, "%s reached relative residual %.3g (tol %.3g)"
+                            % (what, stats["relres"], tol))
+
+
 class CPMSolve(torch.autograd.Function):
     """u = A^-1 b(f, g) with gradients with respect to f (n_s) and the interior
     Dirichlet values g (n_c) from the adjoint solve A^T lam = dl/du."""
@@ -258,14 +266,16 @@ class CPMSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, f, g, band, m, n, tol=1e-10, mode="mixed"):
         b = rhs(band, f.detach().contiguous(), g.detach().contiguous() if band.n_c else None, n)
-        u, _ = solve(band, b, m, n, tol=tol, mode=mode)
+        u, st = solve(band, b, m, n, tol=tol, mode=mode, raise_noconv=False)
+        _check_attained(st, tol, "forward solve")
         ctx.band, ctx.m, ctx.n, ctx.tol, ctx.mode = band, m, n, tol, mode
         return u
 
     @staticmethod
     def backward(ctx, grad_u):
         band = ctx.band
-        lam, _ = solve_adjoint(band, grad_u.contiguous().to(torch.float64), ctx.m, ctx.n,
-                               tol=ctx.tol, mode=ctx.mode)
+        lam, st = solve_adjoint(band, grad_u.contiguous().to(torch.float64), ctx.m, ctx.n,
+                                tol=ctx.tol, mode=ctx.mode, raise_noconv=False)
+        _check_attained(st, ctx.tol, "adjoint solve")
         gf, gg = rhs_adjoint(band, lam, ctx.n)
         return gf, (gg if band.n_c else None), None, None, None, None, None

@@ -256,11 +256,14 @@ __global__ __launch_bounds__(256) void k_gather_rows(int nrows, int nm, const in
 }
 
 // ---------------------------------------------------------------- pass 2
-// v = cd u + co sum_nbr a (+ gauge), one wavefront per block, lane = slot.
-// Lanes 0..7 load the block's metadata (its own and its face neighbours'
-// masks and first DOFs, and the explicit-row mask), broadcast with readlane,
-// so each lane finds its neighbours' DOFs by arithmetic.  ALL = false skips
-// rows with explicit FD stencils; ALL = true (transpose) visits every PDE row.
+// v = cd u + co sum_nbr a (+ gauge); lane = slot; each wavefront handles KB
+// consecutive blocks so that their loads are in flight together.  Lanes
+// 8j..8j+7 load block j's metadata (its own and its face neighbours' masks
+// and first DOFs, and the explicit-row mask), broadcast with readlane, so each
+// lane finds its neighbours' DOFs by arithmetic.  ALL = false skips rows with
+// explicit FD stencils; ALL = true (transpose) visits every PDE row.
+constexpr int kLapBlocksPerWave = 4;
+
 template <class T, int DIM, bool ALL>
 __global__ __launch_bounds__(256) void k_lap(BlockView B, const T* __restrict__ u,
                                              const T* __restrict__ a, T* __restrict__ v,
@@ -268,51 +271,63 @@ __global__ __launch_bounds__(256) void k_lap(BlockView B, const T* __restrict__ 
                                              const double* __restrict__ gsum, double gscale,
                                              int xcd) {
   using G = Geo<DIM>;
+  constexpr int KB = kLapBlocksPerWave;
   const int wg = xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
-  const int blk = wg * 4 + (threadIdx.x >> 6);
+  const int blk0 = (wg * 4 + (threadIdx.x >> 6)) * KB;
   const int slot = threadIdx.x & 63;
-  if (blk >= B.nb) return;
+  if (blk0 >= B.nb) return;
   unsigned long long lm = 0ull;
   int loff = 0;
-  if (slot < 8) {
-    const QMeta q = B.face[(int64_t)blk * 8 + slot];
-    lm = q.mask;
-    loff = q.off;
+  {
+    const int j = slot >> 3, e = slot & 7;
+    if (j < KB && blk0 + j < B.nb) {
+      const QMeta q = B.face[(int64_t)(blk0 + j) * 8 + e];
+      lm = q.mask;
+      loff = q.off;
+    }
   }
-  const unsigned long long m = lane_u64(lm, 0);
-  const int off0 = lane_i32(loff, 0);
-  const unsigned long long xm = lane_u64(lm, 7);
-  unsigned long long fm[2 * DIM];
-  int fo[2 * DIM];
-#pragma unroll
-  for (int f = 0; f < 2 * DIM; ++f) {
-    fm[f] = lane_u64(lm, f + 1);
-    fo[f] = lane_i32(loff, f + 1);
-  }
-  if (!((m >> slot) & 1ull)) return;
-  if (!ALL && ((xm >> slot) & 1ull)) return;
-  const int dof = off0 + __popcll(m & ((1ull << slot) - 1ull));
-  int nd[2 * DIM];
   const int l[3] = {G::lx(slot), G::ly(slot), G::lz(slot)};
+  int dof[KB];
+  int nd[KB][2 * DIM];
 #pragma unroll
-  for (int f = 0; f < 2 * DIM; ++f) {
-    int q[3] = {l[0], l[1], l[2]};
-    q[f >> 1] += (f & 1) ? 1 : -1;
-    const bool out = q[f >> 1] < 0 || q[f >> 1] >= G::BX;
-    q[f >> 1] &= G::BX - 1;
-    const int s2 = G::slot(q[0], q[1], q[2]);
-    const unsigned long long mm = out ? fm[f] : m;
-    const int oo = out ? fo[f] : off0;
-    nd[f] = ((mm >> s2) & 1ull) ? oo + __popcll(mm & ((1ull << s2) - 1ull)) : -1;
+  for (int j = 0; j < KB; ++j) {
+    const unsigned long long m = lane_u64(lm, 8 * j);
+    const int off0 = lane_i32(loff, 8 * j);
+    const unsigned long long xm = lane_u64(lm, 8 * j + 7);
+    bool on = (m >> slot) & 1ull;
+    if (!ALL && ((xm >> slot) & 1ull)) on = false;
+    dof[j] = on ? off0 + __popcll(m & ((1ull << slot) - 1ull)) : -1;
+#pragma unroll
+    for (int f = 0; f < 2 * DIM; ++f) {
+      const unsigned long long fmk = lane_u64(lm, 8 * j + f + 1);
+      const int fof = lane_i32(loff, 8 * j + f + 1);
+      int q[3] = {l[0], l[1], l[2]};
+      q[f >> 1] += (f & 1) ? 1 : -1;
+      const bool out = q[f >> 1] < 0 || q[f >> 1] >= G::BX;
+      q[f >> 1] &= G::BX - 1;
+      const int s2 = G::slot(q[0], q[1], q[2]);
+      const unsigned long long mm = out ? fmk : m;
+      const int oo = out ? fof : off0;
+      nd[j][f] = ((mm >> s2) & 1ull) ? oo + __popcll(mm & ((1ull << s2) - 1ull)) : -1;
+    }
   }
   for (int r = 0; r < nrhs; ++r) {
-    T s = T(0);
+    T out[KB];
 #pragma unroll
-    for (int f = 0; f < 2 * DIM; ++f)
-      if (nd[f] >= 0) s += a[r * ld + nd[f]];
-    T o = cd * u[r * ld + dof] + co * s;
-    if (gsum) o += (T)(gscale * gsum[r]);
-    v[r * ld + dof] = o;
+    for (int j = 0; j < KB; ++j) {
+      T s = T(0);
+#pragma unroll
+      for (int f = 0; f < 2 * DIM; ++f)
+        if (dof[j] >= 0 && nd[j][f] >= 0) s += a[r * ld + nd[j][f]];
+      out[j] = dof[j] >= 0 ? cd * u[r * ld + dof[j]] + co * s : T(0);
+    }
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      if (dof[j] < 0) continue;
+      T o = out[j];
+      if (gsum) o += (T)(gscale * gsum[r]);
+      v[r * ld + dof[j]] = o;
+    }
   }
 }
 
@@ -575,8 +590,8 @@ static void launch_gather(const cpm_band* b, int nrhs, const T* u, T* a, hipStre
     T* ar = a + r * ld;
     if (b->ntiles) {
       const Tune& tn = tune_of<T>(b);
-      if (tn.pad) launch_gather_k<T, DIM, 1>(b, k, ur, ar, ld, tn.xcd, st);
-      else launch_gather_k<T, DIM, 0>(b, k, ur, ar, ld, tn.xcd, st);
+      if (tn.pad) launch_gather_k<T, DIM, 4>(b, k, ur, ar, ld, tn.xcd, st);
+      else launch_gather_k<T, DIM, 1>(b, k, ur, ar, ld, tn.xcd, st);
     }
     r += k;
   }
@@ -602,7 +617,7 @@ static void apply_dim(const cpm_band* b, double m, double n, int nrhs, const T* 
   const T cd = (T)(m + n * (-2.0 * DIM * N2));
   const T co = (T)(n * N2);
   const double gscale = gsum ? gamma / (double)b->n_s : 0.0;
-  hipLaunchKernelGGL((k_lap<T, DIM, false>), dim3((b->nb + 3) / 4), dim3(256), 0, st, bview(b), u,
+  hipLaunchKernelGGL((k_lap<T, DIM, false>), dim3((b->nb + 4 * kLapBlocksPerWave - 1) / (4 * kLapBlocksPerWave)), dim3(256), 0, st, bview(b), u,
                      a, v, ld, nrhs, cd, co, gsum, gscale, tune_of<T>(b).xcd);
   CPM_LAUNCH_CHECK();
   if (ev) CPM_HIP(hipEventRecord(ev[3], st));
@@ -645,7 +660,7 @@ static void apply_T_dim(const cpm_band* b, double m, double n, int nrhs, const T
   // c = (L - diag L)^T w: symmetric bulk over every PDE row, then corrections
   // (fill kernels, not memsets: this sequence may be captured into a graph)
   hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(ld * nrhs, 256, 4096)), dim3(256), 0, st, c, ld * nrhs, T(0));
-  hipLaunchKernelGGL((k_lap<T, DIM, true>), dim3((b->nb + 3) / 4), dim3(256), 0, st, bview(b), w,
+  hipLaunchKernelGGL((k_lap<T, DIM, true>), dim3((b->nb + 4 * kLapBlocksPerWave - 1) / (4 * kLapBlocksPerWave)), dim3(256), 0, st, bview(b), w,
                      w, c, ld, nrhs, T(0), co, nullptr, 0.0, tune_of<T>(b).xcd);
   CPM_LAUNCH_CHECK();
   if (b->n_lrows) {

@@ -347,12 +347,20 @@ __global__ __launch_bounds__(256) void k_stencil_scan(Blocks B, int nb, int N, i
   if (!swaps && bb >= 0 && !holes) atomicAdd(&tile_cnt[bb], 1);
 }
 
+// Tile rows are ordered by their local stencil base inside the tile: rows
+// along one surface normal share cp_S, hence the base, and neighbouring lanes
+// then read identical LDS addresses (served as broadcasts).
 template <int DIM>
-__global__ __launch_bounds__(256) void k_tile_fill(Blocks B, int nb, int N, int64_t n_s,
-                                                   const double* cp, const int* eflag,
-                                                   const int* tile_blk_of, const int* tile_off,
-                                                   int* fill, int ntr, int* perm, double* cp_perm,
-                                                   float* frac32, unsigned* lbase) {
+__device__ __forceinline__ int local_base_code(const int base[3]) {
+  using G = Geo<DIM>;
+  const int lx = base[0] & (G::BX - 1), ly = base[1] & (G::BX - 1);
+  return DIM == 3 ? lx + 4 * ly + 16 * (base[2] & 3) : lx + 8 * ly;
+}
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_tile_count2(Blocks B, int nb, int N, int64_t n_s,
+                                                     const double* cp, const int* eflag,
+                                                     const int* tile_blk_of, int* cnt2) {
   NODE_PROLOGUE(DIM);
   if (eflag[dof]) return;
   const int bb = tile_blk_of[dof];
@@ -361,7 +369,24 @@ __global__ __launch_bounds__(256) void k_tile_fill(Blocks B, int nb, int N, int6
   int base[3];
   double t[3];
   stencil_base<DIM>(y, N, base, t);
-  const int pos = tile_off[bb] + atomicAdd(&fill[bb], 1);
+  atomicAdd(&cnt2[(int64_t)bb * 64 + local_base_code<DIM>(base)], 1);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_tile_fill(Blocks B, int nb, int N, int64_t n_s,
+                                                   const double* cp, const int* eflag,
+                                                   const int* tile_blk_of, int* pos2, int ntr,
+                                                   int* perm, double* cp_perm, float* frac32,
+                                                   unsigned* lbase) {
+  NODE_PROLOGUE(DIM);
+  if (eflag[dof]) return;
+  const int bb = tile_blk_of[dof];
+  if (bb < 0) return;
+  const V3 y = load_v(cp, n_s, dof, DIM);
+  int base[3];
+  double t[3];
+  stencil_base<DIM>(y, N, base, t);
+  const int pos = atomicAdd(&pos2[(int64_t)bb * 64 + local_base_code<DIM>(base)], 1);
   perm[pos] = dof;
   const double yy[3] = {y.x, y.y, y.z};
   for (int a = 0; a < DIM; ++a) {
@@ -820,9 +845,8 @@ void build(cpm_band* b, hipStream_t st) {
   const int64_t n_c = b->n_c;
 
   // ---- interpolation stencils: holes, swaps, tiles
-  Tmp<int> eflag(n_s), tile_blk_of(n_s), tile_cnt(nb), tile_off(nb), fill(nb);
+  Tmp<int> eflag(n_s), tile_blk_of(n_s), tile_cnt(nb), tile_off(nb);
   CPM_HIP(hipMemsetAsync(tile_cnt.p, 0, nb * sizeof(int), st));
-  CPM_HIP(hipMemsetAsync(fill.p, 0, nb * sizeof(int), st));
   hipLaunchKernelGGL(k_stencil_scan<DIM>, gnode, dim3(256), 0, st, B, nb, N, n_s, b->cp,
                      nib ? row_c.p : nullptr, alpha_of.p, side_v.p, eflag.p, tile_blk_of.p,
                      tile_cnt.p, counters.p);
@@ -884,9 +908,20 @@ void build(cpm_band* b, hipStream_t st) {
     b->cp_perm = b->alloc<double>((size_t)DIM * ntr);
     b->frac32 = b->alloc<float>((size_t)DIM * ntr);
     b->lbase = b->alloc<unsigned>(ntr);
-    hipLaunchKernelGGL(k_tile_fill<DIM>, gnode, dim3(256), 0, st, B, nb, N, n_s, b->cp, eflag.p,
-                       tile_blk_of.p, tile_off.p, fill.p, ntr, b->perm, b->cp_perm, b->frac32,
-                       b->lbase);
+    {
+      Tmp<int> cnt2((size_t)nb * 64), pos2((size_t)nb * 64);
+      CPM_HIP(hipMemsetAsync(cnt2.p, 0, (size_t)nb * 64 * sizeof(int), st));
+      hipLaunchKernelGGL(k_tile_count2<DIM>, gnode, dim3(256), 0, st, B, nb, N, n_s, b->cp,
+                         eflag.p, tile_blk_of.p, cnt2.p);
+      CPM_LAUNCH_CHECK();
+      const int64_t tot = scan_exclusive_i32(cnt2.p, pos2.p, (int64_t)nb * 64, st);
+      if (tot != ntr) CPM_FAIL(CPM_E_INVALID, "internal: tile row count mismatch");
+      hipLaunchKernelGGL(k_tile_fill<DIM>, gnode, dim3(256), 0, st, B, nb, N, n_s, b->cp,
+                         eflag.p, tile_blk_of.p, pos2.p, ntr, b->perm, b->cp_perm, b->frac32,
+                         b->lbase);
+      CPM_LAUNCH_CHECK();
+      CPM_HIP(hipStreamSynchronize(st));
+    }
     CPM_LAUNCH_CHECK();
   }
   // explicit L rows: swapped PDE rows then all BC rows

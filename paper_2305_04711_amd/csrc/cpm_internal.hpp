@@ -87,7 +87,7 @@ struct QMeta {
 
 // Launch variants of the apply kernels (chosen by the autotuner).
 struct Tune {
-  int pad = 1;     // LDS line padding of the staged cube (0 or 1 elements)
+  int pad = 1;     // LDS x-line stride of the staged cube: 0 -> E + 1, 1 -> E + 4
   int xcd = 1;     // map consecutive tiles / blocks to one XCD
   int tuned = 0;
 };

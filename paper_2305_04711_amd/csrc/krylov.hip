@@ -502,8 +502,13 @@ void solve_one(const cpm_band* b, const cpm_solve_opts& o, const double* rhs, do
                          1.0 / rb.first);
       CPM_LAUNCH_CHECK();
       const int inner = k.solve(r32, d32, true, itol, std::min(inner_cap, maxit - its), ce, graph,
-                                &restarts, dbest, 1e3);
+                                &restarts, dbest, 10.0);
       its += inner;
+      const Scal& hk = k.read();
+      // an inner FP32 solve that diverged (or stopped unconverged) marks the
+      // limit of FP32 accuracy for this system: apply its best iterate, then
+      // finish in FP64 from the refined x
+      const bool inner_failed = !(hk.done && hk.rr <= hk.tol2);
       if (trace_on()) {
         const Scal& h = k.read();
         std::fprintf(stderr, "[cpm] outer %d relres %.3e inner its %d inner rr %.3e done %d "
@@ -514,6 +519,11 @@ void solve_one(const cpm_band* b, const cpm_solve_opts& o, const double* rhs, do
                          rb.first);
       CPM_LAUNCH_CHECK();
       ++stt.outer_iters;
+      if (inner_failed) {
+        stt.fallback_f64 = 1;
+        ok = plain64(tol);
+        break;
+      }
     }
   }
   stt.krylov_iters += its;
