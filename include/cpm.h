@@ -220,6 +220,35 @@ cpm_status cpm_apply_profile(const cpm_band* band, double m, double n, int dtype
                              int nrhs, const void* u, void* v, int reps,
                              void* hip_stream, double* ms);
 
+/* ---- batched solves (several bands, uneven sizes, nrhs each) ----------
+ * A batch concatenates the bands' device data once (DOFs of band i at
+ * [offsets[i], offsets[i+1]) of a batch vector of length total) so that one
+ * launch per kernel applies every instance; band i uses A_i = m[i] I + n[i] M_i.
+ * Batch vectors are [nrhs][total].  The bands must stay alive while the batch
+ * is used; they must all have the same dimension. */
+typedef struct cpm_batch cpm_batch;
+cpm_status cpm_batch_create(cpm_band* const* bands, int nbands, const double* m,
+                            const double* n, int nrhs, void* hip_stream,
+                            cpm_batch** out);
+void cpm_batch_free(cpm_batch* batch);
+/* offsets: nbands + 1 entries; offsets[nbands] = total */
+cpm_status cpm_batch_offsets(const cpm_batch* batch, int64_t* offsets);
+/* v = A u for every instance and right-hand side (dtype CPM_F64 / CPM_F32) */
+cpm_status cpm_batch_apply(const cpm_batch* batch, int dtype, const void* u,
+                           void* v, void* hip_stream);
+/* Autotune the batch's apply as cpm_autotune does for one band. */
+cpm_status cpm_batch_autotune(cpm_batch* batch, int dtype, int reps,
+                              void* hip_stream, double* ms, int* best);
+/* Solve every system (instance, right-hand side) with its own BiCGSTAB
+ * scalars and convergence flag; opts->m, n and gauge are not used (the batch
+ * holds m, n per instance; the gauge is not supported).  Mixed mode refines
+ * in FP64 per system and finishes in FP64 any system whose FP32 inner solve
+ * fails.  rhs and x are device [nrhs][total] double; x holds x0 on entry.
+ * stats (may be NULL): nrhs * nbands entries, system s = r * nbands + i. */
+cpm_status cpm_batch_solve(cpm_batch* batch, const cpm_solve_opts* opts,
+                           const double* rhs, double* x, cpm_solve_stats* stats,
+                           void* hip_stream);
+
 /* Autotuner: time every launch variant of cpm_apply for this band, dtype and
  * nrhs (LDS line padding of the staged cube x XCD-aware tile order; variant
  * k = 2 * xcd + pad) with HIP events, `reps` calls each, and keep the fastest

@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libcpm.so")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 
-SOURCES = ["common.hip", "builder.hip", "apply.hip", "krylov.hip"]
+SOURCES = ["common.hip", "builder.hip", "apply.hip", "krylov.hip", "batch.hip"]
 ARCH = os.environ.get("CPM_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,

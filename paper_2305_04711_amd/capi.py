@@ -64,7 +64,8 @@ class SolveStats(C.Structure):
 
 EXPORTED = ["cpm_build_band", "cpm_band_free", "cpm_band_query", "cpm_band_export",
             "cpm_apply", "cpm_apply_profile", "cpm_autotune", "cpm_apply_transpose", "cpm_rhs", "cpm_rhs_adjoint", "cpm_solve",
-            "cpm_solve_adjoint", "cpm_last_error"]
+            "cpm_solve_adjoint", "cpm_batch_create", "cpm_batch_free", "cpm_batch_offsets",
+            "cpm_batch_apply", "cpm_batch_autotune", "cpm_batch_solve", "cpm_last_error"]
 
 _lib = None
 
@@ -102,10 +103,18 @@ def load(path=LIB_PATH):
     lib.cpm_solve.argtypes = [vp, C.POINTER(SolveOpts), i, vp, vp, C.POINTER(SolveStats), vp]
     lib.cpm_solve_adjoint.argtypes = [vp, C.POINTER(SolveOpts), i, vp, vp,
                                       C.POINTER(SolveStats), vp]
+    lib.cpm_batch_create.argtypes = [C.POINTER(vp), i, C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double), i, vp, C.POINTER(vp)]
+    lib.cpm_batch_free.argtypes = [vp]
+    lib.cpm_batch_free.restype = None
+    lib.cpm_batch_offsets.argtypes = [vp, C.POINTER(C.c_int64)]
+    lib.cpm_batch_apply.argtypes = [vp, i, vp, vp, vp]
+    lib.cpm_batch_autotune.argtypes = [vp, i, i, vp, C.POINTER(C.c_double), C.POINTER(C.c_int)]
+    lib.cpm_batch_solve.argtypes = [vp, C.POINTER(SolveOpts), vp, vp, C.POINTER(SolveStats), vp]
     lib.cpm_last_error.argtypes = []
     lib.cpm_last_error.restype = C.c_char_p
     for name in EXPORTED:
-        if name not in ("cpm_band_free", "cpm_last_error"):
+        if name not in ("cpm_band_free", "cpm_batch_free", "cpm_last_error"):
             getattr(lib, name).restype = C.c_int
     del dp
     _lib = lib

@@ -279,3 +279,76 @@ class CPMSolve(torch.autograd.Function):
         _check_attained(st, ctx.tol, "adjoint solve")
         gf, gg = rhs_adjoint(band, lam, ctx.n)
         return gf, (gg if band.n_c else None), None, None, None, None, None
+
+
+# ------------------------------------------------------------------ batches
+class Batch:
+    """Several bands solved together, one launch per kernel (cpm_batch_*):
+    band i is solved with A_i = m[i] I + n[i] M_i, nrhs right-hand sides each.
+    Batch vectors are (nrhs, total); instance i occupies columns
+    offsets[i]:offsets[i+1]."""
+
+    def __init__(self, bands, m, n, nrhs=1):
+        lib = capi.load()
+        self._lib = lib
+        self.bands = list(bands)          # keep the bands alive
+        k = len(self.bands)
+        arr = (C.c_void_p * k)(*[b.handle.value for b in self.bands])
+        mm = (C.c_double * k)(*[float(x) for x in m])
+        nn = (C.c_double * k)(*[float(x) for x in n])
+        out = C.c_void_p()
+        capi.check(lib.cpm_batch_create(arr, k, mm, nn, int(nrhs), _stream(), C.byref(out)))
+        self.handle = out
+        self.nrhs = int(nrhs)
+        offs = (C.c_int64 * (k + 1))()
+        capi.check(lib.cpm_batch_offsets(self.handle, offs))
+        self.offsets = list(offs)
+        self.total = self.offsets[-1]
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            self._lib.cpm_batch_free(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, t):
+        if not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != (self.nrhs, self.total):
+            raise ValueError("batch vectors are contiguous GPU tensors of shape (%d, %d)"
+                             % (self.nrhs, self.total))
+
+    def apply(self, u):
+        self._check(u)
+        v = torch.empty_like(u)
+        capi.check(self._lib.cpm_batch_apply(self.handle, _dtype_code(u), _ptr(u), _ptr(v),
+                                             _stream()))
+        return v
+
+    def autotune(self, dtype=torch.float64, reps=5):
+        ms = (C.c_double * 4)()
+        best = C.c_int()
+        code = capi.F64 if dtype == torch.float64 else capi.F32
+        capi.check(self._lib.cpm_batch_autotune(self.handle, code, int(reps), _stream(), ms,
+                                                C.byref(best)))
+        return list(ms), best.value
+
+    def solve(self, b, tol=1e-8, mode="mixed", x0=None, maxit=0, inner_tol=0.0,
+              check_every=0, use_graph=True, raise_noconv=True):
+        """Returns (x, stats) with one stats dict per system (r * nbands + i)."""
+        self._check(b)
+        if b.dtype != torch.float64:
+            raise TypeError("right-hand sides are float64")
+        x = torch.zeros_like(b) if x0 is None else x0.clone().contiguous()
+        ns = self.nrhs * len(self.bands)
+        st = (capi.SolveStats * ns)()
+        o = _opts(0.0, 0.0, tol, mode, maxit, inner_tol, check_every, use_graph, 0.0)
+        status = self._lib.cpm_batch_solve(self.handle, C.byref(o), _ptr(b), _ptr(x), st,
+                                           _stream())
+        stats = [{k: getattr(s, k) for k, _ in capi.SolveStats._fields_} for s in st]
+        if not (status == capi.E_NOCONV and not raise_noconv):
+            capi.check(status)
+        return x, stats

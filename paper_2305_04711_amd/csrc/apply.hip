@@ -63,14 +63,14 @@ struct TileView {
   const int* tile_blk;
   const int* tile_start;
   const int* perm;
-  const double* cp_perm;
+  const double* frac64;
   const float* frac32;
   const unsigned* lbase;
   int ntr;
 };
 
 static TileView tview(const cpm_band* b) {
-  return TileView{b->tile_meta, b->tile_blk, b->tile_start, b->perm, b->cp_perm, b->frac32,
+  return TileView{b->tile_meta, b->tile_blk, b->tile_start, b->perm, b->frac64, b->frac32,
                   b->lbase, b->n_tile_rows};
 }
 
@@ -102,27 +102,22 @@ template <class T, int DIM>
 __device__ __forceinline__ void row_stencil(const TileView& tv, int pos, int N, int lb[3], T t[3]);
 
 template <>
-__device__ __forceinline__ void row_stencil<double, 3>(const TileView& tv, int pos, int N, int lb[3],
+__device__ __forceinline__ void row_stencil<double, 3>(const TileView& tv, int pos, int, int lb[3],
                                                         double t[3]) {
-  const double dn = (double)N;
-  for (int a = 0; a < 3; ++a) {
-    const double y = tv.cp_perm[(int64_t)a * tv.ntr + pos] * dn;
-    const double F = floor(y);
-    lb[a] = ((int)F - 1) & 3;
-    t[a] = y - F;
-  }
+  const unsigned p = tv.lbase[pos];
+  lb[0] = p & 0xff;
+  lb[1] = (p >> 8) & 0xff;
+  lb[2] = (p >> 16) & 0xff;
+  for (int a = 0; a < 3; ++a) t[a] = tv.frac64[(int64_t)a * tv.ntr + pos];
 }
 template <>
-__device__ __forceinline__ void row_stencil<double, 2>(const TileView& tv, int pos, int N, int lb[3],
+__device__ __forceinline__ void row_stencil<double, 2>(const TileView& tv, int pos, int, int lb[3],
                                                         double t[3]) {
-  const double dn = (double)N;
-  for (int a = 0; a < 2; ++a) {
-    const double y = tv.cp_perm[(int64_t)a * tv.ntr + pos] * dn;
-    const double F = floor(y);
-    lb[a] = ((int)F - 1) & 7;
-    t[a] = y - F;
-  }
+  const unsigned p = tv.lbase[pos];
+  lb[0] = p & 0xff;
+  lb[1] = (p >> 8) & 0xff;
   lb[2] = 0;
+  for (int a = 0; a < 2; ++a) t[a] = tv.frac64[(int64_t)a * tv.ntr + pos];
   t[2] = 0.0;
 }
 template <>
@@ -269,7 +264,7 @@ __global__ __launch_bounds__(256) void k_lap(BlockView B, const T* __restrict__ 
                                              const T* __restrict__ a, T* __restrict__ v,
                                              int64_t ld, int nrhs, T cd, T co,
                                              const double* __restrict__ gsum, double gscale,
-                                             int xcd) {
+                                             int xcd, const double* __restrict__ coef) {
   using G = Geo<DIM>;
   constexpr int KB = kLapBlocksPerWave;
   const int wg = xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
@@ -277,13 +272,26 @@ __global__ __launch_bounds__(256) void k_lap(BlockView B, const T* __restrict__ 
   const int slot = threadIdx.x & 63;
   if (blk0 >= B.nb) return;
   unsigned long long lm = 0ull;
-  int loff = 0;
+  int loff = 0, lpad = 0;
   {
     const int j = slot >> 3, e = slot & 7;
     if (j < KB && blk0 + j < B.nb) {
       const QMeta q = B.face[(int64_t)(blk0 + j) * 8 + e];
       lm = q.mask;
       loff = q.off;
+      lpad = q.pad;
+    }
+  }
+  // batched systems: per-instance (cd, co), instance id in entry 7's pad
+  T cdj[KB], coj[KB];
+#pragma unroll
+  for (int j = 0; j < KB; ++j) {
+    cdj[j] = cd;
+    coj[j] = co;
+    if (coef) {
+      const int inst = lane_i32(lpad, 8 * j + 7);
+      cdj[j] = (T)coef[2 * (inst > 0 ? inst : 0)];
+      coj[j] = (T)coef[2 * (inst > 0 ? inst : 0) + 1];
     }
   }
   const int l[3] = {G::lx(slot), G::ly(slot), G::lz(slot)};
@@ -319,7 +327,7 @@ __global__ __launch_bounds__(256) void k_lap(BlockView B, const T* __restrict__ 
 #pragma unroll
       for (int f = 0; f < 2 * DIM; ++f)
         if (dof[j] >= 0 && nd[j][f] >= 0) s += a[r * ld + nd[j][f]];
-      out[j] = dof[j] >= 0 ? cd * u[r * ld + dof[j]] + co * s : T(0);
+      out[j] = dof[j] >= 0 ? cdj[j] * u[r * ld + dof[j]] + coj[j] * s : T(0);
     }
 #pragma unroll
     for (int j = 0; j < KB; ++j) {
@@ -335,10 +343,15 @@ template <class T>
 __global__ void k_lap_rows(int nrows, int nf, const int* __restrict__ row_id,
                            const int* __restrict__ col, const T* __restrict__ u,
                            const T* __restrict__ a, T* __restrict__ v, int64_t ld, int nrhs,
-                           T cd, T co, const double* __restrict__ gsum, double gscale) {
+                           T cd, T co, const double* __restrict__ gsum, double gscale,
+                           const double* __restrict__ coef, const int* __restrict__ row_inst) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nrows) return;
   const int id = row_id[i];
+  if (coef) {
+    cd = (T)coef[2 * row_inst[i]];
+    co = (T)coef[2 * row_inst[i] + 1];
+  }
   for (int r = 0; r < nrhs; ++r) {
     T s = T(0);
     for (int f = 0; f < nf; ++f) {
@@ -618,13 +631,13 @@ static void apply_dim(const cpm_band* b, double m, double n, int nrhs, const T* 
   const T co = (T)(n * N2);
   const double gscale = gsum ? gamma / (double)b->n_s : 0.0;
   hipLaunchKernelGGL((k_lap<T, DIM, false>), dim3((b->nb + 4 * kLapBlocksPerWave - 1) / (4 * kLapBlocksPerWave)), dim3(256), 0, st, bview(b), u,
-                     a, v, ld, nrhs, cd, co, gsum, gscale, tune_of<T>(b).xcd);
+                     a, v, ld, nrhs, cd, co, gsum, gscale, tune_of<T>(b).xcd, b->inst_coef);
   CPM_LAUNCH_CHECK();
   if (ev) CPM_HIP(hipEventRecord(ev[3], st));
   if (b->n_lrows) {
     hipLaunchKernelGGL(k_lap_rows<T>, dim3(grid_for(b->n_lrows, 128)), dim3(128), 0, st,
                        b->n_lrows, 2 * DIM, b->lrow_id, b->lcol, u, a, v, ld, nrhs, cd, co, gsum,
-                       gscale);
+                       gscale, b->inst_coef, b->lrow_inst);
     CPM_LAUNCH_CHECK();
   }
   if (ev) CPM_HIP(hipEventRecord(ev[4], st));
@@ -661,7 +674,7 @@ static void apply_T_dim(const cpm_band* b, double m, double n, int nrhs, const T
   // (fill kernels, not memsets: this sequence may be captured into a graph)
   hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(ld * nrhs, 256, 4096)), dim3(256), 0, st, c, ld * nrhs, T(0));
   hipLaunchKernelGGL((k_lap<T, DIM, true>), dim3((b->nb + 4 * kLapBlocksPerWave - 1) / (4 * kLapBlocksPerWave)), dim3(256), 0, st, bview(b), w,
-                     w, c, ld, nrhs, T(0), co, nullptr, 0.0, tune_of<T>(b).xcd);
+                     w, c, ld, nrhs, T(0), co, nullptr, 0.0, tune_of<T>(b).xcd, nullptr);
   CPM_LAUNCH_CHECK();
   if (b->n_lrows) {
     hipLaunchKernelGGL(k_lap_rows_T<T>, dim3(grid_for(b->n_lrows, 128)), dim3(128), 0, st,

@@ -376,7 +376,7 @@ template <int DIM>
 __global__ __launch_bounds__(256) void k_tile_fill(Blocks B, int nb, int N, int64_t n_s,
                                                    const double* cp, const int* eflag,
                                                    const int* tile_blk_of, int* pos2, int ntr,
-                                                   int* perm, double* cp_perm, float* frac32,
+                                                   int* perm, double* frac64, float* frac32,
                                                    unsigned* lbase) {
   NODE_PROLOGUE(DIM);
   if (eflag[dof]) return;
@@ -388,9 +388,8 @@ __global__ __launch_bounds__(256) void k_tile_fill(Blocks B, int nb, int N, int6
   stencil_base<DIM>(y, N, base, t);
   const int pos = atomicAdd(&pos2[(int64_t)bb * 64 + local_base_code<DIM>(base)], 1);
   perm[pos] = dof;
-  const double yy[3] = {y.x, y.y, y.z};
   for (int a = 0; a < DIM; ++a) {
-    cp_perm[(int64_t)a * ntr + pos] = yy[a];
+    frac64[(int64_t)a * ntr + pos] = t[a];
     frac32[(int64_t)a * ntr + pos] = (float)t[a];
   }
   const unsigned lx = base[0] & (G::BX - 1), ly = base[1] & (G::BX - 1),
@@ -616,6 +615,7 @@ __global__ void k_blk_face(Blocks B, int nb, int dim, int nnbr, const unsigned l
   QMeta m{0ull, 0, -1};
   if (k == 7) {
     m.mask = lrow_mask[i];
+    m.pad = 0;   // instance id (0 for a single band)
   } else if (k <= 2 * dim) {
     int id = i;
     if (k > 0) {
@@ -905,7 +905,7 @@ void build(cpm_band* b, hipStream_t st) {
                            hipMemcpyHostToDevice, st));
     const int ntr = b->n_tile_rows;
     b->perm = b->alloc<int>(ntr);
-    b->cp_perm = b->alloc<double>((size_t)DIM * ntr);
+    b->frac64 = b->alloc<double>((size_t)DIM * ntr);
     b->frac32 = b->alloc<float>((size_t)DIM * ntr);
     b->lbase = b->alloc<unsigned>(ntr);
     {
@@ -917,7 +917,7 @@ void build(cpm_band* b, hipStream_t st) {
       const int64_t tot = scan_exclusive_i32(cnt2.p, pos2.p, (int64_t)nb * 64, st);
       if (tot != ntr) CPM_FAIL(CPM_E_INVALID, "internal: tile row count mismatch");
       hipLaunchKernelGGL(k_tile_fill<DIM>, gnode, dim3(256), 0, st, B, nb, N, n_s, b->cp,
-                         eflag.p, tile_blk_of.p, pos2.p, ntr, b->perm, b->cp_perm, b->frac32,
+                         eflag.p, tile_blk_of.p, pos2.p, ntr, b->perm, b->frac64, b->frac32,
                          b->lbase);
       CPM_LAUNCH_CHECK();
       CPM_HIP(hipStreamSynchronize(st));

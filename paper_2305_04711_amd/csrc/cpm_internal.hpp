@@ -129,7 +129,7 @@ struct cpm_band {
   cpm::QMeta* tile_meta = nullptr;    // [ntiles][8] the 2^d staged blocks
   int* tile_start = nullptr;          // [ntiles + 1]
   int* perm = nullptr;                // [n_tile_rows] row DOF
-  double* cp_perm = nullptr;          // [dim][n_tile_rows]
+  double* frac64 = nullptr;           // [dim][n_tile_rows] FP64 fractions
   float* frac32 = nullptr;            // [dim][n_tile_rows] FP32 fractions
   unsigned int* lbase = nullptr;      // [n_tile_rows] packed local base
 
@@ -153,6 +153,12 @@ struct cpm_band {
   int* bc_side = nullptr;             // [n_c]
   int* bc_curve = nullptr;            // [n_c]
   double ecoef = 2.0;
+
+  // composite of several bands (batched solves): per-instance FD
+  // coefficients (cd, co) of A, instance of each explicit FD row
+  double* inst_coef = nullptr;
+  int* lrow_inst = nullptr;
+  bool composite = false;
 
   int64_t on_c_nodes = 0, no_bc_dof_swaps = 0;
   size_t bytes = 0;
