@@ -173,7 +173,9 @@ cpm_status cpm_rhs_adjoint(const cpm_band* band, double n, int nrhs,
                            double* grad_g, void* hip_stream);
 
 enum { CPM_SOLVE_MIXED = 0,  /* FP32 BiCGSTAB + FP64 iterative refinement */
-       CPM_SOLVE_F64 = 1 };  /* plain FP64 BiCGSTAB                        */
+       CPM_SOLVE_F64 = 1,    /* plain FP64 BiCGSTAB                        */
+       CPM_SOLVE_GMRES = 2 };/* FP64 restarted GMRES(restart), classical
+                                Gram-Schmidt with one re-orthogonalisation  */
 
 typedef struct {
   double m, n;        /* A = m I + n M                                       */
@@ -186,6 +188,7 @@ typedef struct {
   int use_graph;      /* 1: replay the check_every iterations as a hipGraph  */
   double gauge;       /* >0: solve (A + gauge 1 w^T) x = b, w = 1/n_s on PDE
                          DOFs (closed-surface Poisson); 0 = off              */
+  int restart;        /* GMRES restart length (0 = 50, at most 200)          */
 } cpm_solve_opts;
 
 typedef struct {

@@ -22,7 +22,7 @@ IBC_POINT, IBC_LATITUDE, IBC_MERIDIAN = 1, 2, 3
 EXPORT_COORDS, EXPORT_CP, EXPORT_BC_NODE, EXPORT_BC_CPC, EXPORT_BC_SIDE, EXPORT_BC_CURVE, \
     EXPORT_ECOLS, EXPORT_LCOLS, EXPORT_BASE = range(1, 10)
 F64, F32 = 0, 1
-SOLVE_MIXED, SOLVE_F64 = 0, 1
+SOLVE_MIXED, SOLVE_F64, SOLVE_GMRES = 0, 1, 2
 
 
 class Surface(C.Structure):
@@ -53,7 +53,7 @@ class BandInfo(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("m", C.c_double), ("n", C.c_double), ("tol", C.c_double), ("mode", C.c_int),
                 ("maxit", C.c_int), ("inner_tol", C.c_double), ("check_every", C.c_int),
-                ("use_graph", C.c_int), ("gauge", C.c_double)]
+                ("use_graph", C.c_int), ("gauge", C.c_double), ("restart", C.c_int)]
 
 
 class SolveStats(C.Structure):

@@ -215,20 +215,20 @@ def rhs_adjoint(band, lam, n):
     return gf, gg
 
 
-def _opts(m, n, tol, mode, maxit, inner_tol, check_every, use_graph, gauge):
-    code = {"mixed": capi.SOLVE_MIXED, "f64": capi.SOLVE_F64}[mode]
+def _opts(m, n, tol, mode, maxit, inner_tol, check_every, use_graph, gauge, restart=0):
+    code = {"mixed": capi.SOLVE_MIXED, "f64": capi.SOLVE_F64, "gmres": capi.SOLVE_GMRES}[mode]
     return capi.SolveOpts(float(m), float(n), float(tol), code, int(maxit), float(inner_tol),
-                          int(check_every), int(bool(use_graph)), float(gauge))
+                          int(check_every), int(bool(use_graph)), float(gauge), int(restart))
 
 
 def _solve(fn, band, b, m, n, tol, mode, x0, maxit, inner_tol, check_every, use_graph, gauge,
-           raise_noconv):
+           raise_noconv, restart=0):
     nrhs = _check_vec(band, b, band.n)
     if b.dtype != torch.float64:
         raise TypeError("right-hand sides are float64")
     x = torch.zeros_like(b) if x0 is None else x0.clone().contiguous()
     st = capi.SolveStats()
-    o = _opts(m, n, tol, mode, maxit, inner_tol, check_every, use_graph, gauge)
+    o = _opts(m, n, tol, mode, maxit, inner_tol, check_every, use_graph, gauge, restart)
     status = fn(band.handle, C.byref(o), nrhs, _ptr(b), _ptr(x), C.byref(st), _stream())
     stats = {k: getattr(st, k) for k, _ in capi.SolveStats._fields_}
     if status == capi.E_NOCONV and not raise_noconv:
@@ -238,11 +238,11 @@ def _solve(fn, band, b, m, n, tol, mode, x0, maxit, inner_tol, check_every, use_
 
 
 def solve(band, b, m, n, tol=1e-8, mode="mixed", x0=None, maxit=0, inner_tol=0.0,
-          check_every=0, use_graph=True, gauge=0.0, raise_noconv=True):
+          check_every=0, use_graph=True, gauge=0.0, raise_noconv=True, restart=0):
     """Solve A x = b.  mode "mixed": FP32 BiCGSTAB + FP64 refinement; "f64":
-    plain FP64 BiCGSTAB.  Returns (x, stats)."""
+    plain FP64 BiCGSTAB; "gmres": FP64 GMRES(restart).  Returns (x, stats)."""
     return _solve(band._lib.cpm_solve, band, b, m, n, tol, mode, x0, maxit, inner_tol,
-                  check_every, use_graph, gauge, raise_noconv)
+                  check_every, use_graph, gauge, raise_noconv, restart)
 
 
 def solve_adjoint(band, rhs_, m, n, tol=1e-8, mode="mixed", x0=None, maxit=0, inner_tol=0.0,

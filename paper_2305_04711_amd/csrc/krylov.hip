@@ -257,6 +257,64 @@ __global__ void k_zero_scal(Scal* S) {
   }
 }
 
+// ---- GMRES helpers (FP64)
+// part[j][blk] = partial of (V_j, w) for j < nv (grid: blocks x nv)
+__global__ __launch_bounds__(256) void k_gm_dots(int64_t n, const double* __restrict__ V,
+                                                 int64_t ldv, const double* __restrict__ w,
+                                                 double* part) {
+  __shared__ double sh[256];
+  const int j = blockIdx.y;
+  const double* vj = V + (int64_t)j * ldv;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    acc += vj[i] * w[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(int64_t)j * gridDim.x + blockIdx.x] = sh[0];
+}
+
+__global__ void k_gm_sum(const double* part, int np, double* out) {
+  __shared__ double sh[256];
+  const int j = blockIdx.x;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += 256) acc += part[(int64_t)j * np + i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = sh[0];
+}
+
+// w += sign * sum_j c_j V_j
+__global__ void k_gm_comb(int64_t n, const double* __restrict__ V, int64_t ldv, int nv,
+                          const double* __restrict__ c, double sign, double* __restrict__ w) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int j = 0; j < nv; ++j) acc += c[j] * V[(int64_t)j * ldv + i];
+    w[i] += sign * acc;
+  }
+}
+
+__global__ void k_gm_scale(int64_t n, const double* __restrict__ w, double a, double* __restrict__ v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    v[i] = a * w[i];
+}
+
+__global__ void k_gm_res(int64_t n, const double* __restrict__ b, const double* __restrict__ v,
+                         double* __restrict__ r) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    r[i] = b[i] - v[i];
+}
+
 // ================================================================== host
 namespace {
 
@@ -439,8 +497,122 @@ std::pair<double, double> residual64(const cpm_band* b, hipStream_t st, double m
   return {std::sqrt(pin.h->rr), std::sqrt(pin.h->bb)};
 }
 
+// GMRES(k): Arnoldi with classical Gram-Schmidt and one re-orthogonalisation
+// on the device, Givens rotations of the Hessenberg on the host (one read
+// back per iteration; meant for small systems such as curves in R^2).
+void gmres64(const cpm_band* b, const cpm_solve_opts& o, const double* rhs, double* x,
+             cpm_solve_stats& stt, hipStream_t st, bool tr) {
+  const int64_t n = b->n;
+  const int k = std::min(200, o.restart > 0 ? o.restart : 50);
+  const int maxit = o.maxit > 0 ? o.maxit : 20000;
+  const double tol = o.tol > 0 ? o.tol : 1e-8;
+  double* V = (double*)band_scratch(b, 70, sizeof(double) * (size_t)n * (k + 1));
+  double* w = (double*)band_scratch(b, 71, sizeof(double) * n);
+  const int gd = (int)std::min<int64_t>(256, (n + 255) / 256);
+  double* part = (double*)band_scratch(b, 72, sizeof(double) * (size_t)gd * (k + 1));
+  double* dv = (double*)band_scratch(b, 73, sizeof(double) * (k + 2));
+  double* hp = nullptr;
+  CPM_HIP(hipHostMalloc((void**)&hp, sizeof(double) * (k + 2), hipHostMallocDefault));
+  struct HF { double* p; ~HF() { if (p) (void)hipHostFree(p); } } hf{hp};
+  auto A = [&](const double* in, double* out) {
+    if (tr) apply_transpose_impl<double>(b, o.m, o.n, 1, in, out, st, nullptr, o.gauge);
+    else apply_impl<double>(b, o.m, o.n, 1, in, out, st, nullptr, o.gauge);
+  };
+  const int eg = grid_for(n, 256, 4096);
+  auto dots = [&](int nv, const double* vec) {   // dv[0..nv) = (V_j, vec)
+    hipLaunchKernelGGL(k_gm_dots, dim3(gd, nv), dim3(256), 0, st, n, V, n, vec, part);
+    hipLaunchKernelGGL(k_gm_sum, dim3(nv), dim3(256), 0, st, part, gd, dv);
+    CPM_LAUNCH_CHECK();
+    CPM_HIP(hipMemcpyAsync(hp, dv, sizeof(double) * nv, hipMemcpyDeviceToHost, st));
+    CPM_HIP(hipStreamSynchronize(st));
+  };
+  auto norm_of = [&](const double* vec) {        // ||vec|| via V_0 slot trick
+    hipLaunchKernelGGL(k_gm_dots, dim3(gd, 1), dim3(256), 0, st, n, vec, n, vec, part);
+    hipLaunchKernelGGL(k_gm_sum, dim3(1), dim3(256), 0, st, part, gd, dv);
+    CPM_LAUNCH_CHECK();
+    CPM_HIP(hipMemcpyAsync(hp, dv, sizeof(double), hipMemcpyDeviceToHost, st));
+    CPM_HIP(hipStreamSynchronize(st));
+    return std::sqrt(hp[0]);
+  };
+  const double bn = norm_of(rhs);
+  if (bn == 0.0) {
+    CPM_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, st));
+    stt.converged = 1;
+    stt.relres = 0.0;
+    return;
+  }
+  std::vector<double> H((size_t)(k + 1) * k), cs(k), sn(k), g(k + 1), y(k);
+  int its = 0;
+  double rel = 1.0;
+  while (its < maxit) {
+    A(x, w);
+    hipLaunchKernelGGL(k_gm_res, dim3(eg), dim3(256), 0, st, n, rhs, w, w);
+    CPM_LAUNCH_CHECK();
+    const double beta = norm_of(w);
+    rel = beta / bn;
+    stt.relres = rel;
+    ++stt.outer_iters;
+    if (rel <= tol) break;
+    hipLaunchKernelGGL(k_gm_scale, dim3(eg), dim3(256), 0, st, n, w, 1.0 / beta, V);
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int j = 0;
+    for (; j < k && its < maxit; ++j) {
+      A(V + (int64_t)j * n, w);
+      // two passes of classical Gram-Schmidt
+      for (int pass = 0; pass < 2; ++pass) {
+        dots(j + 1, w);
+        for (int i = 0; i <= j; ++i) H[(size_t)i * k + j] += hp[i];
+        CPM_HIP(hipMemcpyAsync(dv, hp, sizeof(double) * (j + 1), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_gm_comb, dim3(eg), dim3(256), 0, st, n, V, n, j + 1, dv, -1.0, w);
+        CPM_LAUNCH_CHECK();
+      }
+      const double hn = norm_of(w);
+      H[(size_t)(j + 1) * k + j] = hn;
+      if (hn > 0.0)
+        hipLaunchKernelGGL(k_gm_scale, dim3(eg), dim3(256), 0, st, n, w, 1.0 / hn,
+                           V + (int64_t)(j + 1) * n);
+      for (int i = 0; i < j; ++i) {
+        const double a = H[(size_t)i * k + j], c2 = H[(size_t)(i + 1) * k + j];
+        H[(size_t)i * k + j] = cs[i] * a + sn[i] * c2;
+        H[(size_t)(i + 1) * k + j] = -sn[i] * a + cs[i] * c2;
+      }
+      const double a = H[(size_t)j * k + j], c2 = H[(size_t)(j + 1) * k + j];
+      const double den = std::hypot(a, c2);
+      cs[j] = den > 0 ? a / den : 1.0;
+      sn[j] = den > 0 ? c2 / den : 0.0;
+      H[(size_t)j * k + j] = den;
+      H[(size_t)(j + 1) * k + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++its;
+      if (std::fabs(g[j + 1]) <= tol * bn || hn == 0.0) {
+        ++j;
+        break;
+      }
+    }
+    // back substitution and x += V y
+    for (int i = j - 1; i >= 0; --i) {
+      double s2 = g[i];
+      for (int q = i + 1; q < j; ++q) s2 -= H[(size_t)i * k + q] * y[q];
+      y[i] = s2 / H[(size_t)i * k + i];
+    }
+    CPM_HIP(hipMemcpyAsync(dv, y.data(), sizeof(double) * j, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_gm_comb, dim3(eg), dim3(256), 0, st, n, V, n, j, dv, 1.0, x);
+    CPM_LAUNCH_CHECK();
+    CPM_HIP(hipStreamSynchronize(st));
+  }
+  stt.krylov_iters += its;
+  stt.converged = rel <= tol ? 1 : 0;
+}
+
 void solve_one(const cpm_band* b, const cpm_solve_opts& o, const double* rhs, double* x,
                cpm_solve_stats& stt, hipStream_t st, bool tr) {
+  if (o.mode == CPM_SOLVE_GMRES) {
+    gmres64(b, o, rhs, x, stt, st, tr);
+    return;
+  }
   const int64_t n = b->n;
   const int maxit = o.maxit > 0 ? o.maxit : 20000;
   const int ce = o.check_every > 0 ? o.check_every : 16;
@@ -536,7 +708,7 @@ cpm_status solve_entry(const cpm_band* b, const cpm_solve_opts* o, int nrhs, con
   cpm_status ret = CPM_OK;
   cpm_status g = guard([&] {
     if (!b || !o || !rhs || !x || nrhs < 1) CPM_FAIL(CPM_E_INVALID, "bad argument");
-    if (o->mode != CPM_SOLVE_MIXED && o->mode != CPM_SOLVE_F64)
+    if (o->mode != CPM_SOLVE_MIXED && o->mode != CPM_SOLVE_F64 && o->mode != CPM_SOLVE_GMRES)
       CPM_FAIL(CPM_E_INVALID, "unknown solve mode %d", o->mode);
     if (tr && o->gauge != 0.0) CPM_FAIL(CPM_E_INVALID, "the gauge is not supported for the adjoint");
     const auto t0 = Clock::now();
