@@ -58,6 +58,70 @@ def cpu_baseline(seconds=12.0):
                       "h = 1/64 (%d DOFs), %d applies over %.1f s" % (sysm.n, k, k * dt)}
 
 
+def run_batch(dev, args):
+    """Batched uneven solves: 32 instances (even k: unit sphere, odd k: torus
+    R = 1, rho = 0.4) at N_k = 64 + round(128 k / 31), 3 right-hand sides
+    each (seeded smooth sources), screened Poisson (m = 1, n = -1), to a
+    relative residual of 1e-8: batched mixed precision and batched FP64
+    against the plain FP64 solve of each instance one call at a time."""
+    import numpy as np
+    import torch
+    from paper_2305_04711_amd import cpm, inputs
+    bands, t0 = [], time.perf_counter()
+    for k in range(32):
+        N = 64 + int(round(128 * k / 31))
+        if k % 2 == 0:
+            bands.append(cpm.Band(cpm.sphere(), [], N))
+        else:
+            bands.append(cpm.Band(cpm.torus(1.0, 0.4), [], N))
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    nrhs = 3
+    batch = cpm.Batch(bands, [1.0] * 32, [-1.0] * 32, nrhs=nrhs)
+    tune = batch.autotune(torch.float32)
+    b = torch.empty(nrhs, batch.total, dtype=torch.float64, device=dev)
+    for k, band in enumerate(bands):
+        cp = torch.tensor(band.cp(), device=dev)
+        lo, hi = batch.offsets[k], batch.offsets[k + 1]
+        for r in range(nrhs):
+            if k % 2 == 0:
+                fv = inputs.sphere_field(inputs.sphere_coeffs(100 + k + 1000 * r, lmin=0), cp)
+            else:
+                fv = inputs.torus_field(inputs.torus_coeffs(100 + k + 1000 * r), cp)
+            b[r, lo:hi] = fv
+    out = {"instances": 32, "nrhs": nrhs, "dofs_total": batch.total,
+           "dofs_min": min(bd.n for bd in bands), "dofs_max": max(bd.n for bd in bands),
+           "build_s": build_s, "autotune_f32": tune}
+    for mode in ("mixed", "f64"):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x, st = batch.solve(b, tol=1e-8, mode=mode, raise_noconv=False)
+        torch.cuda.synchronize()
+        out["batched_" + mode] = {
+            "seconds": time.perf_counter() - t,
+            "converged": all(s["converged"] for s in st),
+            "max_relres": max(s["relres"] for s in st),
+            "max_krylov_iters": max(s["krylov_iters"] for s in st),
+            "fallback_f64_systems": sum(s["fallback_f64"] for s in st)}
+        log("batched %s: %s" % (mode, out["batched_" + mode]))
+    # plain FP64 solves, one instance (3 right-hand sides) per call
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    worst, conv = 0.0, True
+    for k, band in enumerate(bands):
+        lo, hi = batch.offsets[k], batch.offsets[k + 1]
+        xk, st = cpm.solve(band, b[:, lo:hi].contiguous(), 1.0, -1.0, tol=1e-8, mode="f64",
+                           raise_noconv=False)
+        worst = max(worst, st["relres"])
+        conv = conv and bool(st["converged"])
+    torch.cuda.synchronize()
+    out["sequential_f64"] = {"seconds": time.perf_counter() - t, "converged": conv,
+                             "max_relres": worst}
+    log("sequential f64: %s" % out["sequential_f64"])
+    del batch, bands
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,6 +130,8 @@ def main():
     ap.add_argument("--N", type=int, default=512)
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (a kernel of known "
                          "traffic for scaling the HBM byte counters)")
@@ -151,6 +217,32 @@ def main():
                             "fallback_f64": bool(st["fallback_f64"])}
             log("solve %s: %s" % (mode, solves[mode]))
 
+    adjoint = None
+    if not args.no_solve and not args.no_adjoint:
+        # forward + backward of the differentiable solve (loss against a seeded
+        # smooth target): one adjoint solve plus the RHS adjoint
+        t_np = inputs.torus_field(inputs.torus_coeffs(3), cp)
+        tt = torch.tensor(t_np, device=dev)
+        fr = f.clone().requires_grad_(True)
+        gr = g.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        u = cpm.CPMSolve.apply(fr, gr, band, m, n, 1e-8, "mixed")
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t
+        loss = ((u[:band.n_s] - tt) ** 2).sum()
+        t = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        adjoint = {"forward_s": t_fwd, "backward_s": time.perf_counter() - t,
+                   "tol": 1e-8, "grad_f_norm": fr.grad.norm().item(),
+                   "grad_g_norm": gr.grad.norm().item()}
+        log("adjoint: %s" % adjoint)
+
+    batch_out = None
+    if not args.no_batch:
+        batch_out = run_batch(dev, args)
+
     if args.calibrate_copy:
         src = torch.ones(2 ** 27, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -190,6 +282,8 @@ def main():
         "autotune": {"variants": "k = 2 * xcd + pad", "f64_ms": tune64[0], "f64_best": tune64[1],
                      "f32_ms": tune32[0], "f32_best": tune32[1]},
         "build_band_s": build_s,
+        "adjoint": adjoint,
+        "batched": batch_out,
     }
     print(json.dumps(out))
 

@@ -59,6 +59,8 @@ __device__ __forceinline__ int nbr_dof(const BlockView& B, int blk, int mx, int 
 }
 
 struct TileView {
+  const int* tile_inst;   // batched composite: instance of each tile (else null)
+  const int* skip;        // batched composite: instances to skip (else null)
   const QMeta* meta;
   const int* tile_blk;
   const int* tile_start;
@@ -70,32 +72,14 @@ struct TileView {
 };
 
 static TileView tview(const cpm_band* b) {
-  return TileView{b->tile_meta, b->tile_blk, b->tile_start, b->perm, b->frac64, b->frac32,
-                  b->lbase, b->n_tile_rows};
+  return TileView{b->tile_inst, b->inst_skip, b->tile_meta, b->tile_blk, b->tile_start, b->perm,
+                  b->frac64, b->frac32, b->lbase, b->n_tile_rows};
 }
 
 template <int DIM> struct Cube {
   static constexpr int E = 2 * Geo<DIM>::BX;              // cube edge
   static constexpr int SIZE = DIM == 3 ? E * E * E : E * E;
 };
-
-// Stage the 2^d blocks starting at block tb into a dense cube (zeros where no
-// band node).  idx enumerates (quadrant, slot).
-template <class T, int DIM>
-__device__ __forceinline__ void cube_index(const BlockView& B, int tb, int idx, int& dof, int& ci) {
-  using G = Geo<DIM>;
-  const int q = idx >> 6, s = idx & 63;
-  const int qx = q & 1, qy = (q >> 1) & 1, qz = DIM == 3 ? (q >> 2) : 0;
-  const int blk = q == 0 ? tb : B.nbr[tb * G::NNBR + G::code(qx, qy, qz)];
-  const int cx = qx * G::BX + G::lx(s), cy = qy * G::BX + G::ly(s);
-  const int cz = DIM == 3 ? qz * G::BX + G::lz(s) : 0;
-  ci = DIM == 3 ? (cz * Cube<DIM>::E + cy) * Cube<DIM>::E + cx : cy * Cube<DIM>::E + cx;
-  dof = -1;
-  if (blk >= 0) {
-    const unsigned long long m = B.mask[blk];
-    if ((m >> s) & 1ull) dof = B.off[blk] + __popcll(m & ((1ull << s) - 1ull));
-  }
-}
 
 // Per-row stencil base (local to the tile block) and fraction.
 template <class T, int DIM>
@@ -154,6 +138,7 @@ __global__ __launch_bounds__(64) void k_gather(BlockView B, TileView tv, int N, 
   __shared__ T s_u[NR][CS];
   const int t = xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
   const int lane = threadIdx.x;
+  if (tv.skip && tv.skip[tv.tile_inst[t]]) return;   // converged batch instance
   unsigned long long qm = 0ull;
   int qoff = 0;
   if (lane < NQ) {
@@ -236,11 +221,13 @@ template <class T>
 __global__ __launch_bounds__(256) void k_gather_rows(int nrows, int nm, const int* __restrict__ row_id,
                                                      const int* __restrict__ col,
                                                      const T* __restrict__ w, const T* __restrict__ u,
-                                                     T* __restrict__ a, int64_t ld, int nrhs) {
+                                                     T* __restrict__ a, int64_t ld, int nrhs,
+                                                     const int* __restrict__ row_inst,
+                                                     const int* __restrict__ skip) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t i = g / nm;
   const int o = (int)(g % nm);
-  const bool live = i < nrows;
+  const bool live = i < nrows && !(skip && skip[row_inst[i]]);
   const int c = live ? col[i * nm + o] : -1;
   const T wt = live ? w[i * nm + o] : T(0);
   for (int r = 0; r < nrhs; ++r) {
@@ -264,7 +251,8 @@ __global__ __launch_bounds__(256) void k_lap(BlockView B, const T* __restrict__ 
                                              const T* __restrict__ a, T* __restrict__ v,
                                              int64_t ld, int nrhs, T cd, T co,
                                              const double* __restrict__ gsum, double gscale,
-                                             int xcd, const double* __restrict__ coef) {
+                                             int xcd, const double* __restrict__ coef,
+                                             const int* __restrict__ skip) {
   using G = Geo<DIM>;
   constexpr int KB = kLapBlocksPerWave;
   const int wg = xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
@@ -284,14 +272,18 @@ __global__ __launch_bounds__(256) void k_lap(BlockView B, const T* __restrict__ 
   }
   // batched systems: per-instance (cd, co), instance id in entry 7's pad
   T cdj[KB], coj[KB];
+  bool skipj[KB];
 #pragma unroll
   for (int j = 0; j < KB; ++j) {
     cdj[j] = cd;
     coj[j] = co;
+    skipj[j] = false;
     if (coef) {
       const int inst = lane_i32(lpad, 8 * j + 7);
-      cdj[j] = (T)coef[2 * (inst > 0 ? inst : 0)];
-      coj[j] = (T)coef[2 * (inst > 0 ? inst : 0) + 1];
+      const int ii = inst > 0 ? inst : 0;
+      cdj[j] = (T)coef[2 * ii];
+      coj[j] = (T)coef[2 * ii + 1];
+      skipj[j] = skip && skip[ii];
     }
   }
   const int l[3] = {G::lx(slot), G::ly(slot), G::lz(slot)};
@@ -302,7 +294,7 @@ __global__ __launch_bounds__(256) void k_lap(BlockView B, const T* __restrict__ 
     const unsigned long long m = lane_u64(lm, 8 * j);
     const int off0 = lane_i32(loff, 8 * j);
     const unsigned long long xm = lane_u64(lm, 8 * j + 7);
-    bool on = (m >> slot) & 1ull;
+    bool on = ((m >> slot) & 1ull) && !skipj[j];
     if (!ALL && ((xm >> slot) & 1ull)) on = false;
     dof[j] = on ? off0 + __popcll(m & ((1ull << slot) - 1ull)) : -1;
 #pragma unroll
@@ -344,11 +336,13 @@ __global__ void k_lap_rows(int nrows, int nf, const int* __restrict__ row_id,
                            const int* __restrict__ col, const T* __restrict__ u,
                            const T* __restrict__ a, T* __restrict__ v, int64_t ld, int nrhs,
                            T cd, T co, const double* __restrict__ gsum, double gscale,
-                           const double* __restrict__ coef, const int* __restrict__ row_inst) {
+                           const double* __restrict__ coef, const int* __restrict__ row_inst,
+                           const int* __restrict__ skip) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nrows) return;
   const int id = row_id[i];
   if (coef) {
+    if (skip && skip[row_inst[i]]) return;
     cd = (T)coef[2 * row_inst[i]];
     co = (T)coef[2 * row_inst[i] + 1];
   }
@@ -403,20 +397,32 @@ __device__ __forceinline__ void atomic_add(T* p, T v) {
   unsafeAtomicAdd(p, v);
 }
 
-// E^T c for the tile rows: scatter w c_i into the staged cube, then add the
-// cube into z with one atomic per band node.
+// E^T c for the tile rows, one wavefront per tile: every row scatters
+// w c_i into the tile's (2 BX)^d cube in LDS (LDS atomics), then the cube is
+// added into z with one global atomic per band node of the staged blocks.
 template <class T, int DIM>
-__global__ __launch_bounds__(256) void k_gather_T(BlockView B, TileView tv, int N,
-                                                  const T* __restrict__ c, T* __restrict__ z,
-                                                  int64_t ld, int r) {
-  constexpr int CS = Cube<DIM>::SIZE, E = Cube<DIM>::E;
+__global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, int N,
+                                                 const T* __restrict__ c, T* __restrict__ z,
+                                                 int64_t ld, int r, int xcd) {
+  using G = Geo<DIM>;
+  constexpr int E = Cube<DIM>::E, EP = E + 1, NQ = 1 << DIM;
+  constexpr int CS = DIM == 3 ? E * E * EP : E * EP;
   __shared__ T s_z[CS];
-  const int t = blockIdx.x;
-  const int tb = tv.tile_blk[t];
-  for (int idx = threadIdx.x; idx < CS; idx += blockDim.x) s_z[idx] = T(0);
+  const int t = xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int lane = threadIdx.x;
+  for (int idx = lane; idx < CS; idx += 64) s_z[idx] = T(0);
+  unsigned long long qm = 0ull;
+  int qoff = 0;
+  if (lane < NQ) {
+    const QMeta q = tv.meta[(int64_t)t * 8 + lane];
+    qm = q.mask;
+    qoff = q.off;
+  }
   __syncthreads();
   const int end = tv.tile_start[t + 1];
-  for (int pos = tv.tile_start[t] + threadIdx.x; pos < end; pos += blockDim.x) {
+  for (int pos = tv.tile_start[t] + lane; pos < end; pos += 64) {
+    const T ci = c[r * ld + tv.perm[pos]];
+    if (ci == T(0)) continue;
     int lb[3];
     T tt[3];
     row_stencil<T, DIM>(tv, pos, N, lb, tt);
@@ -424,23 +430,30 @@ __global__ __launch_bounds__(256) void k_gather_T(BlockView B, TileView tv, int 
     lagrange4<T>(tt[0], wx);
     lagrange4<T>(tt[1], wy);
     if (DIM == 3) lagrange4<T>(tt[2], wz);
-    const T ci = c[r * ld + tv.perm[pos]];
+#pragma unroll
     for (int cc = 0; cc < (DIM == 3 ? 4 : 1); ++cc) {
+#pragma unroll
       for (int b = 0; b < 4; ++b) {
         const T wyz = (DIM == 3 ? wz[cc] : T(1)) * wy[b] * ci;
-        const int base = DIM == 3 ? ((lb[2] + cc) * E + (lb[1] + b)) * E + lb[0] : (lb[1] + b) * E + lb[0];
+        const int base = DIM == 3 ? ((lb[2] + cc) * E + (lb[1] + b)) * EP + lb[0]
+                                  : (lb[1] + b) * EP + lb[0];
+#pragma unroll
         for (int aa = 0; aa < 4; ++aa) atomicAdd(&s_z[base + aa], wx[aa] * wyz);
       }
     }
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < CS; idx += blockDim.x) {
-    int dof, ci;
-    cube_index<T, DIM>(B, tb, idx, dof, ci);
-    if (dof >= 0) {
-      const T val = s_z[ci];
-      if (val != T(0)) atomic_add(&z[r * ld + dof], val);
-    }
+  const int cx0 = G::lx(lane), cy0 = G::ly(lane), cz0 = G::lz(lane);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const unsigned long long m = lane_u64(qm, q);
+    const int off = lane_i32(qoff, q);
+    if (!((m >> lane) & 1ull)) continue;
+    const int qx = q & 1, qy = (q >> 1) & 1, qz = DIM == 3 ? (q >> 2) : 0;
+    const int cx = qx * G::BX + cx0, cy = qy * G::BX + cy0, cz = qz * G::BX + cz0;
+    const int ci = DIM == 3 ? (cz * E + cy) * EP + cx : cy * EP + cx;
+    const T val = s_z[ci];
+    if (val != T(0)) atomic_add(&z[r * ld + off + __popcll(m & ((1ull << lane) - 1ull))], val);
   }
 }
 
@@ -612,7 +625,8 @@ static void launch_gather(const cpm_band* b, int nrhs, const T* u, T* a, hipStre
   if (b->n_erows) {
     const int nm = DIM == 3 ? 64 : 16;
     hipLaunchKernelGGL(k_gather_rows<T>, dim3(grid_for((int64_t)b->n_erows * nm, 256)), dim3(256),
-                       0, st, b->n_erows, nm, b->erow_id, b->ecol, ew_of<T>(b), u, a, ld, nrhs);
+                       0, st, b->n_erows, nm, b->erow_id, b->ecol, ew_of<T>(b), u, a, ld, nrhs,
+                       b->erow_inst, b->inst_skip);
     CPM_LAUNCH_CHECK();
   }
   if (ev) CPM_HIP(hipEventRecord(ev[2], st));
@@ -631,13 +645,14 @@ static void apply_dim(const cpm_band* b, double m, double n, int nrhs, const T* 
   const T co = (T)(n * N2);
   const double gscale = gsum ? gamma / (double)b->n_s : 0.0;
   hipLaunchKernelGGL((k_lap<T, DIM, false>), dim3((b->nb + 4 * kLapBlocksPerWave - 1) / (4 * kLapBlocksPerWave)), dim3(256), 0, st, bview(b), u,
-                     a, v, ld, nrhs, cd, co, gsum, gscale, tune_of<T>(b).xcd, b->inst_coef);
+                     a, v, ld, nrhs, cd, co, gsum, gscale, tune_of<T>(b).xcd, b->inst_coef,
+                     b->inst_skip);
   CPM_LAUNCH_CHECK();
   if (ev) CPM_HIP(hipEventRecord(ev[3], st));
   if (b->n_lrows) {
     hipLaunchKernelGGL(k_lap_rows<T>, dim3(grid_for(b->n_lrows, 128)), dim3(128), 0, st,
                        b->n_lrows, 2 * DIM, b->lrow_id, b->lcol, u, a, v, ld, nrhs, cd, co, gsum,
-                       gscale, b->inst_coef, b->lrow_inst);
+                       gscale, b->inst_coef, b->lrow_inst, b->inst_skip);
     CPM_LAUNCH_CHECK();
   }
   if (ev) CPM_HIP(hipEventRecord(ev[4], st));
@@ -671,10 +686,14 @@ static void apply_T_dim(const cpm_band* b, double m, double n, int nrhs, const T
   const double N2 = (double)b->N * (double)b->N;
   const T co = (T)N2;
   // c = (L - diag L)^T w: symmetric bulk over every PDE row, then corrections
-  // (fill kernels, not memsets: this sequence may be captured into a graph)
-  hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(ld * nrhs, 256, 4096)), dim3(256), 0, st, c, ld * nrhs, T(0));
+  // (fill kernels, not memsets: this sequence may be captured into a graph);
+  // k_lap<ALL> writes every PDE entry, so only the BC entries need clearing
+  if (b->n_c)
+    for (int r = 0; r < nrhs; ++r)
+      hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(b->n_c, 256, 4096)), dim3(256), 0, st,
+                         c + r * ld + b->n_s, (int64_t)b->n_c, T(0));
   hipLaunchKernelGGL((k_lap<T, DIM, true>), dim3((b->nb + 4 * kLapBlocksPerWave - 1) / (4 * kLapBlocksPerWave)), dim3(256), 0, st, bview(b), w,
-                     w, c, ld, nrhs, T(0), co, nullptr, 0.0, tune_of<T>(b).xcd, nullptr);
+                     w, c, ld, nrhs, T(0), co, nullptr, 0.0, tune_of<T>(b).xcd, nullptr, nullptr);
   CPM_LAUNCH_CHECK();
   if (b->n_lrows) {
     hipLaunchKernelGGL(k_lap_rows_T<T>, dim3(grid_for(b->n_lrows, 128)), dim3(128), 0, st,
@@ -686,8 +705,8 @@ static void apply_T_dim(const cpm_band* b, double m, double n, int nrhs, const T
   hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(ld * nrhs, 256, 4096)), dim3(256), 0, st, e, ld * nrhs, T(0));
   if (b->ntiles)
     for (int r = 0; r < nrhs; ++r) {
-      hipLaunchKernelGGL((k_gather_T<T, DIM>), dim3(b->ntiles), dim3(256), 0, st, bview(b),
-                         tview(b), b->N, c, e, ld, r);
+      hipLaunchKernelGGL((k_gather_T<T, DIM>), dim3(b->ntiles), dim3(64), 0, st, bview(b),
+                         tview(b), b->N, c, e, ld, r, tune_of<T>(b).xcd);
       CPM_LAUNCH_CHECK();
     }
   if (b->n_erows) {

@@ -365,6 +365,10 @@ void build_composite(cpm_batch* B, hipStream_t st) {
   c->lrow_id = c->alloc<int>(nl);
   c->lcol = c->alloc<int>((size_t)nl * nf);
   c->lrow_inst = c->alloc<int>(nl);
+  c->erow_inst = c->alloc<int>(ne);
+  c->tile_inst = c->alloc<int>(nt);
+  c->inst_skip = c->alloc<int>(ni);
+  CPM_HIP(hipMemsetAsync(c->inst_skip, 0, sizeof(int) * ni, st));
   c->inst_coef = c->alloc<double>((size_t)2 * ni);
   int64_t ob = 0, ot = 0, otr = 0, oe = 0, ol = 0;
   auto g = [](int64_t n) { return dim3(grid_for(n, 256)); };
@@ -401,6 +405,10 @@ void build_composite(cpm_batch* B, hipStream_t st) {
                        c->lcol + ol * nf, (int64_t)b->n_lrows * nf, add);
     hipLaunchKernelGGL(k_fill_int, g(b->n_lrows), dim3(256), 0, st, c->lrow_inst + ol,
                        (int64_t)b->n_lrows, i);
+    hipLaunchKernelGGL(k_fill_int, g(b->n_erows), dim3(256), 0, st, c->erow_inst + oe,
+                       (int64_t)b->n_erows, i);
+    hipLaunchKernelGGL(k_fill_int, g(b->ntiles), dim3(256), 0, st, c->tile_inst + ot,
+                       (int64_t)b->ntiles, i);
     CPM_LAUNCH_CHECK();
     ob += b->nb;
     ot += b->ntiles;
@@ -572,6 +580,7 @@ struct BBicg {
         // restart the broken-down systems from their current iterate; the
         // others keep their recurrences (k_binit only touches active ones)
         ++restarts;
+        clear_skip();   // the restart's apply must cover every instance
         const std::vector<int> keep = hact;
         set_active(rs);
         hipLaunchKernelGGL(k_bset_active, dim3((B->nsys + 127) / 128), dim3(128), 0, st, S,
@@ -587,11 +596,31 @@ struct BBicg {
         continue;
       }
       if (all || it >= maxit) break;
+      update_skip(h);
       run(x, std::min(ce, maxit - it), graph && std::min(ce, maxit - it) == ce);
       h = read();
     }
+    clear_skip();
     return it;
   }
+  // instances whose systems are all done are skipped by the apply kernels
+  void update_skip(const BScal* h) {
+    std::vector<int> sk(B->ninst, 1);
+    for (int q = 0; q < B->nsys; ++q)
+      if (!h[q].done) sk[q % B->ninst] = 0;
+    if (sk != hskip) {
+      hskip = sk;
+      CPM_HIP(hipMemcpyAsync(B->comp->inst_skip, hskip.data(), sizeof(int) * B->ninst,
+                             hipMemcpyHostToDevice, st));
+      CPM_HIP(hipStreamSynchronize(st));
+    }
+  }
+  void clear_skip() {
+    hskip.assign(B->ninst, 0);
+    CPM_HIP(hipMemsetAsync(B->comp->inst_skip, 0, sizeof(int) * B->ninst, st));
+    CPM_HIP(hipStreamSynchronize(st));
+  }
+  std::vector<int> hskip;
 };
 
 }  // namespace

@@ -158,6 +158,9 @@ struct cpm_band {
   // coefficients (cd, co) of A, instance of each explicit FD row
   double* inst_coef = nullptr;
   int* lrow_inst = nullptr;
+  int* erow_inst = nullptr;           // instance of each explicit E row
+  int* tile_inst = nullptr;           // instance of each tile
+  int* inst_skip = nullptr;           // [instances] 1: skip (all its systems done)
   bool composite = false;
 
   int64_t on_c_nodes = 0, no_bc_dof_swaps = 0;

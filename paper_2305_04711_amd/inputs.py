@@ -13,13 +13,56 @@ from math import factorial, pi, sqrt
 import numpy as np
 
 
+class _Torch:
+    """The few numpy functions used below, for torch tensors (the same
+    formulas evaluated on the GPU for large inputs)."""
+
+    def __init__(self, torch):
+        self.t = torch
+
+    def asarray(self, a, dtype=None):
+        return a if isinstance(a, self.t.Tensor) else self.t.tensor(a, dtype=self.t.float64)
+
+    def sqrt(self, a):
+        return self.t.sqrt(a)
+
+    def arctan2(self, y, x):
+        return self.t.atan2(y, x)
+
+    def cos(self, a):
+        return self.t.cos(a)
+
+    def sin(self, a):
+        return self.t.sin(a)
+
+    def zeros_like(self, a):
+        return self.t.zeros_like(a)
+
+    def ones_like(self, a):
+        return self.t.ones_like(a)
+
+    def maximum0(self, a):
+        return self.t.clamp(a, min=0.0)
+
+
+def _xp(pts):
+    if type(pts).__module__.startswith("torch"):
+        import torch
+        return _Torch(torch)
+    return None
+
+
 # ---------------------------------------------------------------- sphere
-def _assoc_legendre(lmax, x):
+def _assoc_legendre(lmax, x, xp=None):
     """P[l][m](x) for 0 <= m <= l <= lmax, without the Condon-Shortley phase."""
-    x = np.asarray(x, dtype=np.float64)
-    s = np.sqrt(np.maximum(0.0, 1.0 - x * x))
+    if xp is None:
+        x = np.asarray(x, dtype=np.float64)
+        s = np.sqrt(np.maximum(0.0, 1.0 - x * x))
+        pmm = np.ones_like(x)
+    else:
+        s = xp.sqrt(xp.maximum0(1.0 - x * x))
+        pmm = xp.ones_like(x)
     P = [[None] * (lmax + 1) for _ in range(lmax + 1)]
-    pmm = np.ones_like(x)
     for m in range(lmax + 1):
         if m > 0:
             pmm = pmm * (2 * m - 1) * s
@@ -34,12 +77,17 @@ def _assoc_legendre(lmax, x):
 
 def real_sph_harm(lmax, pts, center=(0.0, 0.0, 0.0)):
     """Dict (l, m) -> values of the orthonormal real spherical harmonic at the
-    directions of pts - center.  m > 0 uses cos(m phi), m < 0 sin(|m| phi)."""
-    d = np.asarray(pts, dtype=np.float64) - np.asarray(center)
-    rr = np.sqrt(np.sum(d * d, axis=1))
-    ct = d[:, 2] / rr
-    phi = np.arctan2(d[:, 1], d[:, 0])
-    P = _assoc_legendre(lmax, ct)
+    directions of pts - center.  m > 0 uses cos(m phi), m < 0 sin(|m| phi).
+    pts may be a numpy array or a torch tensor."""
+    xp = _xp(pts)
+    M = np if xp is None else xp
+    d0 = pts[:, 0] - center[0]
+    d1 = pts[:, 1] - center[1]
+    d2 = pts[:, 2] - center[2]
+    rr = M.sqrt(d0 * d0 + d1 * d1 + d2 * d2)
+    ct = d2 / rr
+    phi = M.arctan2(d1, d0)
+    P = _assoc_legendre(lmax, ct, xp)
     out = {}
     for l in range(lmax + 1):
         for m in range(0, l + 1):
@@ -47,8 +95,8 @@ def real_sph_harm(lmax, pts, center=(0.0, 0.0, 0.0)):
             if m == 0:
                 out[(l, 0)] = nrm * P[l][0]
             else:
-                out[(l, m)] = sqrt(2.0) * nrm * P[l][m] * np.cos(m * phi)
-                out[(l, -m)] = sqrt(2.0) * nrm * P[l][m] * np.sin(m * phi)
+                out[(l, m)] = sqrt(2.0) * nrm * P[l][m] * M.cos(m * phi)
+                out[(l, -m)] = sqrt(2.0) * nrm * P[l][m] * M.sin(m * phi)
     return out
 
 
@@ -63,7 +111,8 @@ def sphere_field(coeffs, pts, center=(0.0, 0.0, 0.0), scale=None):
     """sum c_lm Y_lm at pts; scale(l) multiplies each degree if given."""
     lmax = max(l for l, _ in coeffs)
     Y = real_sph_harm(lmax, pts, center)
-    out = np.zeros(len(pts))
+    xp = _xp(pts)
+    out = np.zeros(len(pts)) if xp is None else xp.zeros_like(pts[:, 0])
     for (l, m), c in coeffs.items():
         out += (c if scale is None else c * scale(l)) * Y[(l, m)]
     return out
@@ -87,10 +136,14 @@ def circle_source(seed, pts, center=(0.0, 0.0)):
 # ---------------------------------------------------------------- torus
 def torus_angles(pts, R=1.0, center=(0.0, 0.0, 0.0)):
     """Toroidal angle phi (about the z axis) and poloidal angle theta."""
-    d = np.asarray(pts, dtype=np.float64) - np.asarray(center)
-    phi = np.arctan2(d[:, 1], d[:, 0])
-    qr = np.sqrt(d[:, 0] ** 2 + d[:, 1] ** 2)
-    theta = np.arctan2(d[:, 2], qr - R)
+    xp = _xp(pts)
+    M = np if xp is None else xp
+    d0 = pts[:, 0] - center[0]
+    d1 = pts[:, 1] - center[1]
+    d2 = pts[:, 2] - center[2]
+    phi = M.arctan2(d1, d0)
+    qr = M.sqrt(d0 * d0 + d1 * d1)
+    theta = M.arctan2(d2, qr - R)
     return phi, theta
 
 
@@ -106,11 +159,13 @@ def torus_coeffs(seed, kmax=4):
 
 
 def torus_field(coeffs, pts, R=1.0, center=(0.0, 0.0, 0.0)):
+    xp = _xp(pts)
+    M = np if xp is None else xp
     phi, theta = torus_angles(pts, R, center)
-    out = np.zeros(len(pts))
+    out = np.zeros(len(pts)) if xp is None else xp.zeros_like(phi)
     for (a, b), (cc, cs) in coeffs.items():
         ang = a * phi + b * theta
-        out += cc * np.cos(ang) + cs * np.sin(ang)
+        out = out + cc * M.cos(ang) + cs * M.sin(ang)
     return out
 
 
