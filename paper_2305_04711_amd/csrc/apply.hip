@@ -397,20 +397,35 @@ __device__ __forceinline__ void atomic_add(T* p, T v) {
   unsafeAtomicAdd(p, v);
 }
 
-// E^T c for the tile rows, one wavefront per tile: every row scatters
-// w c_i into the tile's (2 BX)^d cube in LDS (LDS atomics), then the cube is
-// added into z with one global atomic per band node of the staged blocks.
+// E^T c for the tile rows of one parity class, one wavefront per tile.  Each
+// lane first computes the stencil base and 1-D weights of one row (c_i folded
+// into the last factor) into LDS; then the wave walks the rows with one lane
+// per stencil member (4 rows at a time in 2-D, where a stencil has 16
+// members), adding w c_i into the tile's (2 BX)^d cube in LDS.  The cube is
+// accumulated in FP64 for both precisions: LDS FP64 atomic adds are several
+// times faster than FP32 ones on gfx950.  Lanes past the last row carry zero
+// weights, so the row loop has no branches.  The cube is then added into z
+// with plain loads and stores: tiles of one parity class stage disjoint
+// blocks and the classes run as successive launches, so no two waves of a
+// launch touch the same entry of z.
 template <class T, int DIM>
-__global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, int N,
-                                                 const T* __restrict__ c, T* __restrict__ z,
+__global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const int* __restrict__ list,
+                                                 int N, const T* __restrict__ c, T* __restrict__ z,
                                                  int64_t ld, int r, int xcd) {
   using G = Geo<DIM>;
   constexpr int E = Cube<DIM>::E, EP = E + 1, NQ = 1 << DIM;
   constexpr int CS = DIM == 3 ? E * E * EP : E * EP;
-  __shared__ T s_z[CS];
-  const int t = xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+  constexpr int M = DIM == 3 ? 64 : 16;       // stencil members
+  constexpr int RPI = 64 / M;                 // rows per wave instruction
+  constexpr int NW = DIM == 3 ? 12 : 8;       // 1-D weights per row
+  __shared__ double s_z[CS];
+  __shared__ T s_w[NW][64];                   // per-row 1-D weights, component major
+  __shared__ int s_b[64];                     // per-row cube offset of member 0
+  const int t = list[xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x];
   const int lane = threadIdx.x;
-  for (int idx = lane; idx < CS; idx += 64) s_z[idx] = T(0);
+  const int beg = tv.tile_start[t], end = tv.tile_start[t + 1];
+  if (beg == end) return;
+  for (int idx = lane; idx < CS; idx += 64) s_z[idx] = 0.0;
   unsigned long long qm = 0ull;
   int qoff = 0;
   if (lane < NQ) {
@@ -418,42 +433,78 @@ __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, int N
     qm = q.mask;
     qoff = q.off;
   }
-  __syncthreads();
-  const int end = tv.tile_start[t + 1];
-  for (int pos = tv.tile_start[t] + lane; pos < end; pos += 64) {
-    const T ci = c[r * ld + tv.perm[pos]];
-    if (ci == T(0)) continue;
-    int lb[3];
-    T tt[3];
-    row_stencil<T, DIM>(tv, pos, N, lb, tt);
-    T wx[4], wy[4], wz[4] = {T(1), T(0), T(0), T(0)};
-    lagrange4<T>(tt[0], wx);
-    lagrange4<T>(tt[1], wy);
-    if (DIM == 3) lagrange4<T>(tt[2], wz);
+  // this lane's stencil member and row slot within an instruction
+  const int mo = lane & (M - 1), sub = lane / M;
+  const int ma = mo & 3, mb = (mo >> 2) & 3, mc = DIM == 3 ? (mo >> 4) : 0;
+  const int moff = DIM == 3 ? (mc * E + mb) * EP + ma : mb * EP + ma;
+  for (int p0 = beg; p0 < end; p0 += 64) {
+    const int nrow = min(64, end - p0);
+    T wx[4] = {T(0), T(0), T(0), T(0)}, wy[4] = {T(0), T(0), T(0), T(0)};
+    T wz[4] = {T(0), T(0), T(0), T(0)};
+    int bs = 0;
+    if (lane < nrow) {
+      const int pos = p0 + lane;
+      const T ci = c[r * ld + tv.perm[pos]];
+      int lb[3];
+      T tt[3];
+      row_stencil<T, DIM>(tv, pos, N, lb, tt);
+      lagrange4<T>(tt[0], wx);
+      lagrange4<T>(tt[1], wy);
+      if (DIM == 3) {
+        lagrange4<T>(tt[2], wz);
 #pragma unroll
-    for (int cc = 0; cc < (DIM == 3 ? 4 : 1); ++cc) {
+        for (int k = 0; k < 4; ++k) wz[k] *= ci;
+      } else {
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const T wyz = (DIM == 3 ? wz[cc] : T(1)) * wy[b] * ci;
-        const int base = DIM == 3 ? ((lb[2] + cc) * E + (lb[1] + b)) * EP + lb[0]
-                                  : (lb[1] + b) * EP + lb[0];
-#pragma unroll
-        for (int aa = 0; aa < 4; ++aa) atomicAdd(&s_z[base + aa], wx[aa] * wyz);
+        for (int k = 0; k < 4; ++k) wy[k] *= ci;
       }
+      bs = DIM == 3 ? (lb[2] * E + lb[1]) * EP + lb[0] : lb[1] * EP + lb[0];
     }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      s_w[k][lane] = wx[k];
+      s_w[4 + k][lane] = wy[k];
+      if (DIM == 3) s_w[8 + k][lane] = wz[k];
+    }
+    s_b[lane] = bs;
+    __syncthreads();
+    constexpr int UR = 4;                     // rows per lane per step
+    const int nr = (nrow + UR * RPI - 1) / (UR * RPI) * (UR * RPI);
+    for (int j0 = 0; j0 < nr; j0 += UR * RPI) {
+      double v[UR];
+      int o[UR];
+#pragma unroll
+      for (int u = 0; u < UR; ++u) {
+        const int j = j0 + u * RPI + sub;
+        T w = s_w[ma][j] * s_w[4 + mb][j];
+        if (DIM == 3) w *= s_w[8 + mc][j];
+        v[u] = (double)w;
+        o[u] = s_b[j] + moff;
+      }
+#pragma unroll
+      for (int u = 0; u < UR; ++u) atomicAdd(&s_z[o[u]], v[u]);
+    }
+    __syncthreads();
   }
-  __syncthreads();
+  // all loads of z first, then the sums and stores, so that the wave waits
+  // for memory once rather than once per staged block
   const int cx0 = G::lx(lane), cy0 = G::ly(lane), cz0 = G::lz(lane);
+  T* dst[NQ];
+  T old[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const unsigned long long m = lane_u64(qm, q);
     const int off = lane_i32(qoff, q);
-    if (!((m >> lane) & 1ull)) continue;
+    dst[q] = ((m >> lane) & 1ull) ? z + r * ld + off + __popcll(m & ((1ull << lane) - 1ull))
+                                  : nullptr;
+    old[q] = dst[q] ? *dst[q] : T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
     const int qx = q & 1, qy = (q >> 1) & 1, qz = DIM == 3 ? (q >> 2) : 0;
     const int cx = qx * G::BX + cx0, cy = qy * G::BX + cy0, cz = qz * G::BX + cz0;
     const int ci = DIM == 3 ? (cz * E + cy) * EP + cx : cy * EP + cx;
-    const T val = s_z[ci];
-    if (val != T(0)) atomic_add(&z[r * ld + off + __popcll(m & ((1ull << lane) - 1ull))], val);
+    if (dst[q]) *dst[q] = old[q] + (T)s_z[ci];
   }
 }
 
@@ -703,12 +754,17 @@ static void apply_T_dim(const cpm_band* b, double m, double n, int nrhs, const T
   }
   // e = E^T c
   hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(ld * nrhs, 256, 4096)), dim3(256), 0, st, e, ld * nrhs, T(0));
-  if (b->ntiles)
-    for (int r = 0; r < nrhs; ++r) {
-      hipLaunchKernelGGL((k_gather_T<T, DIM>), dim3(b->ntiles), dim3(64), 0, st, bview(b),
-                         tview(b), b->N, c, e, ld, r, tune_of<T>(b).xcd);
-      CPM_LAUNCH_CHECK();
-    }
+  if (b->ntiles) {
+    if (!b->tile_col) CPM_FAIL(CPM_E_INVALID, "this band has no transpose schedule");
+    for (int r = 0; r < nrhs; ++r)
+      for (int k = 0; k < 8; ++k) {
+        const int cnt = b->col_start[k + 1] - b->col_start[k];
+        if (!cnt) continue;
+        hipLaunchKernelGGL((k_gather_T<T, DIM>), dim3(cnt), dim3(64), 0, st, bview(b), tview(b),
+                           b->tile_col + b->col_start[k], b->N, c, e, ld, r, tune_of<T>(b).xcd);
+        CPM_LAUNCH_CHECK();
+      }
+  }
   if (b->n_erows) {
     const int nm = DIM == 3 ? 64 : 16;
     hipLaunchKernelGGL(k_gather_rows_T<T>, dim3(grid_for((int64_t)b->n_erows * nm, 256)),

@@ -607,6 +607,16 @@ __global__ void k_tile_meta(Blocks B, int ntiles, int nq, int nnbr, const int* t
   meta[g] = m;
 }
 
+// Parity class of a tile's block: two tiles of one class stage disjoint
+// sets of blocks (their block coordinates differ by at least 2 along some
+// axis, and a tile stages its block and the next one along each axis).
+__global__ void k_tile_colour(int ntiles, const int* tile_blk, const int4* coord, int* colour) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  const int4 c = coord[tile_blk[t]];
+  colour[t] = (c.x & 1) | ((c.y & 1) << 1) | ((c.z & 1) << 2);
+}
+
 __global__ void k_blk_face(Blocks B, int nb, int dim, int nnbr, const unsigned long long* lrow_mask,
                            QMeta* face) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -958,6 +968,27 @@ void build(cpm_band* b, hipStream_t st) {
     hipLaunchKernelGGL(k_tile_meta, dim3(grid_for((int64_t)b->ntiles * 8, 256)), dim3(256), 0, st,
                        B, b->ntiles, 1 << DIM, G::NNBR, b->tile_blk, b->tile_meta);
   CPM_LAUNCH_CHECK();
+  // transpose schedule: tiles grouped by parity class (stable in tile order)
+  b->tile_col = b->alloc<int>(b->ntiles);
+  std::fill(b->col_start, b->col_start + 9, 0);
+  if (b->ntiles) {
+    Tmp<int> colour(b->ntiles);
+    hipLaunchKernelGGL(k_tile_colour, dim3(grid_for(b->ntiles, 256)), dim3(256), 0, st, b->ntiles,
+                       b->tile_blk, b->blk_coord, colour.p);
+    CPM_LAUNCH_CHECK();
+    std::vector<int> hcol(b->ntiles), order(b->ntiles);
+    CPM_HIP(hipMemcpyAsync(hcol.data(), colour.p, sizeof(int) * b->ntiles, hipMemcpyDeviceToHost,
+                           st));
+    CPM_HIP(hipStreamSynchronize(st));
+    for (int t = 0; t < b->ntiles; ++t) ++b->col_start[hcol[t] + 1];
+    for (int k = 0; k < 8; ++k) b->col_start[k + 1] += b->col_start[k];
+    int next[8];
+    std::copy(b->col_start, b->col_start + 8, next);
+    for (int t = 0; t < b->ntiles; ++t) order[next[hcol[t]]++] = t;
+    CPM_HIP(hipMemcpyAsync(b->tile_col, order.data(), sizeof(int) * b->ntiles,
+                           hipMemcpyHostToDevice, st));
+    CPM_HIP(hipStreamSynchronize(st));
+  }
   b->blk_face = b->alloc<QMeta>((size_t)nb * 8);
   hipLaunchKernelGGL(k_blk_face, dim3(grid_for((int64_t)nb * 8, 256)), dim3(256), 0, st, B, nb,
                      DIM, G::NNBR, b->lrow_mask, b->blk_face);

@@ -132,6 +132,10 @@ struct cpm_band {
   double* frac64 = nullptr;           // [dim][n_tile_rows] FP64 fractions
   float* frac32 = nullptr;            // [dim][n_tile_rows] FP32 fractions
   unsigned int* lbase = nullptr;      // [n_tile_rows] packed local base
+  // tiles grouped by the parity class of their block (k_tile_colour): class
+  // k is tile_col[col_start[k] .. col_start[k + 1])
+  int* tile_col = nullptr;            // [ntiles]
+  int col_start[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 
   // rows with explicit interpolation stencils (swapped PDE rows, BC rows)
   int n_erows = 0;
