@@ -172,7 +172,7 @@ cpm_status cpm_rhs_adjoint(const cpm_band* band, double n, int nrhs,
                            const double* lambda, double* grad_f,
                            double* grad_g, void* hip_stream);
 
-enum { CPM_SOLVE_MIXED = 0,  /* FP32 BiCGSTAB + FP64 iterative refinement */
+enum { CPM_SOLVE_MIXED = 0,  /* FP32 BiCGSTAB with FP64 reliable updates  */
        CPM_SOLVE_F64 = 1,    /* plain FP64 BiCGSTAB                        */
        CPM_SOLVE_GMRES = 2 };/* FP64 restarted GMRES(restart), classical
                                 Gram-Schmidt with one re-orthogonalisation  */
@@ -182,8 +182,11 @@ typedef struct {
   double tol;         /* stop when ||b - A x||_2 <= tol ||b||_2 (FP64)       */
   int mode;           /* CPM_SOLVE_MIXED or CPM_SOLVE_F64                    */
   int maxit;          /* cap on Krylov iterations in total (0 = 20000)       */
-  double inner_tol;   /* mixed: FP32 inner relative tolerance (0 = 1e-2); each
-                         refinement step runs at most 1000 FP32 iterations  */
+  double inner_tol;   /* mixed: reliable-update factor delta (0 = 0.1): once
+                         the FP32 recursive residual has dropped by delta
+                         since the last update, the FP32 partial solution is
+                         added into x in FP64 and the FP64 true residual
+                         replaces the recursive one                         */
   int check_every;    /* iterations between convergence read-backs (0 = 16)  */
   int use_graph;      /* 1: replay the check_every iterations as a hipGraph  */
   double gauge;       /* >0: solve (A + gauge 1 w^T) x = b, w = 1/n_s on PDE
@@ -193,10 +196,10 @@ typedef struct {
 
 typedef struct {
   int converged;
-  int outer_iters;    /* refinement steps (1 for CPM_SOLVE_F64)              */
+  int outer_iters;    /* FP64 residual evaluations (mixed: reliable updates) */
   int krylov_iters;   /* BiCGSTAB iterations in total                       */
   int restarts;       /* breakdown restarts                                 */
-  int fallback_f64;   /* mixed: inner solve fell back to FP64               */
+  int fallback_f64;   /* mixed: updates stalled, finished in plain FP64      */
   double relres;      /* final true FP64 relative residual (max over RHS)   */
   double time_ms;     /* wall time of the call                              */
 } cpm_solve_stats;

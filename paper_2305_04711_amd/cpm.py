@@ -239,7 +239,8 @@ def _solve(fn, band, b, m, n, tol, mode, x0, maxit, inner_tol, check_every, use_
 
 def solve(band, b, m, n, tol=1e-8, mode="mixed", x0=None, maxit=0, inner_tol=0.0,
           check_every=0, use_graph=True, gauge=0.0, raise_noconv=True, restart=0):
-    """Solve A x = b.  mode "mixed": FP32 BiCGSTAB + FP64 refinement; "f64":
+    """Solve A x = b.  mode "mixed": FP32 BiCGSTAB with FP64 reliable updates
+    (inner_tol = update factor delta, 0 = 0.1); "f64":
     plain FP64 BiCGSTAB; "gmres": FP64 GMRES(restart).  Returns (x, stats)."""
     return _solve(band._lib.cpm_solve, band, b, m, n, tol, mode, x0, maxit, inner_tol,
                   check_every, use_graph, gauge, raise_noconv, restart)

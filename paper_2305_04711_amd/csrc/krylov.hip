@@ -1,7 +1,8 @@
 // Krylov solvers on the device: unpreconditioned BiCGSTAB (van der Vorst; the
 // paper's solver follows Eigen's BiCGSTAB, Sec. 5.4) in FP64 or FP32, and
-// mixed precision: FP32 BiCGSTAB for the correction equation inside FP64
-// iterative refinement (residual and update in FP64).
+// mixed precision: FP32 BiCGSTAB with reliable updates (the FP32 partial
+// solution is added into the FP64 one and the FP64 true residual replaces
+// the recursive one), finished in FP64 where FP32 stops making progress.
 //
 // The recurrence scalars live in device memory.  Every reduction kernel
 // writes one partial sum per workgroup; the last workgroup to finish (found
@@ -185,17 +186,59 @@ __global__ __launch_bounds__(256) void k_xr(int64_t n, T* __restrict__ x, const 
     if (!__builtin_isfinite(tot[1])) {
       S->breakdown = 1;
       S->done = 1;
-    } else if (tot[1] <= S->tol2) {
-      S->done = 1;
     } else if (tot[0] == 0.0 || S->omega == 0.0) {
-      S->breakdown = 1;
       S->done = 1;
+      S->breakdown = tot[1] <= S->tol2 ? 0 : 1;
     } else {
+      // rho and beta are kept current also on the converging iteration, so
+      // that a residual replacement can continue the recurrence from here
       S->rho_old = S->rho;
       S->rho = tot[0];
       S->beta = (S->rho / S->rho_old) * (S->alpha / S->omega);
+      if (tot[1] <= S->tol2) S->done = 1;
     }
   }
+}
+
+// Residual replacement of the mixed-precision solver: r = r64 * inv (the
+// FP64 true residual, rescaled), x = 0 (the FP32 partial solution has been
+// added into the FP64 one), then rho = (rh, r) and beta from it, so the next
+// direction update p = r + beta (p - omega v) continues the recurrence with
+// the true residual in place of the recursive one.
+template <class T>
+__global__ __launch_bounds__(256) void k_replace(int64_t n, const double* __restrict__ r64, double inv,
+                                                 T* __restrict__ r, const T* __restrict__ rh,
+                                                 T* __restrict__ x, double* part, Scal* S) {
+  double acc[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kRedThreads) {
+    const T ri = (T)(r64[i] * inv);
+    r[i] = ri;
+    x[i] = T(0);
+    acc[0] += (double)rh[i] * (double)ri;
+    acc[1] += (double)ri * (double)ri;
+  }
+  double tot[2];
+  if (finish_reduction<2>(acc, part, S, tot) && threadIdx.x == 0) {
+    S->rr = tot[1];
+    if (!__builtin_isfinite(tot[0]) || !__builtin_isfinite(tot[1]) || tot[0] == 0.0 ||
+        S->rho_old == 0.0 || S->omega == 0.0) {
+      S->breakdown = 1;
+      S->done = 1;
+    } else {
+      S->rho = tot[0];
+      S->beta = (S->rho / S->rho_old) * (S->alpha / S->omega);
+      S->breakdown = 0;
+      S->done = tot[1] <= S->tol2 ? 1 : 0;
+    }
+  }
+}
+
+template <class T>
+__global__ void k_zero(int64_t n, T* __restrict__ x) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = T(0);
 }
 
 // p = r + beta (p - omega v)
@@ -229,20 +272,25 @@ __global__ __launch_bounds__(256) void k_res64(int64_t n, const double* __restri
   }
 }
 
-__global__ void k_to32(int64_t n, const double* __restrict__ r, float* __restrict__ r32,
-                       float* __restrict__ d32, double inv) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    r32[i] = (float)(r[i] * inv);
-    d32[i] = 0.0f;
-  }
-}
-
-__global__ void k_add32(int64_t n, double* __restrict__ x, const float* __restrict__ d, double scale) {
+// x += scale * d (FP64 accumulation of a partial solution of either precision)
+template <class T>
+__global__ void k_addT(int64_t n, double* __restrict__ x, const T* __restrict__ d, double scale) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     x[i] += scale * (double)d[i];
 }
+
+// out = (T)(r * inv), d = 0
+template <class T>
+__global__ void k_scaleT(int64_t n, const double* __restrict__ r, double inv, T* __restrict__ out,
+                         T* __restrict__ d) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    out[i] = (T)(r[i] * inv);
+    d[i] = T(0);
+  }
+}
+
 
 __global__ void k_set_it(Scal* S, int it) {
   if (threadIdx.x == 0) S->it = it;
@@ -387,21 +435,33 @@ struct Bicg {
     else apply_impl<T>(b, m, nn, 1, in, out, st, nullptr, gamma);
   }
 
+  // r = rhs - A x, rh = p = r, v = 0, beta = 0 (so the first direction
+  // update of an iteration leaves p = r)
   void init(const T* rhs, const T* x, bool x_zero, double tol) {
     if (!x_zero) apply(x, v);
     hipLaunchKernelGGL(k_init<T>, dim3(red_g), dim3(kRedThreads), 0, st, n, rhs, v, !x_zero, r,
                        rh, p, part, S, tol);
+    hipLaunchKernelGGL(k_zero<T>, dim3(ew_grid), dim3(256), 0, st, n, v);
     CPM_LAUNCH_CHECK();
   }
 
+  // One BiCGSTAB step, starting with the direction update so that a step
+  // ends right after the new residual (where a replacement can take place).
   void iteration(T* x) {
+    hipLaunchKernelGGL(k_p<T>, dim3(ew_grid), dim3(256), 0, st, n, r, p, v, S);
     apply(p, v);
     hipLaunchKernelGGL(k_dot_rv<T>, dim3(red_g), dim3(kRedThreads), 0, st, n, rh, v, part, S);
     hipLaunchKernelGGL(k_s<T>, dim3(ew_grid), dim3(256), 0, st, n, r, v, s, S);
     apply(s, t);
     hipLaunchKernelGGL(k_dot_ts<T>, dim3(red_g), dim3(kRedThreads), 0, st, n, t, s, part, S);
     hipLaunchKernelGGL(k_xr<T>, dim3(red_g), dim3(kRedThreads), 0, st, n, x, p, s, t, r, rh, part, S);
-    hipLaunchKernelGGL(k_p<T>, dim3(ew_grid), dim3(256), 0, st, n, r, p, v, S);
+    CPM_LAUNCH_CHECK();
+  }
+
+  // residual replacement (see k_replace); x is the partial solution vector
+  void replace(const double* r64, double inv, T* x) {
+    hipLaunchKernelGGL(k_replace<T>, dim3(red_g), dim3(kRedThreads), 0, st, n, r64, inv, r, rh, x,
+                       part, S);
     CPM_LAUNCH_CHECK();
   }
 
@@ -439,31 +499,18 @@ struct Bicg {
   }
 
   // Solve A x = rhs to the recursive residual tol (relative).  Returns the
-  // iterations spent; breakdowns restart from the current iterate.  With
-  // xbest, the iterate of smallest recursive residual seen at a check is kept
-  // and returned when the solve ends unconverged, and the solve stops early
-  // once the residual exceeds diverge * ||rhs|| (FP32 BiCGSTAB on badly
-  // conditioned systems can diverge after a long plateau).
+  // iterations spent; breakdowns restart from the current iterate.
   int solve(const T* rhs, T* x, bool x_zero, double tol, int maxit, int check_every,
-            bool use_graph, int* restarts, T* xbest = nullptr, double diverge = 0.0) {
+            bool use_graph, int* restarts) {
     hipLaunchKernelGGL(k_zero_scal, dim3(1), dim3(64), 0, st, S);
     init(rhs, x, x_zero, tol);
     int it = 0;
     const Scal* h = &read();
-    double best = h->rr;
-    bool have_best = false;
-    const size_t vb = sizeof(T) * (size_t)n;
     while (!h->done && it < maxit) {
       const int k = std::min(check_every, maxit - it);
       run_iters(x, k, use_graph && k == check_every);
       h = &read();
       it = h->it;
-      if (xbest && !h->done && h->rr < best) {
-        CPM_HIP(hipMemcpyAsync(xbest, x, vb, hipMemcpyDeviceToDevice, st));
-        best = h->rr;
-        have_best = true;
-      }
-      if (diverge > 0.0 && !(h->rr <= diverge * diverge * h->bb)) break;
       if (h->done && h->breakdown && !(h->rr <= h->tol2)) {
         if (++*restarts > 50) break;
         const int keep = h->it;
@@ -474,11 +521,6 @@ struct Bicg {
         h = &read();
       }
     }
-    const bool converged = h->done && h->rr <= h->tol2;
-    if (xbest && have_best && !converged && !(h->rr <= best))
-      CPM_HIP(hipMemcpyAsync(x, xbest, vb, hipMemcpyDeviceToDevice, st));
-    else if (xbest && !have_best && !converged && x_zero && !(h->rr <= best))
-      CPM_HIP(hipMemsetAsync(x, 0, vb, st));   // nothing better than the zero start
     return h->it;
   }
 };
@@ -607,6 +649,81 @@ void gmres64(const cpm_band* b, const cpm_solve_opts& o, const double* rhs, doub
   stt.converged = rel <= tol ? 1 : 0;
 }
 
+// Shared state of a reliable-update solve of A x = rhs: the recurrence runs
+// on A d = r0 / sigma; x accumulates sigma d in FP64.
+struct RU {
+  const cpm_band* b;
+  hipStream_t st;
+  double m, nn, gamma;
+  bool tr;
+  const double* rhs;
+  double* x;
+  double *r64, *v64, *part;
+  Scal* S;
+  Pinned* pin;
+  double bn, sigma, delta, tol;
+  int maxit, ce;
+  bool graph;
+  cpm_solve_stats* stt;
+  int its = 0;
+
+  std::pair<double, double> residual() {
+    return residual64(b, st, m, nn, gamma, tr, rhs, x, r64, v64, part, S, *pin);
+  }
+};
+
+enum { RU_CONVERGED = 0, RU_STALLED = 1, RU_MAXIT = 2, RU_NONFINITE = 3 };
+
+// Runs a recurrence of precision T with reliable updates until the FP64
+// residual reaches tol.  An update happens when the recursive residual has
+// dropped by delta since the last one, when the recurrence stops (converged
+// or broken down), or after max_cycle iterations without either.  It adds
+// sigma d into x, recomputes r = b - A x in FP64 and substitutes it for the
+// recursive residual (k_replace).  The run ends (RU_STALLED, with x and r64
+// current) at the first update that fails to halve the FP64 residual of the
+// previous one, that follows a breakdown, or whose recursive residual
+// underestimates the true one by more than 1.5x.
+template <class T>
+int ru_run(RU& c, Bicg<T>& k, T* d, double rn, int max_cycle) {
+  const int64_t n = c.b->n;
+  const double inv = 1.0 / c.sigma;
+  const int eg = grid_for(n, 256, 4096);
+  double maxr = rn * inv, prev = rn;
+  int last = k.read().it, cycle0 = last;
+  while (c.its < c.maxit) {
+    const int kk = std::min(c.ce, c.maxit - c.its);
+    k.run_iters(d, kk, c.graph && kk == c.ce);
+    const Scal& h = k.read();
+    c.its += h.it - last;
+    last = h.it;
+    const double rrec = std::sqrt(h.rr);
+    const bool bad = !__builtin_isfinite(h.rr);
+    if (!bad) maxr = std::max(maxr, rrec);
+    if (!(h.done || bad || rrec < c.delta * maxr || h.it - cycle0 >= max_cycle)) continue;
+    const bool broken = h.breakdown || bad;
+    if (!bad) {   // a non-finite recursion leaves x as it was at the last update
+      hipLaunchKernelGGL(k_addT<T>, dim3(eg), dim3(256), 0, c.st, n, c.x, d, c.sigma);
+      CPM_LAUNCH_CHECK();
+    }
+    auto rb = c.residual();
+    rn = rb.first;
+    c.stt->relres = rn / c.bn;
+    ++c.stt->outer_iters;
+    if (trace_on())
+      std::fprintf(stderr, "[cpm] %s update %d: recursive %.3e true relres %.3e its %d%s\n",
+                   sizeof(T) == 4 ? "FP32" : "FP64", c.stt->outer_iters, rrec * c.sigma / c.bn,
+                   c.stt->relres, c.its, broken ? " (breakdown)" : "");
+    if (c.stt->relres <= c.tol) return RU_CONVERGED;
+    if (!__builtin_isfinite(rn)) return RU_NONFINITE;
+    if (broken || !(rn < 0.5 * prev) || rn > 1.5 * rrec * c.sigma) return RU_STALLED;
+    prev = rn;
+    maxr = rn * inv;
+    cycle0 = h.it;
+    k.replace(c.r64, inv, d);
+  }
+  return RU_MAXIT;
+}
+
 void solve_one(const cpm_band* b, const cpm_solve_opts& o, const double* rhs, double* x,
                cpm_solve_stats& stt, hipStream_t st, bool tr) {
   if (o.mode == CPM_SOLVE_GMRES) {
@@ -641,62 +758,49 @@ void solve_one(const cpm_band* b, const cpm_solve_opts& o, const double* rhs, do
     }
     return false;
   };
+  // Mixed precision: one FP32 BiCGSTAB recurrence on A d = r0 / sigma with
+  // reliable updates (ru_run): the solution accumulates in FP64 and
+  // convergence is decided on the FP64 residual only.  Rounding a smooth
+  // vector to FP32 perturbs A p by about eps32 ||A|| ||p||, which bounds the
+  // residual reduction the FP32 recurrence can deliver (about four decades
+  // for the Laplacian at h = 1/512); at the first update that shows it, the
+  // solve continues with FP64 BiCGSTAB from the refined x.
+  auto mixed_ru = [&]() {
+    RU c{b, st, o.m, o.n, gamma, tr, rhs, x, r64, v64, part, S, &pin};
+    auto rb = c.residual();
+    c.bn = rb.second;
+    const double rn = rb.first;
+    stt.relres = c.bn > 0 ? rn / c.bn : 0.0;
+    if (c.bn == 0.0 || stt.relres <= tol) return true;
+    if (!__builtin_isfinite(rn)) return false;
+    c.sigma = rn;
+    c.delta = o.inner_tol > 0 ? o.inner_tol : 0.1;
+    c.tol = tol;
+    c.maxit = maxit;
+    c.ce = ce;
+    c.graph = graph;
+    c.stt = &stt;
+    const double inv = 1.0 / c.sigma;
+    Bicg<float> k32(b, st, o.m, o.n, gamma, tr, 10);
+    float* r32 = (float*)band_scratch(b, 24, sizeof(float) * n);
+    float* d32 = (float*)band_scratch(b, 25, sizeof(float) * n);
+    hipLaunchKernelGGL(k_scaleT<float>, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, n, r64,
+                       inv, r32, d32);
+    hipLaunchKernelGGL(k_zero_scal, dim3(1), dim3(64), 0, st, k32.S);
+    CPM_LAUNCH_CHECK();
+    k32.init(r32, d32, true, 0.5 * tol * c.bn * inv);
+    const int status = ru_run<float>(c, k32, d32, rn, 400);
+    its += c.its;
+    if (status == RU_CONVERGED) return true;
+    if (status == RU_MAXIT) return false;
+    stt.fallback_f64 = 1;
+    return plain64(tol);
+  };
   bool ok = false;
   if (o.mode == CPM_SOLVE_F64) {
     ok = plain64(tol);
   } else {
-    const double itol = o.inner_tol > 0 ? o.inner_tol : 1e-2;
-    const int inner_cap = 1000;
-    Bicg<float> k(b, st, o.m, o.n, gamma, tr, 10);
-    float* r32 = (float*)band_scratch(b, 24, sizeof(float) * n);
-    float* d32 = (float*)band_scratch(b, 25, sizeof(float) * n);
-    float* dbest = (float*)band_scratch(b, 26, sizeof(float) * n);
-    double prev = HUGE_VAL;
-    int stall = 0;
-    for (int outer = 0; outer < 100; ++outer) {
-      auto rb = residual64(b, st, o.m, o.n, gamma, tr, rhs, x, r64, v64, part, S, pin);
-      const double rel = rb.second > 0 ? rb.first / rb.second : 0.0;
-      stt.relres = rel;
-      if (rel <= tol || rb.second == 0.0) {
-        ok = true;
-        break;
-      }
-      if (its >= maxit) break;
-      if (rel > 0.5 * prev) ++stall;
-      else stall = 0;
-      if (stall >= 2 || !__builtin_isfinite(rel)) {
-        stt.fallback_f64 = 1;
-        ok = plain64(tol);
-        break;
-      }
-      prev = rel;
-      hipLaunchKernelGGL(k_to32, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, n, r64, r32, d32,
-                         1.0 / rb.first);
-      CPM_LAUNCH_CHECK();
-      const int inner = k.solve(r32, d32, true, itol, std::min(inner_cap, maxit - its), ce, graph,
-                                &restarts, dbest, 10.0);
-      its += inner;
-      const Scal& hk = k.read();
-      // an inner FP32 solve that diverged (or stopped unconverged) marks the
-      // limit of FP32 accuracy for this system: apply its best iterate, then
-      // finish in FP64 from the refined x
-      const bool inner_failed = !(hk.done && hk.rr <= hk.tol2);
-      if (trace_on()) {
-        const Scal& h = k.read();
-        std::fprintf(stderr, "[cpm] outer %d relres %.3e inner its %d inner rr %.3e done %d "
-                     "breakdown %d restarts %d\n", outer, rel, inner, h.rr, h.done, h.breakdown,
-                     restarts);
-      }
-      hipLaunchKernelGGL(k_add32, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, n, x, d32,
-                         rb.first);
-      CPM_LAUNCH_CHECK();
-      ++stt.outer_iters;
-      if (inner_failed) {
-        stt.fallback_f64 = 1;
-        ok = plain64(tol);
-        break;
-      }
-    }
+    ok = mixed_ru();
   }
   stt.krylov_iters += its;
   stt.restarts += restarts;
