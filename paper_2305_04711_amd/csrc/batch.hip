@@ -27,7 +27,7 @@ struct BScal {
   unsigned pad;
 };
 
-constexpr int kChunk = 2048;   // elements per reduction workgroup (256 x 8)
+constexpr int kChunk = 32768;  // elements per reduction workgroup (256 x 128)
 constexpr int kBT = 256;
 
 // ---------------------------------------------------------------- concat
@@ -774,7 +774,9 @@ extern "C" cpm_status cpm_batch_solve(cpm_batch* b, const cpm_solve_opts* o, con
                            scale, r32, d32);
         CPM_LAUNCH_CHECK();
         k.set_active(active);
-        k.solve(r32, d32, true, itol, 1000, ce, graph);
+        // FP32 resolves a few decades at most on these systems; a step that
+        // has not reached itol within 250 iterations hands its system over
+        k.solve(r32, d32, true, itol, 250, ce, graph);
         const BScal* h = k.read();
         for (int q = 0; q < ns; ++q) {
           if (!active[q]) continue;
