@@ -10,12 +10,15 @@ Timed step: one FP64 application of A = m I + n [diag L + (L - diag L) E]
 (m = 0, n = -1: Poisson) to a vector resident in HBM; value = DOFs / step
 time in Gnodes/s.  Also reported on the same line: the FP32 apply rate, the
 per-phase time of the apply from HIP events on its stream, the roofline of
-the dominant kernel (the tile gather), the time to a relative residual of
-1e-8 for the mixed-precision and the plain FP64 solve, the band build time,
-and the FP64 CPU oracle timed on the host (cpu_baseline).
+the dominant kernel (the tile gather), the transposed apply, the time to a
+relative residual of 1e-8 for the mixed-precision and the plain FP64 solve,
+the differentiable solve (forward, and backward through the adjoint solve),
+the batched uneven solves (32 spheres and tori, h = 1/64 .. 1/192, 3
+right-hand sides each) against one FP64 solve per instance, the band build
+time, and the FP64 CPU oracle timed on the host (cpu_baseline).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-solve]
-       [--no-cpu] [--N 512]
+       [--no-cpu] [--no-batch] [--no-adjoint] [--N 512]
 """
 
 import argparse
@@ -30,6 +33,24 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
 BYTES_PER_ROW_F64 = 40.0   # tile gather: cp_S 24 + u 8 + a 8 (FP64)
 BYTES_PER_ROW_F32 = 24.0   # tile gather: fraction 12 + base 4 + u 4 + a 4 (FP32)
+
+# HBM bytes per launch of the FP64 tile gather on this workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; summaries and commands in
+# profiles/gather_torus512_pmc.md), each scaled by the same counter's reading
+# for a plain device copy of known size.  They hold only for the kernel
+# sources they were taken on: `traffic` is null when the hash differs.
+GATHER_PMC = {"sources_sha1": None, "fetch_bytes": None, "write_bytes": None}
+GATHER_SOURCES = ["paper_2305_04711_amd/csrc/apply.hip", "paper_2305_04711_amd/csrc/cpm_internal.hpp",
+                  "paper_2305_04711_amd/csrc/lagrange.hpp"]
+
+
+def gather_sources_sha1():
+    import hashlib
+    h = hashlib.sha1()
+    for f in GATHER_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def log(*a):
@@ -117,6 +138,9 @@ def run_batch(dev, args):
     torch.cuda.synchronize()
     out["sequential_f64"] = {"seconds": time.perf_counter() - t, "converged": conv,
                              "max_relres": worst}
+    out["speedup_vs_sequential_f64"] = {
+        mode: out["sequential_f64"]["seconds"] / out["batched_" + mode]["seconds"]
+        for mode in ("mixed", "f64")}
     log("sequential f64: %s" % out["sequential_f64"])
     del batch, bands
     return out
@@ -199,6 +223,30 @@ def main():
     log("apply f64 %.4f ms (%.2f Gnodes/s), phases %s" % (dt64 * 1e3, band.n / dt64 / 1e9, ph64))
     log("apply f32 %.4f ms (%.2f Gnodes/s), phases %s" % (dt32 * 1e3, band.n / dt32 / 1e9, ph32))
 
+    def transpose_once(u, v, code):
+        st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        r = lib.cpm_apply_transpose(h, m, n, code, 1, C.c_void_p(u.data_ptr()),
+                                    C.c_void_p(v.data_ptr()), st)
+        if r != 0:
+            raise RuntimeError(lib.cpm_last_error().decode())
+
+    def timed_T(u, v, code, reps=10):
+        for _ in range(2):
+            transpose_once(u, v, code)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            transpose_once(u, v, code)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps
+
+    dtT64 = timed_T(u64, v64, 0)
+    dtT32 = timed_T(u32, v32, 1)
+    log("transpose apply f64 %.4f ms, f32 %.4f ms" % (dtT64 * 1e3, dtT32 * 1e3))
+    traffic = None
+    if GATHER_PMC["sources_sha1"] is not None and GATHER_PMC["sources_sha1"] == gather_sources_sha1():
+        traffic = GATHER_PMC["fetch_bytes"] + GATHER_PMC["write_bytes"]
+
     solves = None
     if not args.no_solve:
         cp = band.cp()
@@ -206,16 +254,24 @@ def main():
         g = torch.tensor(inputs.meridian_dirichlet(band.bc_cpc(), seed=2), device=dev)
         b = cpm.rhs(band, f, g, n)
         solves = {}
+        xs = {}
         for mode in ("mixed", "f64"):
             torch.cuda.synchronize()
             t = time.perf_counter()
             x, st = cpm.solve(band, b, m, n, tol=1e-8, mode=mode, raise_noconv=False)
             torch.cuda.synchronize()
+            xs[mode] = x
             solves[mode] = {"seconds": time.perf_counter() - t, "converged": bool(st["converged"]),
                             "relres": st["relres"], "krylov_iters": st["krylov_iters"],
                             "outer_iters": st["outer_iters"],
                             "fallback_f64": bool(st["fallback_f64"])}
             log("solve %s: %s" % (mode, solves[mode]))
+        # both solutions meet the same residual; their difference reflects
+        # the conditioning of A at this h, not a precision loss
+        solves["mixed_vs_f64_rel_linf"] = ((xs["mixed"] - xs["f64"]).abs().max()
+                                           / xs["f64"].abs().max()).item()
+        solves["speedup_mixed"] = solves["f64"]["seconds"] / solves["mixed"]["seconds"]
+        del xs
 
     adjoint = None
     if not args.no_solve and not args.no_adjoint:
@@ -269,12 +325,13 @@ def main():
                    "n_s": band.n_s, "n_c": band.n_c, "dofs": band.n},
         "roofline": {"bound": "hbm", "kernel": "k_gather<double,3,1> (tile gather a = E u)",
                      "achieved": ach64, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach64 / HBM_PEAK_GBS, "traffic": None,
+                     "frac": ach64 / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_row": BYTES_PER_ROW_F64, "rows_per_launch": tile_rows,
                      "launch_ms": ph64[0]},
         "cpu_baseline": base,
         "apply_f32": {"gnodes_per_s": band.n / dt32 / 1e9, "ms": dt32 * 1e3,
                       "gather_gbs": ach32, "gather_frac": ach32 / HBM_PEAK_GBS},
+        "transpose_apply_ms": {"f64": dtT64 * 1e3, "f32": dtT32 * 1e3},
         "apply_phase_ms": {"f64": ph64, "f32": ph32,
                            "order": ["tile gather", "explicit E rows", "block Laplacian",
                                      "explicit L rows"]},

@@ -129,9 +129,13 @@ __device__ __forceinline__ void row_stencil<float, 2>(const TileView& tv, int po
 // padded by PAD elements to spread LDS banks), then each lane interpolates
 // rows of the tile (sum-factorised tensor product).  The staged blocks' masks
 // and first DOFs come from the tile's metadata in one load.
+// At most 6 waves per SIMD keeps the FP64 variant's register use in check
+// (left to itself the compiler hoists every LDS read of a row and the
+// occupancy drops to 4 waves per SIMD, about 1.5x slower).
 template <class T, int DIM, int NR, int PAD>
-__global__ __launch_bounds__(64) void k_gather(BlockView B, TileView tv, int N, const T* __restrict__ u,
-                                               T* __restrict__ a, int64_t ld, int xcd) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void k_gather(
+    BlockView B, TileView tv, int N, const T* __restrict__ u, T* __restrict__ a, int64_t ld,
+    int xcd) {
   using G = Geo<DIM>;
   constexpr int E = Cube<DIM>::E, EP = E + PAD, NQ = 1 << DIM;
   constexpr int CS = DIM == 3 ? E * E * EP : E * EP;
@@ -147,6 +151,12 @@ __global__ __launch_bounds__(64) void k_gather(BlockView B, TileView tv, int N, 
     qoff = q.off;
   }
   const int cx0 = G::lx(lane), cy0 = G::ly(lane), cz0 = G::lz(lane);
+  // the first pass's row data is requested before the staging loads, and
+  // every pass requests the next pass's before interpolating
+  const int beg = tv.tile_start[t], end = tv.tile_start[t + 1];
+  int lb[3] = {0, 0, 0};
+  T tt[3] = {T(0), T(0), T(0)};
+  if (beg + lane < end) row_stencil<T, DIM>(tv, beg + lane, N, lb, tt);
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const unsigned long long m = lane_u64(qm, q);
@@ -160,15 +170,14 @@ __global__ __launch_bounds__(64) void k_gather(BlockView B, TileView tv, int N, 
     for (int r = 0; r < NR; ++r) s_u[r][ci] = on ? u[r * ld + dof] : T(0);
   }
   __syncthreads();
-  const int end = tv.tile_start[t + 1];
-  for (int pos = tv.tile_start[t] + lane; pos < end; pos += 64) {
-    int lb[3];
-    T tt[3];
-    row_stencil<T, DIM>(tv, pos, N, lb, tt);
+  for (int pos = beg + lane; pos < end; pos += 64) {
     T wx[4], wy[4], wz[4];
     lagrange4<T>(tt[0], wx);
     lagrange4<T>(tt[1], wy);
     if (DIM == 3) lagrange4<T>(tt[2], wz);
+    const int lx = lb[0], ly = lb[1], lz = lb[2];
+    const int dof = tv.perm[pos];
+    if (pos + 64 < end) row_stencil<T, DIM>(tv, pos + 64, N, lb, tt);
     T acc[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r] = T(0);
@@ -180,7 +189,7 @@ __global__ __launch_bounds__(64) void k_gather(BlockView B, TileView tv, int N, 
         for (int r = 0; r < NR; ++r) accz[r] = T(0);
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-          const int base = ((lb[2] + c) * E + (lb[1] + b)) * EP + lb[0];
+          const int base = ((lz + c) * E + (ly + b)) * EP + lx;
 #pragma unroll
           for (int r = 0; r < NR; ++r) {
             const T* row = &s_u[r][base];
@@ -194,7 +203,7 @@ __global__ __launch_bounds__(64) void k_gather(BlockView B, TileView tv, int N, 
     } else {
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        const int base = (lb[1] + b) * EP + lb[0];
+        const int base = (ly + b) * EP + lx;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
           const T* row = &s_u[r][base];
@@ -203,7 +212,6 @@ __global__ __launch_bounds__(64) void k_gather(BlockView B, TileView tv, int N, 
         }
       }
     }
-    const int dof = tv.perm[pos];
 #pragma unroll
     for (int r = 0; r < NR; ++r) a[r * ld + dof] = acc[r];
   }
@@ -244,7 +252,7 @@ __global__ __launch_bounds__(256) void k_gather_rows(int nrows, int nm, const in
 // and first DOFs, and the explicit-row mask), broadcast with readlane, so each
 // lane finds its neighbours' DOFs by arithmetic.  ALL = false skips rows with
 // explicit FD stencils; ALL = true (transpose) visits every PDE row.
-constexpr int kLapBlocksPerWave = 4;
+constexpr int kLapBlocksPerWave = 2;
 
 template <class T, int DIM, bool ALL>
 __global__ __launch_bounds__(256) void k_lap(BlockView B, const T* __restrict__ u,
