@@ -100,6 +100,7 @@ def run_batch(dev, args):
     nrhs = 3
     batch = cpm.Batch(bands, [1.0] * 32, [-1.0] * 32, nrhs=nrhs)
     tune = batch.autotune(torch.float32)
+    tune64 = batch.autotune(torch.float64)
     b = torch.empty(nrhs, batch.total, dtype=torch.float64, device=dev)
     for k, band in enumerate(bands):
         cp = torch.tensor(band.cp(), device=dev)
@@ -112,7 +113,7 @@ def run_batch(dev, args):
             b[r, lo:hi] = fv
     out = {"instances": 32, "nrhs": nrhs, "dofs_total": batch.total,
            "dofs_min": min(bd.n for bd in bands), "dofs_max": max(bd.n for bd in bands),
-           "build_s": build_s, "autotune_f32": tune}
+           "build_s": build_s, "autotune_f32": tune, "autotune_f64": tune64}
     for mode in ("mixed", "f64"):
         torch.cuda.synchronize()
         t = time.perf_counter()
