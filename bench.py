@@ -39,7 +39,8 @@ BYTES_PER_ROW_F32 = 24.0   # tile gather: fraction 12 + base 4 + u 4 + a 4 (FP32
 # profiles/gather_torus512_pmc.md), each scaled by the same counter's reading
 # for a plain device copy of known size.  They hold only for the kernel
 # sources they were taken on: `traffic` is null when the hash differs.
-GATHER_PMC = {"sources_sha1": None, "fetch_bytes": None, "write_bytes": None}
+GATHER_PMC = {"sources_sha1": "3a0b2d07d43a9a45c7f2062ae8767b4696585926",
+              "fetch_bytes": 1.72562e+09, "write_bytes": 3.40212e+08}
 GATHER_SOURCES = ["paper_2305_04711_amd/csrc/apply.hip", "paper_2305_04711_amd/csrc/cpm_internal.hpp",
                   "paper_2305_04711_amd/csrc/lagrange.hpp"]
 
