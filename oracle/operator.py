@@ -26,6 +26,13 @@ Interior boundaries (Sec. 4.3), with the readings below:
     with cpbar_C(x) = cp_S(2 cp_C(x) - x) (eq. cpc-bar), the mirror stencil's
     member m stays a BC DOF when on the director's side and in Omega(C), and
     is the PDE DOF otherwise.
+  * BC row E, zero Neumann (Sec. 4.3, eq. IBC-1st-order-Neumann and eq.
+    cpc-bar): u_alpha = u(y) interpolated at y = cp_C(x) (first order) or
+    y = cpbar_C(x) (second order), members chosen as for the Dirichlet mirror
+    row, no constant.
+  * Each side of a C carries its own condition (Sec. 4.2, mixed IBCs).  A BC
+    DOF whose node lies on side s stands in for side -s (a stencil of side -s
+    swaps to it), so it takes the condition of side -s.
   * Every row (PDE and BC) uses the stabilised form M = diag L + (L - diag L)E;
     the Dirichlet constants e of E move to the right-hand side:
     A u = f - n (L - diag L) e.
@@ -97,13 +104,16 @@ def face_offsets(dim):
 
 class CPMSystem:
     """The discrete CPM system for one surface, one grid and a list of
-    interior Dirichlet boundaries.
+    interior boundaries; bc_types[c] = (condition of side +1, of side -1),
+    each "dirichlet" or "neumann" (default: Dirichlet on both sides).
 
     Attributes
       K, CP        PDE nodes (lexicographic) and their stored cp_S
       n_s, n_c     numbers of PDE and BC DOFs
       E, L         (n, n) CSR, n = n_s + n_c, linear parts only
-      e_coef       (n_c,) multiplier of g in the constant of E (1 or 2)
+      e_coef       (n_c,) multiplier of g in the constant of E (Dirichlet:
+                   1 or 2 by order; Neumann: 0)
+      bc_kind      (n_c,) condition of each BC DOF (0 Dirichlet, 1 Neumann)
       bc_node      (n_c,) PDE DOF of the node each BC DOF sits on
       bc_curve     (n_c,) index of the C each BC DOF belongs to
       bc_cpc       (n_c, d) cp_C of the node (where the Dirichlet value is read)
@@ -112,7 +122,7 @@ class CPMSystem:
     """
 
     def __init__(self, surface, N, ibcs=(), order=2, p=3, q=1, r=None,
-                 tau_factor=0.1, check_factor=2.0):
+                 tau_factor=0.1, check_factor=2.0, bc_types=None):
         if p != 3:
             raise ValueError("only cubic interpolation (p = 3) is implemented")
         d = surface.dim
@@ -161,7 +171,17 @@ class CPMSystem:
                        if self.sets else np.zeros((0, d)))
         self.bc_side = (np.concatenate([s.side[s.omega_nodes] for s in self.sets])
                         if self.sets else np.zeros(0, np.int64))
-        self.e_coef = np.full(self.n_c, 2.0 if self.order == 2 else 1.0)
+        kinds = {"dirichlet": 0, "neumann": 1}
+        if bc_types is None:
+            bc_types = [("dirichlet", "dirichlet")] * len(ibcs)
+        if len(bc_types) != len(ibcs):
+            raise ValueError("one (side +1, side -1) condition pair per interior boundary")
+        self.bc_types = [tuple(kinds[k] for k in pair) for pair in bc_types]
+        # a BC DOF on side s serves side -s
+        served = -self.bc_side
+        self.bc_kind = np.array([self.bc_types[c][0 if sv > 0 else 1]
+                                 for c, sv in zip(self.bc_curve, served)], dtype=np.int64)
+        self.e_coef = np.where(self.bc_kind == 0, 2.0 if self.order == 2 else 1.0, 0.0)
 
         self._build_E()
         self._build_L()
@@ -201,23 +221,32 @@ class CPMSystem:
         r_idx = [np.repeat(np.arange(n_s), nm)]
         c_idx = [cols.ravel()]
         vals = [W.ravel()]
-        # BC rows (Sec. 4.3, Dirichlet)
-        if self.order == 2:
-            for st, amap in zip(self.sets, self.alpha_of):
-                nodes = st.omega_nodes
-                if nodes.size == 0:
-                    continue
-                X = node_coords(self.K[nodes], self.N)
-                Z = 2.0 * st.cpc[nodes] - X
-                Ybar = self.surface.cp(Z)                # cpbar_C (eq. cpc-bar)
-                b2, W2 = stencil(Ybar, self.N, d)
-                M = self._members(b2)
-                dot = dot_rows(st.v[nodes][:, None, :], st.v[M])
-                keep_bc = (dot >= 0.0) & (amap[M] >= 0)
-                M2 = np.where(keep_bc, amap[M], M)
-                r_idx.append(np.repeat(amap[nodes], nm))
-                c_idx.append(M2.ravel())
-                vals.append(-W2.ravel())
+        # BC rows (Sec. 4.3): Dirichlet second order -w at cpbar_C; zero
+        # Neumann +w at cp_C (first order) or cpbar_C (second order)
+        for st, amap in zip(self.sets, self.alpha_of):
+            nodes = st.omega_nodes
+            if nodes.size == 0:
+                continue
+            kind = self.bc_kind[amap[nodes] - n_s]
+            X = node_coords(self.K[nodes], self.N)
+            Ybar = self.surface.cp(2.0 * st.cpc[nodes] - X)   # cpbar_C (eq. cpc-bar)
+            if self.order == 2:
+                Y, sign = Ybar, np.where(kind == 1, 1.0, -1.0)
+                use = np.ones(nodes.size, dtype=bool)
+            else:
+                Y, sign = st.cpc[nodes], np.ones(nodes.size)
+                use = kind == 1
+            if not np.any(use):
+                continue
+            nodes, Y, sign = nodes[use], Y[use], sign[use]
+            b2, W2 = stencil(Y, self.N, d)
+            M = self._members(b2)
+            dot = dot_rows(st.v[nodes][:, None, :], st.v[M])
+            keep_bc = (dot >= 0.0) & (amap[M] >= 0)
+            M2 = np.where(keep_bc, amap[M], M)
+            r_idx.append(np.repeat(amap[nodes], nm))
+            c_idx.append(M2.ravel())
+            vals.append((sign[:, None] * W2).ravel())
         self.E = sp.csr_matrix((np.concatenate(vals),
                                 (np.concatenate(r_idx), np.concatenate(c_idx))),
                                shape=(self.n, self.n))

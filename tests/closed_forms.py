@@ -71,3 +71,21 @@ def torus_manufactured(pts, R, rho):
 
 def fit_slope(hs, errs):
     return np.polyfit(np.log(hs), np.log(errs), 1)[0]
+
+
+def equator_split(pts, side):
+    """Screened Poisson -Delta u + u = f on the unit sphere with a zero-Neumann
+    interior boundary on the equator: u = x on the north side (side +1) and
+    u = x + 3 z^2 + 6 on the south side.  Both satisfy the Neumann condition
+    (the z-derivative of 3 z^2 vanishes at z = 0; x is even in z), x is an
+    l = 1 harmonic (-Delta x = 2 x) and 3 z^2 + 6 = (3 z^2 - 1) + 7 combines
+    an l = 2 harmonic (eigenvalue 6) with a constant, so
+    f = 3 x on the north side and 3 x + 7 (3 z^2 - 1) + 7 = 3 x + 21 z^2 on
+    the south side: f is continuous across the equator while u jumps by 6.
+    Returns (u, f)."""
+    pts = np.asarray(pts, dtype=np.float64)
+    x, z = pts[:, 0], pts[:, 2]
+    south = np.asarray(side) < 0
+    u = x + np.where(south, 3.0 * z * z + 6.0, 0.0)
+    f = 3.0 * x + np.where(south, 21.0 * z * z, 0.0)
+    return u, f

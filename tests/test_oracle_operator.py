@@ -8,7 +8,8 @@ import numpy as np
 import pytest
 
 from closed_forms import (circle_point_dirichlet, fit_slope, jump_exact,
-                          latitude_harmonic, sphere_poisson, torus_manufactured)
+                          latitude_harmonic, sphere_poisson, torus_manufactured,
+                          equator_split)
 from oracle import adjoint as AD
 from oracle import geometry as G
 from oracle import krylov as KR
@@ -215,6 +216,51 @@ def test_latitude_circle_closed_form_second_order():
     assert fit_slope(1.0 / np.array(Ns), errs) > 1.7, errs
     assert errs[-1] < 1e-3
     assert errs1[-1] > 5 * errs[-1]          # first order is visibly worse
+
+
+def _equator_errors(N, order, bc_types, with_ibc=True):
+    """Surface-value error of the equator problem (closed_forms.equator_split)
+    with the given conditions on the equator (side +1 = north)."""
+    S = G.Sphere()
+    C = G.LatitudeC(S, 0.0)
+    side_sys = O.CPMSystem(S, N, [C], order=order, bc_types=bc_types)
+    st = side_sys.sets[0]
+    # the method's side inside the check region (on-C rule included); away
+    # from C (where cp_C is undefined on the z axis) the hemisphere
+    side = np.where(st.in_check, st.side, np.where(side_sys.CP[:, 2] < 0.0, -1, 1))
+    sysm = side_sys if with_ibc else O.CPMSystem(S, N, [], order=order)
+    u_ex, f = equator_split(sysm.CP, side)
+    # Dirichlet BC DOFs hold the north value x at cp_C (only the north side is
+    # ever Dirichlet here); Neumann DOFs ignore g
+    g = sysm.bc_cpc[:, 0].copy() if sysm.n_c else np.zeros(0)
+    b = sysm.rhs(f, g, -1.0)
+    u, info = KR.bicgstab(lambda x: sysm.apply(x, 1.0, -1.0), b, tol=1e-10)
+    assert info["converged"], info
+    return np.max(np.abs(sysm.surface_values(u, g) - u_ex))
+
+
+def test_equator_zero_neumann_closed_form():
+    """Zero-Neumann IBC (Sec. 4.3, eq. IBC-1st-order-Neumann, eq. cpc-bar) on
+    both sides of the equator: the sides decouple and the solution jumps."""
+    Ns = [16, 24, 32]
+    nn = ("neumann", "neumann")
+    e2 = [_equator_errors(N, 2, [nn]) for N in Ns]
+    e1 = [_equator_errors(N, 1, [nn]) for N in Ns]
+    hs = 1.0 / np.array(Ns)
+    assert fit_slope(hs, e2) > 1.7, e2
+    assert 0.7 < fit_slope(hs, e1) < 1.6, e1
+    assert e1[-1] > 3 * e2[-1]
+    # without the interior boundary the jump of 6 is smeared: O(1) error
+    assert _equator_errors(16, 2, None, with_ibc=False) > 0.5
+
+
+def test_equator_mixed_dirichlet_neumann_closed_form():
+    """Mixed two-sided IBC (Sec. 4.2): Dirichlet u = x on the north side,
+    zero Neumann on the south side, second order."""
+    Ns = [16, 24, 32]
+    e2 = [_equator_errors(N, 2, [("dirichlet", "neumann")]) for N in Ns]
+    assert fit_slope(1.0 / np.array(Ns), e2) > 1.7, e2
+    assert e2[-1] < 5e-3
 
 
 def test_torus_meridian_dirichlet_manufactured():
