@@ -70,6 +70,18 @@ enum { CPM_IBC_POINT = 1,     /* C = {p}; orient = o_C given by the caller   */
        CPM_IBC_MERIDIAN = 3 };/* torus only: poloidal circle in the vertical
                                  plane with horizontal unit direction dir   */
 
+/* Condition imposed on one side of an interior boundary (Sec. 4.3).  Each
+ * side carries its own (Sec. 4.2: two-sided and mixed IBCs).  The sides are
+ * told apart by the orientation o_C: side +1 is where (cp_S - cp_C) . o_C >= 0
+ * (POINT: the caller's orient; LATITUDE: north; MERIDIAN: the plane normal
+ * (-ey, ex, 0)). */
+enum { CPM_BC_DIRICHLET = 0,  /* u = g on C: first order extends g, second
+                                 order 2 g - u at the mirror point cpbar_C  */
+       CPM_BC_NEUMANN = 1 };  /* zero conormal derivative on C: the BC DOF
+                                 interpolates u at cp_C (first order) or at
+                                 cpbar_C = cp_S(2 cp_C - x) (second order);
+                                 not defined for a point C                   */
+
 typedef struct {
   int kind;
   double p[3];       /* POINT: the point (on S)                               */
@@ -77,12 +89,14 @@ typedef struct {
                         (within tau of it) is assigned to (Sec. 4.2)          */
   double z0;         /* LATITUDE                                              */
   double dir[2];     /* MERIDIAN: (ex, ey), a unit vector                     */
+  int bc[2];         /* CPM_BC_* of side +1 and of side -1; zero-initialised
+                        = Dirichlet on both sides                            */
 } cpm_ibc;
 
 typedef struct {
   int N;               /* h = 1/N                                             */
   int p;               /* interpolation degree; only 3 is supported           */
-  int order;           /* Dirichlet IBC order: 1 or 2 (Sec. 4.3)              */
+  int order;           /* IBC order (Dirichlet and Neumann): 1 or 2 (Sec. 4.3) */
   int check_reach;     /* 1: reject h above the reach bound (Sec. 8 grid
                           resolution in practice)                           */
   double r_band;       /* 0 = eq. (bandwidth) with q = 1                      */

@@ -37,21 +37,31 @@ def torus(R=1.0, rho=0.4, center=(0.0, 0.0, 0.0)):
     return capi.Surface(capi.SURF_TORUS, (C.c_double * 3)(*center), R, rho)
 
 
+_BC = {"dirichlet": capi.BC_DIRICHLET, "neumann": capi.BC_NEUMANN}
+
+
+def _bc(bc):
+    """(condition of side +1, condition of side -1), "dirichlet" or "neumann"."""
+    if isinstance(bc, str):
+        bc = (bc, bc)
+    return (C.c_int * 2)(_BC[bc[0]], _BC[bc[1]])
+
+
 def point_ibc(p, orient):
     p = list(p) + [0.0] * (3 - len(p))
     o = list(orient) + [0.0] * (3 - len(orient))
     return capi.IBC(capi.IBC_POINT, (C.c_double * 3)(*p), (C.c_double * 3)(*o), 0.0,
-                    (C.c_double * 2)(0.0, 0.0))
+                    (C.c_double * 2)(0.0, 0.0), _bc("dirichlet"))
 
 
-def latitude_ibc(z0):
+def latitude_ibc(z0, bc="dirichlet"):
     return capi.IBC(capi.IBC_LATITUDE, (C.c_double * 3)(), (C.c_double * 3)(), z0,
-                    (C.c_double * 2)(0.0, 0.0))
+                    (C.c_double * 2)(0.0, 0.0), _bc(bc))
 
 
-def meridian_ibc(ex, ey):
+def meridian_ibc(ex, ey, bc="dirichlet"):
     return capi.IBC(capi.IBC_MERIDIAN, (C.c_double * 3)(), (C.c_double * 3)(), 0.0,
-                    (C.c_double * 2)(ex, ey))
+                    (C.c_double * 2)(ex, ey), _bc(bc))
 
 
 # ------------------------------------------------------------------ band

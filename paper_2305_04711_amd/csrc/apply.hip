@@ -591,7 +591,8 @@ __global__ void k_rhs_init(int64_t n_s, int64_t n_c, int nrhs, const double* __r
 
 __global__ void k_rhs_rows(int nrows, int nf, int64_t n_s, int64_t n_c, int nrhs,
                            const int* __restrict__ row_id, const int* __restrict__ col,
-                           const double* __restrict__ g, double scale, double* __restrict__ b) {
+                           const double* __restrict__ g, const double* __restrict__ ecoef,
+                           double scale, double* __restrict__ b) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nrows) return;
   const int id = row_id[i];
@@ -600,7 +601,7 @@ __global__ void k_rhs_rows(int nrows, int nf, int64_t n_s, int64_t n_c, int nrhs
     double s = 0.0;
     for (int f = 0; f < nf; ++f) {
       const int c = col[i * nf + f];
-      if (c >= n_s) s += g[r * n_c + (c - n_s)];
+      if (c >= n_s) s += ecoef[c - n_s] * g[r * n_c + (c - n_s)];
     }
     b[r * n + id] -= scale * s;
   }
@@ -624,7 +625,8 @@ __global__ void k_gradf_bc(int64_t n_s, int64_t n_c, int nrhs, const int* __rest
 
 __global__ void k_gradg(int nrows, int nf, int64_t n_s, int64_t n_c, int nrhs,
                         const int* __restrict__ row_id, const int* __restrict__ col,
-                        const double* __restrict__ lam, double scale, double* __restrict__ gg) {
+                        const double* __restrict__ lam, const double* __restrict__ ecoef,
+                        double scale, double* __restrict__ gg) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nrows) return;
   const int id = row_id[i];
@@ -633,7 +635,8 @@ __global__ void k_gradg(int nrows, int nf, int64_t n_s, int64_t n_c, int nrhs,
     const double li = lam[r * n + id];
     for (int f = 0; f < nf; ++f) {
       const int c = col[i * nf + f];
-      if (c >= n_s) atomicAdd(&gg[r * n_c + (c - n_s)], scale * li);
+      if (c >= n_s && ecoef[c - n_s] != 0.0)
+        atomicAdd(&gg[r * n_c + (c - n_s)], scale * ecoef[c - n_s] * li);
     }
   }
 }
@@ -939,7 +942,7 @@ extern "C" cpm_status cpm_rhs(const cpm_band* b, double n, int nrhs, const doubl
       const double N2 = (double)b->N * (double)b->N;
       hipLaunchKernelGGL(k_rhs_rows, dim3(grid_for(b->n_lrows, 128)), dim3(128), 0, st,
                          b->n_lrows, 2 * b->dim, b->n_s, b->n_c, nrhs, b->lrow_id, b->lcol, g,
-                         n * N2 * b->ecoef, out);
+                         b->bc_ecoef, n * N2, out);
       CPM_LAUNCH_CHECK();
     }
   });
@@ -963,7 +966,7 @@ extern "C" cpm_status cpm_rhs_adjoint(const cpm_band* b, double n, int nrhs, con
       const double N2 = (double)b->N * (double)b->N;
       hipLaunchKernelGGL(k_gradg, dim3(grid_for(b->n_lrows, 128)), dim3(128), 0, st, b->n_lrows,
                          2 * b->dim, b->n_s, b->n_c, nrhs, b->lrow_id, b->lcol, lam,
-                         -n * b->ecoef * N2, grad_g);
+                         b->bc_ecoef, -n * N2, grad_g);
       CPM_LAUNCH_CHECK();
     }
   });

@@ -450,24 +450,34 @@ __global__ __launch_bounds__(256) void k_erow_pde(Blocks B, int nb, int N, int64
 }
 
 
-// Explicit interpolation rows of BC DOFs (Sec. 4.3, Dirichlet).  Second
-// order: u_alpha = 2 g - u(cpbar_C(x)), cpbar_C(x) = cp_S(2 cp_C(x) - x) (eq.
-// cpc-bar), with weights -w; a member stays a BC DOF when it lies in
-// Omega(C) on the director's side (d*_alpha = v of the node) and is the PDE
-// DOF otherwise.  First order: no linear part (u_alpha = g).
+// Explicit interpolation rows of BC DOFs (Sec. 4.3).  A BC DOF whose node
+// lies on side s stands in for side -s, so it takes that side's condition.
+//   Dirichlet, second order: u_alpha = 2 g - u(cpbar_C(x)), cpbar_C(x) =
+//     cp_S(2 cp_C(x) - x) (eq. cpc-bar), weights -w, constant 2 g.
+//   Dirichlet, first order: no linear part, constant g (u_alpha = g).
+//   Zero Neumann: u_alpha = u(y) with y = cp_C(x) (first order, eq.
+//     IBC-1st-order-Neumann) or cpbar_C(x) (second order), weights +w, no
+//     constant.
+// A member stays a BC DOF when it lies in Omega(C) on the director's side
+// (d*_alpha = v of the node) and is the PDE DOF otherwise.  ecoef receives
+// the multiplier of g in the row's constant (2, 1 or 0).
 template <int DIM>
 __global__ void k_erow_bc(Blocks B, int N, int64_t n_s, int64_t n_c, int order,
-                          cpm_surface S, const int* bc_node, const double* bc_cpc,
-                          const int* bc_k, const int* row_c, const int* alpha_of,
-                          const double* side_v, int r0, int* erow_id, int* ecol, double* ew,
-                          float* ew32, int* ebase, unsigned long long* counters) {
+                          cpm_surface S, IBCList L, const int* bc_node, const double* bc_cpc,
+                          const int* bc_side, const int* bc_curve, const int* bc_k,
+                          const int* row_c, const int* alpha_of, const double* side_v, int r0,
+                          int* erow_id, int* ecol, double* ew, float* ew32, int* ebase,
+                          double* ecoef, unsigned long long* counters) {
   using G = Geo<DIM>;
   constexpr int NM = DIM == 3 ? 64 : 16;
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n_c) return;
   const int r = r0 + (int)k;
   erow_id[r] = (int)(n_s + k);
-  if (order != 2) {
+  const int served = -bc_side[k];
+  const bool neumann = L.c[bc_curve[k]].bc[served > 0 ? 0 : 1] == CPM_BC_NEUMANN;
+  ecoef[k] = neumann ? 0.0 : (order == 2 ? 2.0 : 1.0);
+  if (order != 2 && !neumann) {
     for (int o = 0; o < NM; ++o) {
       ecol[(int64_t)r * NM + o] = -1;
       ew[(int64_t)r * NM + o] = 0.0;
@@ -480,7 +490,8 @@ __global__ void k_erow_bc(Blocks B, int N, int64_t n_s, int64_t n_c, int order,
   const V3 x = node_pos(bc_k[k * 3], bc_k[k * 3 + 1], bc_k[k * 3 + 2], N);
   const V3 pc{bc_cpc[k * DIM], bc_cpc[k * DIM + 1], DIM == 3 ? bc_cpc[k * DIM + 2] : 0.0};
   const V3 z{2.0 * pc.x - x.x, 2.0 * pc.y - x.y, DIM == 3 ? 2.0 * pc.z - x.z : 0.0};
-  const V3 y = cp_surface<DIM>(S, z);
+  const V3 y = order == 2 ? cp_surface<DIM>(S, z) : pc;
+  const double sgn = neumann ? 1.0 : -1.0;
   int base[3];
   double t[3];
   stencil_base<DIM>(y, N, base, t);
@@ -502,10 +513,10 @@ __global__ void k_erow_bc(Blocks B, int N, int64_t n_s, int64_t n_c, int order,
                !(dot3<DIM>(vj, load_v(side_v, n_s, m, DIM)) < 0.0)) {
       m = alpha_of[m];
     }
-    const double wt = DIM == 3 ? (w[2][c] * w[1][b]) * w[0][a] : w[1][b] * w[0][a];
+    const double wt = sgn * (DIM == 3 ? (w[2][c] * w[1][b]) * w[0][a] : w[1][b] * w[0][a]);
     ecol[(int64_t)r * NM + o] = m;
-    ew[(int64_t)r * NM + o] = -wt;
-    ew32[(int64_t)r * NM + o] = (float)(-wt);
+    ew[(int64_t)r * NM + o] = wt;
+    ew32[(int64_t)r * NM + o] = (float)wt;
   }
   if (holes) atomicAdd(&counters[3], (unsigned long long)holes);
 }
@@ -887,11 +898,12 @@ void build(cpm_band* b, hipStream_t st) {
                          alpha_of.p, side_v.p, eflag.p, eidx.p, b->erow_id, b->ecol, b->ew,
                          b->ew32, b->ebase);
     CPM_LAUNCH_CHECK();
+    b->bc_ecoef = b->alloc<double>(n_c);
     if (n_c)
       hipLaunchKernelGGL(k_erow_bc<DIM>, dim3(grid_for(n_c, 128)), dim3(128), 0, st, B, N, n_s,
-                         n_c, b->order, S, b->bc_node, b->bc_cpc, bc_kp->p, row_c.p, alpha_of.p,
-                         side_v.p, (int)ne_pde, b->erow_id, b->ecol, b->ew, b->ew32, b->ebase,
-                         counters.p);
+                         n_c, b->order, S, L, b->bc_node, b->bc_cpc, b->bc_side, b->bc_curve,
+                         bc_kp->p, row_c.p, alpha_of.p, side_v.p, (int)ne_pde, b->erow_id,
+                         b->ecol, b->ew, b->ew32, b->ebase, b->bc_ecoef, counters.p);
     CPM_LAUNCH_CHECK();
     unsigned long long hc[4];
     CPM_HIP(hipMemcpyAsync(hc, counters.p, sizeof(hc), hipMemcpyDeviceToHost, st));
@@ -961,7 +973,6 @@ void build(cpm_band* b, hipStream_t st) {
                          b->lrow_id, b->lcol, b->lcol0);
     CPM_LAUNCH_CHECK();
   }
-  b->ecoef = b->order == 2 ? 2.0 : 1.0;
   // metadata read by the apply kernels
   b->tile_meta = b->alloc<QMeta>((size_t)b->ntiles * 8);
   if (b->ntiles)
@@ -1041,6 +1052,16 @@ extern "C" cpm_status cpm_build_band(const cpm_surface* surface, const cpm_ibc* 
                                               std::fabs(ibcs[c].z0) < surface->R) ||
                       (k == CPM_IBC_MERIDIAN && kind == CPM_SURF_TORUS);
       if (!ok) CPM_FAIL(CPM_E_INVALID, "interior boundary %d (kind %d) does not fit surface kind %d", c, k, kind);
+      for (int s2 = 0; s2 < 2; ++s2) {
+        const int bc = ibcs[c].bc[s2];
+        if (bc != CPM_BC_DIRICHLET && bc != CPM_BC_NEUMANN)
+          CPM_FAIL(CPM_E_INVALID, "interior boundary %d: unknown condition %d", c, bc);
+        // a conormal direction does not exist at a point C of a surface; a
+        // point of a curve in R^2 has one (the curve's own direction)
+        if (bc == CPM_BC_NEUMANN && k == CPM_IBC_POINT && kind != CPM_SURF_CIRCLE)
+          CPM_FAIL(CPM_E_INVALID, "interior boundary %d: a zero-Neumann condition is not "
+                   "defined at a point of a surface", c);
+      }
     }
     hipStream_t st = (hipStream_t)hip_stream;
     std::unique_ptr<cpm_band> b(new cpm_band());

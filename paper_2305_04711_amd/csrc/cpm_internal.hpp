@@ -156,7 +156,7 @@ struct cpm_band {
   double* bc_cpc = nullptr;           // [n_c][dim]
   int* bc_side = nullptr;             // [n_c]
   int* bc_curve = nullptr;            // [n_c]
-  double ecoef = 2.0;
+  double* bc_ecoef = nullptr;         // [n_c] multiplier of g in the row constant
 
   // composite of several bands (batched solves): per-instance FD
   // coefficients (cd, co) of A, instance of each explicit FD row

@@ -35,11 +35,30 @@ def oracle_and_gpu(cfg, N, order=2):
         S = G.Torus(1.0, 0.4)
         Cs = [G.MeridianC(S, 1.0, 0.0), G.MeridianC(S, -1.0, 0.0)]
         gs, gi = cpm.torus(1.0, 0.4), [cpm.meridian_ibc(1.0, 0.0), cpm.meridian_ibc(-1.0, 0.0)]
+    elif cfg == "sphere_eq_neumann":
+        S = G.Sphere()
+        Cs, bct = [G.LatitudeC(S, 0.0)], [("neumann", "neumann")]
+        gs, gi = cpm.sphere(), [cpm.latitude_ibc(0.0, bc="neumann")]
+    elif cfg == "sphere_eq_mixed":
+        S = G.Sphere()
+        Cs, bct = [G.LatitudeC(S, 0.0)], [("dirichlet", "neumann")]
+        gs, gi = cpm.sphere(), [cpm.latitude_ibc(0.0, bc=("dirichlet", "neumann"))]
+    elif cfg == "circle_mixed":
+        S = G.Circle()
+        Cs, bct = [G.PointC((1.0, 0.0), (0.0, 1.0))], [("neumann", "dirichlet")]
+        ib = cpm.point_ibc((1.0, 0.0), (0.0, 1.0))
+        ib.bc[0], ib.bc[1] = 1, 0
+        gs, gi = cpm.circle(), [ib]
     else:
         raise KeyError(cfg)
-    sysm = O.CPMSystem(S, N, Cs, order=order)
+    bc_types = bct if cfg in NEUMANN_CASES else None
+    sysm = O.CPMSystem(S, N, Cs, order=order, bc_types=bc_types)
     band = cpm.Band(gs, gi, N, order=order)
     return sysm, band
+
+
+# configurations with a zero-Neumann side (screened operators: m = 1)
+NEUMANN_CASES = ("sphere_eq_neumann", "sphere_eq_mixed", "circle_mixed")
 
 
 def dof_map(sysm, band):

@@ -8,12 +8,13 @@ import pytest
 from oracle import adjoint as AD
 from oracle import krylov as KR
 from paper_2305_04711_amd import inputs
-from parity_helpers import dof_map, oracle_and_gpu
+from parity_helpers import NEUMANN_CASES, dof_map, oracle_and_gpu
 
 pytestmark = pytest.mark.gpu
 
 CASES = [("circle_point", 32), ("circle_jump", 64), ("sphere", 16), ("sphere_lat", 16),
-         ("sphere_lat", 27), ("torus", 12), ("torus_meridians", 16)]
+         ("sphere_lat", 27), ("torus", 12), ("torus_meridians", 16),
+         ("sphere_eq_neumann", 16), ("sphere_eq_mixed", 19), ("circle_mixed", 40)]
 
 
 @pytest.fixture(scope="module")
@@ -148,7 +149,8 @@ def test_rhs_and_rhs_adjoint_match_oracle(torch_cuda, cfg, N):
 
 
 @pytest.mark.parametrize("mode", ["f64", "mixed"])
-@pytest.mark.parametrize("cfg,N", [("circle_point", 32), ("sphere_lat", 16), ("torus_meridians", 16)])
+@pytest.mark.parametrize("cfg,N", [("circle_point", 32), ("sphere_lat", 16), ("torus_meridians", 16),
+                                   ("sphere_eq_mixed", 16), ("circle_mixed", 32)])
 def test_solve_matches_oracle(torch_cuda, cfg, N, mode):
     torch = torch_cuda
     from paper_2305_04711_amd import cpm
@@ -156,7 +158,8 @@ def test_solve_matches_oracle(torch_cuda, cfg, N, mode):
     rng = np.random.default_rng(14)
     f_o = rng.standard_normal(sysm.n_s)
     g_o = rng.standard_normal(sysm.n_c)
-    m, n = (0.0, -1.0) if cfg != "torus_meridians" else (1.0, -1.0)
+    screened = cfg == "torus_meridians" or cfg in NEUMANN_CASES
+    m, n = (1.0, -1.0) if screened else (0.0, -1.0)
     b_o = sysm.rhs(f_o, g_o, n)
     A = sysm.matrix(m, n)
     import scipy.sparse.linalg as spl
@@ -255,3 +258,62 @@ def test_circle_gmres_matches_oracle_and_closed_form(torch_cuda):
         errs.append(np.max(np.abs(sysm.surface_values(uo, np.zeros(sysm.n_c)) - ex)))
     rate = np.log2(errs[0] / errs[-1]) / 2
     assert rate > 1.7, errs
+
+
+@pytest.mark.parametrize("cfg,N", [("sphere_eq_neumann", 16), ("sphere_eq_mixed", 16),
+                                   ("circle_mixed", 32)])
+def test_first_order_bc_rows_match_oracle(torch_cuda, cfg, N):
+    """First-order BC rows: Dirichlet rows have no linear part, zero-Neumann
+    rows interpolate at cp_C (eq. IBC-1st-order-Neumann)."""
+    torch = torch_cuda
+    from paper_2305_04711_amd import cpm
+    sysm, band, g2o = _pair(cfg, N, order=1)
+    rng = np.random.default_rng(15)
+    U = rng.standard_normal(sysm.n)
+    for td, tol in ((torch.float64, 1e-13), (torch.float32, 2e-6)):
+        u = torch.tensor(U[g2o], dtype=td, device="cuda")
+        for fn, ref in ((cpm.apply, sysm.apply(U, 1.0, -1.0)),
+                        (cpm.apply_transpose, None)):
+            if ref is None:
+                from oracle import adjoint as AD2
+                ref = AD2.apply_transpose(sysm, U, 1.0, -1.0)
+            v = fn(band, u, 1.0, -1.0).cpu().numpy().astype(np.float64)
+            err = np.max(np.abs(v - ref[g2o])) / np.max(np.abs(ref))
+            assert err < tol, (fn.__name__, td, err)
+    g_o = rng.standard_normal(sysm.n_c)
+    ref = sysm.rhs(U[:sysm.n_s], g_o, -1.0)
+    b = cpm.rhs(band, torch.tensor(U[g2o[:band.n_s]], device="cuda"),
+                torch.tensor(g_o[g2o[band.n_s:] - sysm.n_s], device="cuda"), -1.0).cpu().numpy()
+    assert np.max(np.abs(b - ref[g2o])) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("bc", [("neumann", "neumann"), ("dirichlet", "neumann")])
+def test_equator_split_second_order_on_gpu(torch_cuda, bc):
+    """The equator problem of the oracle pins (closed_forms.equator_split),
+    solved on the GPU at h = 1/32 and 1/64 with second-order zero-Neumann (and
+    mixed) IBCs: grid values away from C converge at second order to the
+    closed form (the sides decouple; without the IBC the error is O(1))."""
+    torch = torch_cuda
+    from paper_2305_04711_amd import cpm
+    from closed_forms import equator_split
+    errs = []
+    for N in (32, 64):
+        band = cpm.Band(cpm.sphere(), [cpm.latitude_ibc(0.0, bc=bc)], N, order=2)
+        cp = band.cp()
+        side = np.where(cp[:, 2] < 0.0, -1, 1)
+        u_ex, f = equator_split(cp, side)
+        g = band.bc_cpc()[:, 0].copy()        # Dirichlet data of the north side
+        b = cpm.rhs(band, torch.tensor(f, device="cuda"), torch.tensor(g, device="cuda"), -1.0)
+        x, st = cpm.solve(band, b, 1.0, -1.0, tol=1e-11, mode="f64")
+        assert st["converged"]
+        xs = x.cpu().numpy()[:band.n_s]
+        # grid values carry the solution only where every FD neighbour is in
+        # the band (rows at the band's edge drop neighbours and are never read
+        # by E); keep those nodes, away from C
+        X = band.coords() / float(N)
+        depth = np.abs(np.sqrt((X * X).sum(1)) - 1.0)
+        keep = (depth <= np.sqrt(17.0) / N - 1.0 / N) & (np.abs(cp[:, 2]) > 0.2)
+        errs.append(np.max(np.abs(xs[keep] - u_ex[keep])))
+        print("equator", bc, N, "Linf away from C", errs[-1], st, flush=True)
+    assert np.log2(errs[0] / errs[1]) > 1.7, errs
+    assert errs[1] < 1e-3, errs
