@@ -23,10 +23,12 @@ Modules
             system A = mI + n[diag L + (L - diag L)E] (Sec. 5.4), the RHS
   krylov    dense LU, BiCGSTAB (van der Vorst), GMRES(k)
   adjoint   transposed operator and gradients of a quadratic loss
+  local     the operator evaluated row by row (sampled rows of large bands)
+  timestep  Crank-Nicolson steps of the heat equation (Sec. 6.2)
 
 Parity status: every function is pinned by the CPU tests in
 ``tests/test_oracle_*.py`` (closed forms, invariants, brute force); none is
 "parity unpinned".
 """
 
-from . import geometry, band, operator, krylov, adjoint  # noqa: F401
+from . import geometry, band, operator, krylov, adjoint, local, timestep  # noqa: F401

@@ -89,3 +89,9 @@ def equator_split(pts, side):
     u = x + np.where(south, 3.0 * z * z + 6.0, 0.0)
     f = 3.0 * x + np.where(south, 21.0 * z * z, 0.0)
     return u, f
+
+
+def heat_l1(pts, t, axis=2):
+    """u(x, t) = exp(-2 t) x_axis on the unit sphere: the l = 1 solution of
+    u_t = Delta_S u (the paper's heat test with axis = 2, the polar cosine)."""
+    return np.exp(-2.0 * t) * np.asarray(pts, dtype=np.float64)[:, axis]

@@ -9,11 +9,12 @@ import pytest
 
 from closed_forms import (circle_point_dirichlet, fit_slope, jump_exact,
                           latitude_harmonic, sphere_poisson, torus_manufactured,
-                          equator_split)
+                          equator_split, heat_l1)
 from oracle import adjoint as AD
 from oracle import geometry as G
 from oracle import krylov as KR
 from oracle import operator as O
+from oracle import timestep as TS
 from paper_2305_04711_amd import inputs
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -344,3 +345,40 @@ def test_adjoint_gradients_match_finite_differences():
     lam_k, info = AD.solve_adjoint(sysm, AD.adjoint_rhs(sysm, u, tgt), m, n, tol=1e-13)
     assert info["converged"]
     assert np.max(np.abs(lam_k - lam)) < 1e-8 * np.max(np.abs(lam))
+
+
+def _heat_error(N, order, curve, bc_types, axis, T=0.025):
+    """Crank-Nicolson with dt = 0.1 h (Sec. 6.2) on the unit sphere, exact
+    solution exp(-2t) x_axis, Dirichlet data the exact solution on C.  Returns
+    the surface-value error at t = T (the paper runs to 0.1; the order of the
+    scheme does not depend on T, and a shorter run keeps the test fast)."""
+    S = G.Sphere()
+    sysm = O.CPMSystem(S, N, [curve], order=order, bc_types=bc_types)
+    dt = 0.1 / N
+    nsteps = int(round(T / dt))
+    u0 = np.empty(sysm.n)
+    u0[:sysm.n_s] = heat_l1(sysm.CP, 0.0, axis)
+    u0[sysm.n_s:] = u0[sysm.bc_node]          # smooth data: either side's value
+    g = np.stack([heat_l1(sysm.bc_cpc, k * dt, axis) for k in range(nsteps + 1)])
+    u = TS.heat_cn(sysm, u0, dt, nsteps, g)
+    T = nsteps * dt
+    return np.max(np.abs(sysm.surface_values(u, g[-1]) - heat_l1(sysm.CP, T, axis)))
+
+
+def test_heat_crank_nicolson_dirichlet_latitude():
+    """Heat test of Sec. 6.2 with a second-order Dirichlet IBC on the circle
+    z = 0.3: second order in h (dt = 0.1 h)."""
+    Ns = [12, 16, 20, 24]
+    errs = [_heat_error(N, 2, G.LatitudeC(G.Sphere(), 0.3), None, 2) for N in Ns]
+    assert fit_slope(1.0 / np.array(Ns), errs) > 1.7, errs
+    e1 = _heat_error(24, 1, G.LatitudeC(G.Sphere(), 0.3), None, 2)
+    assert e1 > 10 * errs[-1], (e1, errs)     # first order is visibly worse
+
+
+def test_heat_crank_nicolson_neumann_equator():
+    """Heat test with a second-order zero-Neumann IBC on the equator and the
+    exact solution exp(-2t) x (its conormal derivative vanishes there)."""
+    Ns = [12, 16, 20, 24]
+    nn = [("neumann", "neumann")]
+    errs = [_heat_error(N, 2, G.LatitudeC(G.Sphere(), 0.0), nn, 0) for N in Ns]
+    assert fit_slope(1.0 / np.array(Ns), errs) > 1.7, errs
