@@ -14,8 +14,9 @@ the dominant kernel (the tile gather), the transposed apply, the time to a
 relative residual of 1e-8 for the mixed-precision and the plain FP64 solve,
 the differentiable solve (forward, and backward through the adjoint solve),
 the batched uneven solves (32 spheres and tori, h = 1/64 .. 1/192, 3
-right-hand sides each) against one FP64 solve per instance, the band build
-time, and the FP64 CPU oracle timed on the host (cpu_baseline).
+right-hand sides each) against one FP64 solve per instance, the paper's heat
+test (Crank-Nicolson, sphere h = 1/256) with its error, the band build time,
+and the FP64 CPU oracle timed on the host (cpu_baseline).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-solve]
        [--no-cpu] [--no-batch] [--no-adjoint] [--N 512]
@@ -145,6 +146,42 @@ def run_batch(dev, args):
         for mode in ("mixed", "f64")}
     log("sequential f64: %s" % out["sequential_f64"])
     del batch, bands
+    return out
+
+
+def run_heat(dev, N=256):
+    """The heat test of Sec. 6.2 at h = 1/N: unit sphere, exact solution
+    exp(-2t) z, second-order Dirichlet IBC on the circle z = 0.3 with the exact
+    solution as data, Crank-Nicolson with dt = 0.1 h to t = 0.1 (N steps),
+    FP64 solves to 1e-10 warm-started from the previous step."""
+    import numpy as np
+    import torch
+    from paper_2305_04711_amd import cpm
+    band = cpm.Band(cpm.sphere(), [cpm.latitude_ibc(0.3)], N, order=2)
+    cp = band.cp()
+    dt = 0.1 / N
+    nsteps = N
+    u0 = np.empty(band.n)
+    u0[:band.n_s] = cp[:, 2]
+    u0[band.n_s:] = u0[band.bc_node()]
+    zc = band.bc_cpc()[:, 2]
+    g = np.exp(-2.0 * dt * np.arange(nsteps + 1))[:, None] * zc[None, :]
+    u0t = torch.tensor(u0, device=dev)
+    gt = torch.tensor(g, device=dev)
+    cpm.heat_cn(band, u0t, dt, 2, gt[:3].contiguous(), tol=1e-10)     # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    u, st = cpm.heat_cn(band, u0t, dt, nsteps, gt, tol=1e-10)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t
+    X = band.coords() / float(N)
+    depth = np.abs(np.sqrt((X * X).sum(1)) - 1.0)
+    keep = (depth <= np.sqrt(17.0) / N - 1.0 / N) & (np.abs(cp[:, 2] - 0.3) > 0.2)
+    err = np.max(np.abs(u.cpu().numpy()[:band.n_s][keep] - np.exp(-0.2) * cp[keep, 2]))
+    out = {"N": N, "dofs": band.n, "steps": nsteps, "seconds": sec,
+           "ms_per_step": sec / nsteps * 1e3, "krylov_iters": st["krylov_iters"],
+           "converged": bool(st["converged"]), "linf_err_vs_exact": err}
+    log("heat: %s" % out)
     return out
 
 
@@ -301,6 +338,10 @@ def main():
     if not args.no_batch:
         batch_out = run_batch(dev, args)
 
+    heat_out = None
+    if not args.no_solve:
+        heat_out = run_heat(dev)
+
     if args.calibrate_copy:
         src = torch.ones(2 ** 27, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -343,6 +384,7 @@ def main():
         "build_band_s": build_s,
         "adjoint": adjoint,
         "batched": batch_out,
+        "heat_cn": heat_out,
     }
     print(json.dumps(out))
 

@@ -231,6 +231,22 @@ cpm_status cpm_solve_adjoint(const cpm_band* band, const cpm_solve_opts* opts,
                              int nrhs, const double* rhs, double* lambda,
                              cpm_solve_stats* stats, void* hip_stream);
 
+/* Crank-Nicolson time stepping of u_t = Delta_S u (the heat test of Sec.
+ * 6.2; trapezoidal rule) on the band's system with its interior boundaries:
+ *   (I - dt/2 M) u^{k+1} = (I + dt/2 M) u^k + dt/2 (L - D)(e(g^k) + e(g^{k+1}))
+ * for k = 0 .. nsteps-1, with M = diag L + (L - diag L) E.  u: device double
+ * [n], u^0 on entry and u^nsteps on return (updated in place step by step).
+ * g: device double [nsteps + 1][n_c], the Dirichlet data at t_k = k dt (only
+ * Dirichlet BC DOFs read it; NULL when there are none).  opts: mode, tol,
+ * maxit, check_every, use_graph and inner_tol as for cpm_solve (m, n are
+ * set by the scheme; the gauge must be 0); each step is warm-started from
+ * u^k.  stats (may be NULL): iterations summed over the steps, worst relative
+ * residual.  A step that does not converge stops the run with CPM_E_NOCONV
+ * (u then holds that step's last iterate). */
+cpm_status cpm_heat_cn(const cpm_band* band, double dt, int nsteps,
+                       const double* g, double* u, const cpm_solve_opts* opts,
+                       cpm_solve_stats* stats, void* hip_stream);
+
 /* Measurement: run cpm_apply `reps` times on hip_stream with HIP events
  * around each of its four phases and return the mean milliseconds per call in
  * ms[4]: [0] tile gather (a = E u for rows without swaps), [1] explicit

@@ -66,7 +66,8 @@ class SolveStats(C.Structure):
 EXPORTED = ["cpm_build_band", "cpm_band_free", "cpm_band_query", "cpm_band_export",
             "cpm_apply", "cpm_apply_profile", "cpm_autotune", "cpm_apply_transpose", "cpm_rhs", "cpm_rhs_adjoint", "cpm_solve",
             "cpm_solve_adjoint", "cpm_batch_create", "cpm_batch_free", "cpm_batch_offsets",
-            "cpm_batch_apply", "cpm_batch_autotune", "cpm_batch_solve", "cpm_last_error"]
+            "cpm_batch_apply", "cpm_batch_autotune", "cpm_batch_solve", "cpm_heat_cn",
+            "cpm_last_error"]
 
 _lib = None
 
@@ -104,6 +105,8 @@ def load(path=LIB_PATH):
     lib.cpm_solve.argtypes = [vp, C.POINTER(SolveOpts), i, vp, vp, C.POINTER(SolveStats), vp]
     lib.cpm_solve_adjoint.argtypes = [vp, C.POINTER(SolveOpts), i, vp, vp,
                                       C.POINTER(SolveStats), vp]
+    lib.cpm_heat_cn.argtypes = [vp, d, i, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveStats),
+                                vp]
     lib.cpm_batch_create.argtypes = [C.POINTER(vp), i, C.POINTER(C.c_double),
                                      C.POINTER(C.c_double), i, vp, C.POINTER(vp)]
     lib.cpm_batch_free.argtypes = [vp]

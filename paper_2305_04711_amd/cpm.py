@@ -247,6 +247,33 @@ def _solve(fn, band, b, m, n, tol, mode, x0, maxit, inner_tol, check_every, use_
     return x, stats
 
 
+def heat_cn(band, u0, dt, nsteps, g=None, tol=1e-10, mode="f64", maxit=0, check_every=0,
+            use_graph=True, raise_noconv=True):
+    """cpm_heat_cn: nsteps Crank-Nicolson steps of u_t = Delta_S u from u0
+    (float64, length n); g: float64 (nsteps + 1, n_c) Dirichlet data at the
+    step times, or None.  Returns (u, stats)."""
+    if _check_vec(band, u0, band.n) != 1 or u0.dim() != 1:
+        raise ValueError("the state is one vector of length n")
+    if u0.dtype != torch.float64:
+        raise TypeError("the state is float64")
+    u = u0.clone().contiguous()
+    gp = None
+    if g is not None:
+        if g.dtype != torch.float64 or not g.is_cuda or tuple(g.shape) != (nsteps + 1, band.n_c):
+            raise ValueError("g must be a float64 device tensor of shape (nsteps + 1, n_c)")
+        g = g.contiguous()
+        gp = _ptr(g)
+    st = capi.SolveStats()
+    o = _opts(1.0, -0.5 * dt, tol, mode, maxit, 0.0, check_every, use_graph, 0.0)
+    status = band._lib.cpm_heat_cn(band.handle, float(dt), int(nsteps), gp, _ptr(u), C.byref(o),
+                                   C.byref(st), _stream())
+    stats = {k: getattr(st, k) for k, _ in capi.SolveStats._fields_}
+    if status == capi.E_NOCONV and not raise_noconv:
+        return u, stats
+    capi.check(status)
+    return u, stats
+
+
 def solve(band, b, m, n, tol=1e-8, mode="mixed", x0=None, maxit=0, inner_tol=0.0,
           check_every=0, use_graph=True, gauge=0.0, raise_noconv=True, restart=0):
     """Solve A x = b.  mode "mixed": FP32 BiCGSTAB with FP64 reliable updates

@@ -938,15 +938,23 @@ extern "C" cpm_status cpm_rhs(const cpm_band* b, double n, int nrhs, const doubl
     hipLaunchKernelGGL(k_rhs_init, dim3(grid_for(total, 256)), dim3(256), 0, st, b->n_s, b->n_c,
                        nrhs, f, b->bc_node, out);
     CPM_LAUNCH_CHECK();
-    if (b->n_c && b->n_lrows) {
-      const double N2 = (double)b->N * (double)b->N;
-      hipLaunchKernelGGL(k_rhs_rows, dim3(grid_for(b->n_lrows, 128)), dim3(128), 0, st,
-                         b->n_lrows, 2 * b->dim, b->n_s, b->n_c, nrhs, b->lrow_id, b->lcol, g,
-                         b->bc_ecoef, n * N2, out);
-      CPM_LAUNCH_CHECK();
-    }
+    if (g) add_dirichlet_term(b, n, g, nrhs, out, st);
   });
 }
+
+namespace cpm {
+// out -= n (L - diag L) e(g) over the rows that reference BC DOFs: the
+// Dirichlet part of the right-hand side (Sec. 4.3), nrhs vectors.
+void add_dirichlet_term(const cpm_band* b, double n, const double* g, int nrhs, double* out,
+                        hipStream_t st) {
+  if (!b->n_c || !b->n_lrows) return;
+  const double N2 = (double)b->N * (double)b->N;
+  hipLaunchKernelGGL(k_rhs_rows, dim3(grid_for(b->n_lrows, 128)), dim3(128), 0, st, b->n_lrows,
+                     2 * b->dim, b->n_s, b->n_c, nrhs, b->lrow_id, b->lcol, g, b->bc_ecoef,
+                     n * N2, out);
+  CPM_LAUNCH_CHECK();
+}
+}  // namespace cpm
 
 extern "C" cpm_status cpm_rhs_adjoint(const cpm_band* b, double n, int nrhs, const double* lam,
                                       double* grad_f, double* grad_g, void* hip_stream) {

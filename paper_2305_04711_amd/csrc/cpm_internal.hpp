@@ -209,6 +209,9 @@ template <class T>
 void apply_transpose_impl(const cpm_band* b, double m, double n, int nrhs,
                           const T* w, T* z, hipStream_t s,
                           const double* gauge_sum = nullptr, double gamma = 0.0);
+// out -= n (L - diag L) e(g): the Dirichlet part of a right-hand side
+void add_dirichlet_term(const cpm_band* b, double n, const double* g, int nrhs, double* out,
+                        hipStream_t st);
 
 inline int grid_for(int64_t n, int threads, int cap = 1 << 20) {
   int64_t g = (n + threads - 1) / threads;

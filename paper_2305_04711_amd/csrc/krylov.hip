@@ -869,3 +869,60 @@ extern "C" cpm_status cpm_solve_adjoint(const cpm_band* b, const cpm_solve_opts*
                                         cpm_solve_stats* stats, void* hip_stream) {
   return solve_entry(b, o, nrhs, rhs, lambda, stats, hip_stream, true);
 }
+
+// Crank-Nicolson steps of u_t = Delta_S u with interior boundary conditions
+// (the heat test of Sec. 6.2; trapezoidal rule):
+//   (I - dt/2 M) u^{k+1} = (I + dt/2 M) u^k + dt/2 (L - D)(e(g^k) + e(g^{k+1})).
+// Each step solves with the given options, warm-started from u^k.
+extern "C" cpm_status cpm_heat_cn(const cpm_band* b, double dt, int nsteps, const double* g,
+                                  double* u, const cpm_solve_opts* o, cpm_solve_stats* stats,
+                                  void* hip_stream) {
+  cpm_status ret = CPM_OK;
+  const cpm_status gs = guard([&] {
+    if (!b || !u || !o) CPM_FAIL(CPM_E_INVALID, "null argument");
+    if (!(dt > 0.0) || nsteps < 0) CPM_FAIL(CPM_E_INVALID, "dt must be > 0 and nsteps >= 0");
+    if (o->mode != CPM_SOLVE_MIXED && o->mode != CPM_SOLVE_F64 && o->mode != CPM_SOLVE_GMRES)
+      CPM_FAIL(CPM_E_INVALID, "unknown solve mode %d", o->mode);
+    if (o->gauge != 0.0) CPM_FAIL(CPM_E_INVALID, "the gauge does not apply to time stepping");
+    if (b->composite) CPM_FAIL(CPM_E_INVALID, "time stepping takes a single band");
+    const auto t0 = Clock::now();
+    CPM_HIP(hipStreamSynchronize((hipStream_t)hip_stream));
+    hipStream_t st = nullptr;
+    CPM_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    struct StreamGuard {
+      hipStream_t s;
+      ~StreamGuard() { (void)hipStreamSynchronize(s); (void)hipStreamDestroy(s); }
+    } sg{st};
+    double* rhs = (double*)band_scratch(b, 80, sizeof(double) * (size_t)b->n);
+    cpm_solve_opts oo = *o;
+    oo.m = 1.0;
+    oo.n = -0.5 * dt;
+    cpm_solve_stats agg{};
+    agg.converged = 1;
+    for (int k = 0; k < nsteps; ++k) {
+      apply_impl<double>(b, 1.0, 0.5 * dt, 1, u, rhs, st);
+      if (g && b->n_c) {
+        add_dirichlet_term(b, -0.5 * dt, g + (int64_t)k * b->n_c, 1, rhs, st);
+        add_dirichlet_term(b, -0.5 * dt, g + (int64_t)(k + 1) * b->n_c, 1, rhs, st);
+      }
+      cpm_solve_stats s1{};
+      solve_one(b, oo, rhs, u, s1, st, false);
+      agg.outer_iters += s1.outer_iters;
+      agg.krylov_iters += s1.krylov_iters;
+      agg.restarts += s1.restarts;
+      agg.fallback_f64 |= s1.fallback_f64;
+      agg.relres = std::max(agg.relres, s1.relres);
+      if (!s1.converged) {
+        agg.converged = 0;
+        set_error("time step %d did not reach tol %.3g (relative residual %.3g)", k, o->tol,
+                  s1.relres);
+        ret = CPM_E_NOCONV;
+        break;
+      }
+    }
+    CPM_HIP(hipStreamSynchronize(st));
+    agg.time_ms = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+    if (stats) *stats = agg;
+  });
+  return gs != CPM_OK ? gs : ret;
+}
