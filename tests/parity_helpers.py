@@ -35,6 +35,13 @@ def oracle_and_gpu(cfg, N, order=2):
         S = G.Torus(1.0, 0.4)
         Cs = [G.MeridianC(S, 1.0, 0.0), G.MeridianC(S, -1.0, 0.0)]
         gs, gi = cpm.torus(1.0, 0.4), [cpm.meridian_ibc(1.0, 0.0), cpm.meridian_ibc(-1.0, 0.0)]
+    elif cfg == "sphere_point":
+        a, b = 1.1, 0.7
+        pt = (np.sin(a) * np.cos(b), np.sin(a) * np.sin(b), np.cos(a))
+        o = (np.cos(a) * np.cos(b), np.cos(a) * np.sin(b), -np.sin(a))
+        S = G.Sphere()
+        Cs = [G.PointC(pt, o)]
+        gs, gi = cpm.sphere(), [cpm.point_ibc(pt, o)]
     elif cfg == "sphere_eq_neumann":
         S = G.Sphere()
         Cs, bct = [G.LatitudeC(S, 0.0)], [("neumann", "neumann")]

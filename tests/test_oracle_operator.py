@@ -382,3 +382,32 @@ def test_heat_crank_nicolson_neumann_equator():
     nn = [("neumann", "neumann")]
     errs = [_heat_error(N, 2, G.LatitudeC(G.Sphere(), 0.0), nn, 0) for N in Ns]
     assert fit_slope(1.0 / np.array(Ns), errs) > 1.7, errs
+
+
+def _sphere_point(N, order, shift=0.0):
+    """Poisson on the unit sphere with a Dirichlet IBC at one point p of S
+    (Sec. 4.5: points C in R^3; the crossing test becomes a half-space test
+    through p).  Exact solution: degree 1..4 spherical harmonics (seed 7);
+    the point value is the exact one (plus shift).  Returns the surface-value
+    error."""
+    a, b = 1.1, 0.7
+    p = np.array([np.sin(a) * np.cos(b), np.sin(a) * np.sin(b), np.cos(a)])
+    o = np.array([np.cos(a) * np.cos(b), np.cos(a) * np.sin(b), -np.sin(a)])
+    coeffs = inputs.sphere_coeffs(7, lmin=1, lmax=4)
+    sysm = O.CPMSystem(G.Sphere(), N, [G.PointC(p, o)], order=order)
+    u_ex = inputs.sphere_field(coeffs, sysm.CP)
+    f = inputs.sphere_field(coeffs, sysm.CP, scale=lambda l: l * (l + 1))
+    g = np.full(sysm.n_c, inputs.sphere_field(coeffs, p[None, :])[0] + shift)
+    u, info = KR.bicgstab(lambda x: sysm.apply(x, 0.0, -1.0), sysm.rhs(f, g, -1.0), tol=1e-10)
+    assert info["converged"], info
+    return np.max(np.abs(sysm.surface_values(u, g) - u_ex))
+
+
+def test_point_ibc_on_sphere_second_order():
+    """A point C on a surface in R^3 (Sec. 4.5) with consistent Dirichlet data:
+    second-order convergence; wrong point data changes the solution at O(1)
+    (the point condition is enforced, not ignored)."""
+    Ns = [16, 24, 32]
+    errs = [_sphere_point(N, 2) for N in Ns]
+    assert fit_slope(1.0 / np.array(Ns), errs) > 1.7, errs
+    assert _sphere_point(16, 2, shift=1.0) > 0.5
