@@ -142,6 +142,12 @@ class IBCSets:
         self.curve = curve
         self.in_omega = dC <= r            # Omega(C)
         self.in_check = dC < 2.0 * r       # K(C)
+        if hasattr(curve, "at_boundary"):
+            # open curve: no BC DOFs and no stencil modification where cp_C is
+            # an endpoint (Omega(dC), eq. IBC_boundary_set)
+            end = curve.at_boundary(X)
+            self.in_omega &= ~end
+            self.in_check &= ~end
         self.omega_nodes = np.nonzero(self.in_omega)[0]   # lexicographic
         self.cpc = CPC
         V = CP - CPC

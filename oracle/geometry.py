@@ -143,6 +143,51 @@ class LatitudeC:
                          np.full(CPC.shape[0], self.rho0 / self.R)], axis=1)
 
 
+class LatitudeArc(LatitudeC):
+    """An open arc of the latitude circle (Sec. 4.4, open curves C): the
+    points of the circle whose horizontal direction lies counter-clockwise
+    from the unit direction a to the unit direction b.  cp_C is the circle's
+    closest point when x's horizontal direction lies in the arc and the
+    nearer endpoint otherwise (squared distances compared, ties to the start).
+    at_boundary(X) flags Omega(dC), the nodes whose cp_C is an endpoint
+    (eq. IBC_boundary_set)."""
+
+    def __init__(self, sphere, z0, a, b):
+        super().__init__(sphere, z0)
+        self.a = np.asarray(a, dtype=np.float64)
+        self.b = np.asarray(b, dtype=np.float64)
+
+    def _inside(self, X):
+        dx = X[:, 0] - self.c[0]
+        dy = X[:, 1] - self.c[1]
+        a0, a1 = self.a
+        b0, b1 = self.b
+        ca = a0 * dy - a1 * dx          # a x u
+        cb = dx * b1 - dy * b0          # u x b
+        if a0 * b1 - a1 * b0 >= 0.0:     # arc of at most a half turn
+            return (ca >= 0.0) & (cb >= 0.0)
+        return (ca >= 0.0) | (cb >= 0.0)
+
+    def endpoints(self):
+        z = self.c[2] + self.z0
+        e0 = np.array([self.c[0] + self.rho0 * self.a[0], self.c[1] + self.rho0 * self.a[1], z])
+        e1 = np.array([self.c[0] + self.rho0 * self.b[0], self.c[1] + self.rho0 * self.b[1], z])
+        return e0, e1
+
+    def cp(self, X):
+        P = super().cp(X)
+        inside = self._inside(X)
+        e0, e1 = self.endpoints()
+        D0, D1 = X - e0, X - e1
+        d0 = (D0[:, 0] * D0[:, 0] + D0[:, 1] * D0[:, 1]) + D0[:, 2] * D0[:, 2]
+        d1 = (D1[:, 0] * D1[:, 0] + D1[:, 1] * D1[:, 1]) + D1[:, 2] * D1[:, 2]
+        E = np.where((d1 < d0)[:, None], e1, e0)
+        return np.where(inside[:, None], P, E)
+
+    def at_boundary(self, X):
+        return ~self._inside(X)
+
+
 class MeridianC:
     """A meridian (poloidal) circle of a torus: the tube circle in the vertical
     plane through the torus axis with horizontal unit direction (ex, ey).  Its

@@ -154,6 +154,8 @@ class CPMSystem:
                 X = node_coords(K, N)
                 D = X - curve.cp(X)
                 st.in_check = np.sqrt(dot_rows(D, D)) < check_factor * self.r
+                if hasattr(curve, "at_boundary"):
+                    st.in_check &= ~curve.at_boundary(X)
             self.sets.append(st)
             amap = np.full(n_s, -1, dtype=np.int64)
             amap[st.omega_nodes] = nxt + np.arange(st.omega_nodes.size)
@@ -273,17 +275,23 @@ class CPMSystem:
         rr = np.repeat(np.arange(n_s), 2 * d)[present.ravel()]
         cc = cols.ravel()[present.ravel()]
         r_idx, c_idx = [rr], [cc]
-        # BC rows: neighbours restricted to Omega(C) (eq. FD-crossing-test)
+        # BC rows: neighbours restricted to Omega(C) (eq. FD-crossing-test);
+        # past the end of an open curve the solution is single valued, so a
+        # neighbour there without a BC DOF is its PDE DOF
+        X = node_coords(self.K, self.N)
         for st, amap in zip(self.sets, self.alpha_of):
             nodes = st.omega_nodes
             if nodes.size == 0:
                 continue
+            past = (st.curve.at_boundary(X) if hasattr(st.curve, "at_boundary")
+                    else np.zeros(n_s, dtype=bool))
             NBn = NB[nodes]
             ok = NBn >= 0
             NBc = np.where(ok, NBn, 0)
-            ok &= amap[NBc] >= 0
+            has_bc = amap[NBc] >= 0
+            ok &= has_bc | past[NBc]
             dot = dot_rows(st.v[nodes][:, None, :], st.v[NBc])
-            col = np.where(dot < 0.0, NBc, amap[NBc])
+            col = np.where(has_bc, np.where(dot < 0.0, NBc, amap[NBc]), NBc)
             r_idx.append(np.repeat(amap[nodes], 2 * d)[ok.ravel()])
             c_idx.append(col.ravel()[ok.ravel()])
         r_idx = np.concatenate(r_idx)

@@ -138,3 +138,32 @@ def test_omega_c_and_check_region_are_the_definitions():
     assert sysm.n_c == int(np.sum(d <= r))
     # BC DOFs are numbered after the PDE DOFs (Sec. 4.1)
     assert sysm.n == sysm.n_s + sysm.n_c
+
+
+@pytest.mark.parametrize("a_ang,b_ang", [(-0.75 * np.pi, 0.25 * np.pi), (0.3, 0.3 + 1.4 * np.pi)])
+def test_latitude_arc_cp_and_boundary_brute_force(a_ang, b_ang):
+    """cp_C of an open arc (Sec. 4.4) is the nearest arc point (brute force
+    over a fine sampling of the arc, half-turn and longer arcs) and Omega(dC)
+    (eq. IBC_boundary_set) is exactly where the nearest arc point is an
+    endpoint."""
+    S = G.Sphere()
+    z0 = 0.3
+    arc = G.LatitudeArc(S, z0, (np.cos(a_ang), np.sin(a_ang)), (np.cos(b_ang), np.sin(b_ang)))
+    rho0 = np.sqrt(1 - z0 * z0)
+    span = (b_ang - a_ang) % (2 * np.pi)
+    t = a_ang + span * np.linspace(0.0, 1.0, 20001)
+    P = np.stack([rho0 * np.cos(t), rho0 * np.sin(t), np.full(t.size, z0)], axis=1)
+    X = _pts(400, 3, 1.3, 11)
+    X = X[np.abs(np.linalg.norm(X, axis=1) - 1.0) < 0.3]
+    CP = arc.cp(X)
+    end = arc.at_boundary(X)
+    for x, c, e in zip(X, CP, end):
+        d = np.linalg.norm(P - x, axis=1)
+        k = int(np.argmin(d))
+        assert np.linalg.norm(c - x) <= d[k] + 1e-12
+        assert np.linalg.norm(c - x) >= d[k] - 2e-4
+        if k not in (0, t.size - 1) and d[k] < min(d[0], d[-1]) - 1e-3:
+            assert not e
+        if k in (0, t.size - 1) and d[k] < np.min(d[1:-1]) - 1e-9:
+            assert e
+    assert end.any() and (~end).any()

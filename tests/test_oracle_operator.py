@@ -411,3 +411,52 @@ def test_point_ibc_on_sphere_second_order():
     errs = [_sphere_point(N, 2) for N in Ns]
     assert fit_slope(1.0 / np.array(Ns), errs) > 1.7, errs
     assert _sphere_point(16, 2, shift=1.0) > 0.5
+
+
+def _arc(z0, a_ang, b_ang):
+    return G.LatitudeArc(G.Sphere(), z0, (np.cos(a_ang), np.sin(a_ang)),
+                         (np.cos(b_ang), np.sin(b_ang)))
+
+
+def test_open_arc_structure():
+    """Open curve (Sec. 4.4): nodes whose cp_C is an endpoint get no BC DOF and
+    their rows are not modified; the BC DOFs scale with the arc length."""
+    N = 24
+    full = O.CPMSystem(G.Sphere(), N, [G.LatitudeC(G.Sphere(), 0.3)])
+    half = O.CPMSystem(G.Sphere(), N, [_arc(0.3, -0.75 * np.pi, 0.25 * np.pi)])
+    assert 0.4 < half.n_c / full.n_c < 0.6
+    st = half.sets[0]
+    X = half.K / float(N)
+    end = st.curve.at_boundary(X)
+    assert not np.any(st.in_omega & end) and not np.any(st.in_check & end)
+    # rows of end nodes use PDE DOFs only
+    rows = np.nonzero(end)[0]
+    E = half.E[rows].tocoo()
+    L = half.L_off[rows].tocoo()
+    assert np.all(E.col < half.n_s) and np.all(L.col < half.n_s)
+
+
+def _arc_poisson_error(N, curve, bc_types, u_of, f_of, g_of, m):
+    sysm = O.CPMSystem(G.Sphere(), N, [curve], bc_types=bc_types)
+    u_ex, f = u_of(sysm.CP), f_of(sysm.CP)
+    g = g_of(sysm.bc_cpc)
+    u, info = KR.bicgstab(lambda x: sysm.apply(x, m, -1.0), sysm.rhs(f, g, -1.0), tol=1e-10)
+    assert info["converged"], info
+    return np.max(np.abs(sysm.surface_values(u, g) - u_ex))
+
+
+def test_open_arc_dirichlet_and_neumann_second_order():
+    """Consistent data on an open arc: Dirichlet (spherical harmonics, Poisson)
+    and zero Neumann on an equator arc (u = x, screened Poisson) converge at
+    second order."""
+    coeffs = inputs.sphere_coeffs(8, lmin=1, lmax=4)
+    u_h = lambda P: inputs.sphere_field(coeffs, P)                              # noqa: E731
+    f_h = lambda P: inputs.sphere_field(coeffs, P, scale=lambda l: l * (l + 1))  # noqa: E731
+    Ns = [16, 24, 32]
+    ed = [_arc_poisson_error(N, _arc(0.3, -0.75 * np.pi, 0.25 * np.pi), None, u_h, f_h, u_h, 0.0)
+          for N in Ns]
+    assert fit_slope(1.0 / np.array(Ns), ed) > 1.7, ed
+    en = [_arc_poisson_error(N, _arc(0.0, 0.3, 0.3 + 1.4 * np.pi), [("neumann", "neumann")],
+                             lambda P: P[:, 0], lambda P: 3.0 * P[:, 0], lambda P: P[:, 0], 1.0)
+          for N in Ns]
+    assert fit_slope(1.0 / np.array(Ns), en) > 1.7, en
