@@ -67,8 +67,14 @@ typedef struct {
 
 enum { CPM_IBC_POINT = 1,     /* C = {p}; orient = o_C given by the caller   */
        CPM_IBC_LATITUDE = 2,  /* sphere only: circle at height center_z + z0 */
-       CPM_IBC_MERIDIAN = 3 };/* torus only: poloidal circle in the vertical
+       CPM_IBC_MERIDIAN = 3,  /* torus only: poloidal circle in the vertical
                                  plane with horizontal unit direction dir   */
+       CPM_IBC_LATITUDE_ARC = 4 }; /* sphere only: the open arc of the
+                                 LATITUDE circle running counter-clockwise
+                                 from the horizontal unit direction
+                                 (arc[0], arc[1]) to (arc[2], arc[3]) (Sec.
+                                 4.4: no BC DOF and no stencil change where
+                                 cp_C is an endpoint)                       */
 
 /* Condition imposed on one side of an interior boundary (Sec. 4.3).  Each
  * side carries its own (Sec. 4.2: two-sided and mixed IBCs).  The sides are
@@ -91,6 +97,7 @@ typedef struct {
   double dir[2];     /* MERIDIAN: (ex, ey), a unit vector                     */
   int bc[2];         /* CPM_BC_* of side +1 and of side -1; zero-initialised
                         = Dirichlet on both sides                            */
+  double arc[4];     /* LATITUDE_ARC: start and end directions (unit)         */
 } cpm_ibc;
 
 typedef struct {

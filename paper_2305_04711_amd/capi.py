@@ -19,7 +19,7 @@ STATUS_NAMES = {0: "CPM_OK", -1: "CPM_E_INVALID", -2: "CPM_E_STENCIL_HOLE", -3: 
 
 SURF_CIRCLE, SURF_SPHERE, SURF_TORUS = 1, 2, 3
 BC_DIRICHLET, BC_NEUMANN = 0, 1
-IBC_POINT, IBC_LATITUDE, IBC_MERIDIAN = 1, 2, 3
+IBC_POINT, IBC_LATITUDE, IBC_MERIDIAN, IBC_LATITUDE_ARC = 1, 2, 3, 4
 EXPORT_COORDS, EXPORT_CP, EXPORT_BC_NODE, EXPORT_BC_CPC, EXPORT_BC_SIDE, EXPORT_BC_CURVE, \
     EXPORT_ECOLS, EXPORT_LCOLS, EXPORT_BASE = range(1, 10)
 F64, F32 = 0, 1
@@ -33,7 +33,8 @@ class Surface(C.Structure):
 
 class IBC(C.Structure):
     _fields_ = [("kind", C.c_int), ("p", C.c_double * 3), ("orient", C.c_double * 3),
-                ("z0", C.c_double), ("dir", C.c_double * 2), ("bc", C.c_int * 2)]
+                ("z0", C.c_double), ("dir", C.c_double * 2), ("bc", C.c_int * 2),
+                ("arc", C.c_double * 4)]
 
 
 class Grid(C.Structure):

@@ -59,6 +59,15 @@ def latitude_ibc(z0, bc="dirichlet"):
                     (C.c_double * 2)(0.0, 0.0), _bc(bc))
 
 
+def latitude_arc_ibc(z0, a, b, bc="dirichlet"):
+    """Open arc of the latitude circle from unit direction a to unit direction
+    b, counter-clockwise (Sec. 4.4)."""
+    ib = capi.IBC(capi.IBC_LATITUDE_ARC, (C.c_double * 3)(), (C.c_double * 3)(), z0,
+                  (C.c_double * 2)(0.0, 0.0), _bc(bc))
+    ib.arc[0], ib.arc[1], ib.arc[2], ib.arc[3] = float(a[0]), float(a[1]), float(b[0]), float(b[1])
+    return ib
+
+
 def meridian_ibc(ex, ey, bc="dirichlet"):
     return capi.IBC(capi.IBC_MERIDIAN, (C.c_double * 3)(), (C.c_double * 3)(), 0.0,
                     (C.c_double * 2)(ex, ey), _bc(bc))

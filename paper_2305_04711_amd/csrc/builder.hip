@@ -245,6 +245,8 @@ __global__ __launch_bounds__(256) void k_ibc_rows(Blocks B, int nb, cpm_surface 
   const V3 q = load_v(cp, n_s, dof, DIM);
   int rc = -1, om = 0;
   for (int c = 0; c < L.n; ++c) {
+    // past the end of an open curve: neither BC DOFs nor stencil changes
+    if (curve_at_end(S, L.c[c], p)) continue;
     const V3 pc = cp_curve<DIM>(S, L.c[c], p);
     const double dC = dist<DIM>(p, pc);
     if (dC < cf * r) {
@@ -575,9 +577,10 @@ __global__ __launch_bounds__(256) void k_lrow_pde(Blocks B, int nb, int64_t n_s,
 // FD rows of BC DOFs (eq. FD-crossing-test): neighbours outside Omega(C) are
 // removed; a neighbour stays a BC DOF unless it lies on the other side.
 template <int DIM>
-__global__ void k_lrow_bc(Blocks B, int64_t n_s, int64_t n_c, const int* bc_node,
-                          const int* bc_k, const int* row_c, const int* alpha_of,
-                          const double* side_v, int r0, int* lrow_id, int* lcol, int* lcol0) {
+__global__ void k_lrow_bc(Blocks B, int N, cpm_surface S, IBCList L, int64_t n_s, int64_t n_c,
+                          const int* bc_node, const int* bc_k, const int* row_c,
+                          const int* alpha_of, const double* side_v, int r0, int* lrow_id,
+                          int* lcol, int* lcol0) {
   using G = Geo<DIM>;
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n_c) return;
@@ -594,8 +597,15 @@ __global__ void k_lrow_bc(Blocks B, int64_t n_s, int64_t n_c, const int* bc_node
     m[f >> 1] += (f & 1) ? 1 : -1;
     const int q = node_dof<DIM>(B, blk, m[0], m[1], m[2]);
     int col = -1;
-    if (q >= 0 && alpha_of[q] >= 0 && row_c[q] == rc)
+    if (q >= 0 && alpha_of[q] >= 0 && row_c[q] == rc) {
       col = dot3<DIM>(vj, load_v(side_v, n_s, q, DIM)) < 0.0 ? q : alpha_of[q];
+    } else if (q >= 0) {
+      // past the end of an open curve the solution is single valued: a
+      // neighbour there without a BC DOF is its PDE DOF
+      int qk[3] = {kk[0], kk[1], kk[2]};
+      qk[f >> 1] += (f & 1) ? 1 : -1;
+      if (curve_at_end(S, L.c[rc], node_pos(qk[0], qk[1], DIM == 3 ? qk[2] : 0, N))) col = q;
+    }
     lcol0[r * 2 * DIM + f] = -1;
     lcol[r * 2 * DIM + f] = col;
   }
@@ -968,9 +978,9 @@ void build(cpm_band* b, hipStream_t st) {
                          b->lrow_mask);
     CPM_LAUNCH_CHECK();
     if (n_c)
-      hipLaunchKernelGGL(k_lrow_bc<DIM>, dim3(grid_for(n_c, 128)), dim3(128), 0, st, B, n_s, n_c,
-                         b->bc_node, bc_kp->p, row_c.p, alpha_of.p, side_v.p, (int)nl_pde,
-                         b->lrow_id, b->lcol, b->lcol0);
+      hipLaunchKernelGGL(k_lrow_bc<DIM>, dim3(grid_for(n_c, 128)), dim3(128), 0, st, B, N, S, L,
+                         n_s, n_c, b->bc_node, bc_kp->p, row_c.p, alpha_of.p, side_v.p,
+                         (int)nl_pde, b->lrow_id, b->lcol, b->lcol0);
     CPM_LAUNCH_CHECK();
   }
   // metadata read by the apply kernels
@@ -1048,8 +1058,12 @@ extern "C" cpm_status cpm_build_band(const cpm_surface* surface, const cpm_ibc* 
       CPM_FAIL(CPM_E_INVALID, "bad surface radii");
     for (int c = 0; c < n_ibc; ++c) {
       const int k = ibcs[c].kind;
-      const bool ok = k == CPM_IBC_POINT || (k == CPM_IBC_LATITUDE && kind == CPM_SURF_SPHERE &&
-                                              std::fabs(ibcs[c].z0) < surface->R) ||
+      const bool arc_ok = k != CPM_IBC_LATITUDE_ARC ||
+                          (std::hypot(ibcs[c].arc[0], ibcs[c].arc[1]) > 0.5 &&
+                           std::hypot(ibcs[c].arc[2], ibcs[c].arc[3]) > 0.5);
+      const bool ok = k == CPM_IBC_POINT ||
+                      ((k == CPM_IBC_LATITUDE || k == CPM_IBC_LATITUDE_ARC) &&
+                       kind == CPM_SURF_SPHERE && std::fabs(ibcs[c].z0) < surface->R && arc_ok) ||
                       (k == CPM_IBC_MERIDIAN && kind == CPM_SURF_TORUS);
       if (!ok) CPM_FAIL(CPM_E_INVALID, "interior boundary %d (kind %d) does not fit surface kind %d", c, k, kind);
       for (int s2 = 0; s2 < 2; ++s2) {

@@ -62,14 +62,43 @@ __device__ __forceinline__ V3 cp_surface(const cpm_surface& S, const V3& p) {
   return V3{cx + (qx + ex * t), cy + (qy + ey * t), cz + dz * t};
 }
 
-// cp_C for a point, a latitude circle of a sphere, a meridian of a torus.
+// Open latitude arc: does the horizontal direction of p lie in the arc
+// (counter-clockwise from a to b)?  Sign tests of cross products only.
+__device__ __forceinline__ bool arc_inside(const cpm_surface& S, const cpm_ibc& C, const V3& p) {
+  const double dx = p.x - S.center[0], dy = p.y - S.center[1];
+  const double a0 = C.arc[0], a1 = C.arc[1], b0 = C.arc[2], b1 = C.arc[3];
+  const double ca = a0 * dy - a1 * dx;
+  const double cb = dx * b1 - dy * b0;
+  if (a0 * b1 - a1 * b0 >= 0.0) return ca >= 0.0 && cb >= 0.0;
+  return ca >= 0.0 || cb >= 0.0;
+}
+
+// Is cp_C(p) an endpoint of an open curve (Omega(dC), eq. IBC_boundary_set)?
+__device__ __forceinline__ bool curve_at_end(const cpm_surface& S, const cpm_ibc& C,
+                                             const V3& p) {
+  return C.kind == CPM_IBC_LATITUDE_ARC && !arc_inside(S, C, p);
+}
+
+// cp_C for a point, a latitude circle or arc of a sphere, a meridian of a
+// torus.  For an arc outside its angular range: the nearer endpoint (squared
+// distances, ties to the start).
 template <int DIM>
 __device__ __forceinline__ V3 cp_curve(const cpm_surface& S, const cpm_ibc& C,
                                        const V3& p) {
   if (C.kind == CPM_IBC_POINT) return V3{C.p[0], C.p[1], DIM == 3 ? C.p[2] : 0.0};
   const double cx = S.center[0], cy = S.center[1], cz = S.center[2];
-  if (C.kind == CPM_IBC_LATITUDE) {
+  if (C.kind == CPM_IBC_LATITUDE || C.kind == CPM_IBC_LATITUDE_ARC) {
     const double rho0 = sqrt(S.R * S.R - C.z0 * C.z0);
+    if (C.kind == CPM_IBC_LATITUDE_ARC && !arc_inside(S, C, p)) {
+      const double z = cz + C.z0;
+      const V3 e0{cx + rho0 * C.arc[0], cy + rho0 * C.arc[1], z};
+      const V3 e1{cx + rho0 * C.arc[2], cy + rho0 * C.arc[3], z};
+      const double d0x = p.x - e0.x, d0y = p.y - e0.y, d0z = p.z - e0.z;
+      const double d1x = p.x - e1.x, d1y = p.y - e1.y, d1z = p.z - e1.z;
+      const double d0 = (d0x * d0x + d0y * d0y) + d0z * d0z;
+      const double d1 = (d1x * d1x + d1y * d1y) + d1z * d1z;
+      return d1 < d0 ? e1 : e0;
+    }
     const double dx = p.x - cx, dy = p.y - cy;
     const double q = sqrt(dx * dx + dy * dy);
     const double s = rho0 / q;
@@ -91,7 +120,7 @@ template <int DIM>
 __device__ __forceinline__ V3 orient_curve(const cpm_surface& S,
                                            const cpm_ibc& C, const V3& cpc) {
   if (C.kind == CPM_IBC_POINT) return V3{C.orient[0], C.orient[1], DIM == 3 ? C.orient[2] : 0.0};
-  if (C.kind == CPM_IBC_LATITUDE) {
+  if (C.kind == CPM_IBC_LATITUDE || C.kind == CPM_IBC_LATITUDE_ARC) {
     const double rho0 = sqrt(S.R * S.R - C.z0 * C.z0);
     const double ux = (cpc.x - S.center[0]) / rho0;
     const double uy = (cpc.y - S.center[1]) / rho0;

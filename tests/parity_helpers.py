@@ -42,6 +42,15 @@ def oracle_and_gpu(cfg, N, order=2):
         S = G.Sphere()
         Cs = [G.PointC(pt, o)]
         gs, gi = cpm.sphere(), [cpm.point_ibc(pt, o)]
+    elif cfg in ("sphere_arc", "sphere_arc_neumann"):
+        if cfg == "sphere_arc":
+            z0, a0, a1, bct = 0.3, -0.75 * np.pi, 0.25 * np.pi, [("dirichlet", "dirichlet")]
+        else:
+            z0, a0, a1, bct = 0.0, 0.3, 0.3 + 1.4 * np.pi, [("neumann", "neumann")]
+        a, b = (np.cos(a0), np.sin(a0)), (np.cos(a1), np.sin(a1))
+        S = G.Sphere()
+        Cs = [G.LatitudeArc(S, z0, a, b)]
+        gs, gi = cpm.sphere(), [cpm.latitude_arc_ibc(z0, a, b, bc=bct[0])]
     elif cfg == "sphere_eq_neumann":
         S = G.Sphere()
         Cs, bct = [G.LatitudeC(S, 0.0)], [("neumann", "neumann")]
@@ -58,14 +67,14 @@ def oracle_and_gpu(cfg, N, order=2):
         gs, gi = cpm.circle(), [ib]
     else:
         raise KeyError(cfg)
-    bc_types = bct if cfg in NEUMANN_CASES else None
+    bc_types = bct if cfg in NEUMANN_CASES or cfg == "sphere_arc" else None
     sysm = O.CPMSystem(S, N, Cs, order=order, bc_types=bc_types)
     band = cpm.Band(gs, gi, N, order=order)
     return sysm, band
 
 
 # configurations with a zero-Neumann side (screened operators: m = 1)
-NEUMANN_CASES = ("sphere_eq_neumann", "sphere_eq_mixed", "circle_mixed")
+NEUMANN_CASES = ("sphere_eq_neumann", "sphere_eq_mixed", "circle_mixed", "sphere_arc_neumann")
 
 
 def dof_map(sysm, band):

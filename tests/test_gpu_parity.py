@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 CASES = [("circle_point", 32), ("circle_jump", 64), ("sphere", 16), ("sphere_lat", 16),
          ("sphere_lat", 27), ("torus", 12), ("torus_meridians", 16),
          ("sphere_eq_neumann", 16), ("sphere_eq_mixed", 19), ("circle_mixed", 40),
-         ("sphere_point", 20)]
+         ("sphere_point", 20), ("sphere_arc", 24), ("sphere_arc_neumann", 21)]
 
 
 @pytest.fixture(scope="module")
@@ -152,7 +152,8 @@ def test_rhs_and_rhs_adjoint_match_oracle(torch_cuda, cfg, N):
 @pytest.mark.parametrize("mode", ["f64", "mixed"])
 @pytest.mark.parametrize("cfg,N", [("circle_point", 32), ("sphere_lat", 16), ("torus_meridians", 16),
                                    ("sphere_eq_mixed", 16), ("circle_mixed", 32),
-                                   ("sphere_point", 16)])
+                                   ("sphere_point", 16), ("sphere_arc", 16),
+                                   ("sphere_arc_neumann", 16)])
 def test_solve_matches_oracle(torch_cuda, cfg, N, mode):
     torch = torch_cuda
     from paper_2305_04711_amd import cpm
