@@ -39,19 +39,18 @@ BYTES_PER_ROW_F32 = 24.0   # tile gather: fraction 12 + base 4 + u 4 + a 4 (FP32
 # rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; summaries and commands in
 # profiles/gather_torus512_pmc.md), each scaled by the same counter's reading
 # for a plain device copy of known size.  They hold only for the kernel
-# sources they were taken on: `traffic` is null when the hash differs.
-GATHER_PMC = {"sources_sha1": "3a0b2d07d43a9a45c7f2062ae8767b4696585926",
+# source they were taken on: `traffic` is null when its hash differs.
+GATHER_PMC = {"sources_sha1": "bf12c7b47de1a89afc33d0c11f79d912b5970fa1",
               "fetch_bytes": 1.72562e+09, "write_bytes": 3.40212e+08}
-GATHER_SOURCES = ["paper_2305_04711_amd/csrc/apply.hip", "paper_2305_04711_amd/csrc/cpm_internal.hpp",
-                  "paper_2305_04711_amd/csrc/lagrange.hpp"]
-
-
 def gather_sources_sha1():
+    """Hash of the FP64 tile gather's own source: the k_gather template, the
+    row and cube helpers it calls, and the Lagrange weights."""
     import hashlib
-    h = hashlib.sha1()
-    for f in GATHER_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+    src = open(os.path.join(ROOT, "paper_2305_04711_amd/csrc/apply.hip")).read()
+    a = src.index("struct TileView {")
+    b = src.index("template <class T>\n__device__ __forceinline__ T wave_sum")
+    h = hashlib.sha1(src[a:b].encode())
+    h.update(open(os.path.join(ROOT, "paper_2305_04711_amd/csrc/lagrange.hpp"), "rb").read())
     return h.hexdigest()
 
 
