@@ -672,17 +672,19 @@ struct RU {
   }
 };
 
-enum { RU_CONVERGED = 0, RU_STALLED = 1, RU_MAXIT = 2, RU_NONFINITE = 3 };
+enum { RU_CONVERGED = 0, RU_STALLED = 1, RU_MAXIT = 2 };
 
 // Runs a recurrence of precision T with reliable updates until the FP64
 // residual reaches tol.  An update happens when the recursive residual has
 // dropped by delta since the last one, when the recurrence stops (converged
 // or broken down), or after max_cycle iterations without either.  It adds
 // sigma d into x, recomputes r = b - A x in FP64 and substitutes it for the
-// recursive residual (k_replace).  The run ends (RU_STALLED, with x and r64
-// current) at the first update that fails to halve the FP64 residual of the
-// previous one, that follows a breakdown, or whose recursive residual
-// underestimates the true one by more than 1.5x.
+// recursive residual (k_replace).  The run ends (RU_STALLED) at the first
+// update that fails to halve the FP64 residual of the previous one, that was
+// forced by max_cycle (the recurrence converges far slower than it did), that
+// follows a breakdown, or whose recursive residual underestimates the true
+// one by more than 1.5x; an update that left the FP64 residual above the
+// previous one is taken back first, so x is the best iterate of the run.
 template <class T>
 int ru_run(RU& c, Bicg<T>& k, T* d, double rn, int max_cycle) {
   const int64_t n = c.b->n;
@@ -699,7 +701,8 @@ int ru_run(RU& c, Bicg<T>& k, T* d, double rn, int max_cycle) {
     const double rrec = std::sqrt(h.rr);
     const bool bad = !__builtin_isfinite(h.rr);
     if (!bad) maxr = std::max(maxr, rrec);
-    if (!(h.done || bad || rrec < c.delta * maxr || h.it - cycle0 >= max_cycle)) continue;
+    const bool forced = h.it - cycle0 >= max_cycle;
+    if (!(h.done || bad || rrec < c.delta * maxr || forced)) continue;
     const bool broken = h.breakdown || bad;
     if (!bad) {   // a non-finite recursion leaves x as it was at the last update
       hipLaunchKernelGGL(k_addT<T>, dim3(eg), dim3(256), 0, c.st, n, c.x, d, c.sigma);
@@ -714,8 +717,15 @@ int ru_run(RU& c, Bicg<T>& k, T* d, double rn, int max_cycle) {
                    sizeof(T) == 4 ? "FP32" : "FP64", c.stt->outer_iters, rrec * c.sigma / c.bn,
                    c.stt->relres, c.its, broken ? " (breakdown)" : "");
     if (c.stt->relres <= c.tol) return RU_CONVERGED;
-    if (!__builtin_isfinite(rn)) return RU_NONFINITE;
-    if (broken || !(rn < 0.5 * prev) || rn > 1.5 * rrec * c.sigma) return RU_STALLED;
+    if (!__builtin_isfinite(rn) || !(rn <= prev)) {
+      if (!bad) {   // take the update back
+        hipLaunchKernelGGL(k_addT<T>, dim3(eg), dim3(256), 0, c.st, n, c.x, d, -c.sigma);
+        CPM_LAUNCH_CHECK();
+      }
+      c.stt->relres = prev / c.bn;
+      return RU_STALLED;
+    }
+    if (broken || forced || !(rn < 0.5 * prev) || rn > 1.5 * rrec * c.sigma) return RU_STALLED;
     prev = rn;
     maxr = rn * inv;
     cycle0 = h.it;
@@ -743,8 +753,13 @@ void solve_one(const cpm_band* b, const cpm_solve_opts& o, const double* rhs, do
   CPM_HIP(hipMemsetAsync(S, 0, sizeof(Scal), st));
   Pinned pin;
   int its = 0, restarts = 0;
+  // Plain FP64 BiCGSTAB, restarted from the current x while the recursive
+  // residual has drifted from the true one.  The iterate of smallest true
+  // residual is kept, so a pass cut short by maxit never returns a worse one.
   auto plain64 = [&](double tol_) {
     Bicg<double> k(b, st, o.m, o.n, gamma, tr, 30);
+    double* xbest = nullptr;
+    double best = HUGE_VAL;
     for (int rep = 0; rep < 20 && its < maxit; ++rep) {
       its += k.solve(rhs, x, false, tol_, maxit - its, ce, graph, &restarts);
       auto rb = residual64(b, st, o.m, o.n, gamma, tr, rhs, x, r64, v64, part, S, pin);
@@ -754,7 +769,15 @@ void solve_one(const cpm_band* b, const cpm_solve_opts& o, const double* rhs, do
         std::fprintf(stderr, "[cpm] f64 pass %d relres %.3e iterations %d restarts %d\n", rep,
                      stt.relres, its, restarts);
       if (stt.relres <= tol) return true;
-      // the recursive residual drifted from the true one: restart
+      if (stt.relres < best) {
+        if (!xbest) xbest = (double*)band_scratch(b, 28, sizeof(double) * n);
+        CPM_HIP(hipMemcpyAsync(xbest, x, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        best = stt.relres;
+      }
+    }
+    if (xbest && !(stt.relres <= best)) {
+      CPM_HIP(hipMemcpyAsync(x, xbest, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+      stt.relres = best;
     }
     return false;
   };
@@ -789,7 +812,7 @@ void solve_one(const cpm_band* b, const cpm_solve_opts& o, const double* rhs, do
     hipLaunchKernelGGL(k_zero_scal, dim3(1), dim3(64), 0, st, k32.S);
     CPM_LAUNCH_CHECK();
     k32.init(r32, d32, true, 0.5 * tol * c.bn * inv);
-    const int status = ru_run<float>(c, k32, d32, rn, 400);
+    const int status = ru_run<float>(c, k32, d32, rn, 200);
     its += c.its;
     if (status == RU_CONVERGED) return true;
     if (status == RU_MAXIT) return false;

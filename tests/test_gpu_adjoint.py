@@ -78,14 +78,15 @@ def test_autograd_gradients_match_central_differences():
 
     def loss_at(ff, gg_):
         b = cpm.rhs(band, ff, gg_, -1.0)
-        u, st = cpm.solve(band, b, 0.0, -1.0, tol=1e-11, mode="mixed", raise_noconv=False)
+        u, st = cpm.solve(band, b, 0.0, -1.0, tol=5e-11, mode="mixed", raise_noconv=False)
         assert st["relres"] <= 1e-10, st
         return ((u[:band.n_s] - t) ** 2).sum().item()
 
     # b(f, g) is linear and the loss quadratic in (f, g), so central
     # differences carry no truncation error at any step; steps of 10 % and
     # 100 % of ||(f, g)|| keep the loss difference far above the solver's
-    # rounding-level error (relative residual 1e-11, condition ~1e5).
+    # rounding-level error (relative residual 5e-11, condition ~1e5; FP64
+    # BiCGSTAB stagnates near 1e-11 on this system).
     scale = torch.sqrt((f * f).sum() + (g * g).sum()).item()
     gen = torch.Generator(device="cuda")
     gen.manual_seed(41)
