@@ -7,9 +7,11 @@ BC DOFs N_S..N_S+N_C-1 (the nodes of Omega(C), lexicographic within each C,
 concatenated over the C's in the order given).
 
 Interpolation (eq. interp-stencil): for a query y the stencil is the (p+1)^d
-nodes b + {0..3}^d with b = floor(y N) - 1 per axis; the weights are the
-tensor product of 1-D barycentric-Lagrange weights (Berrut and Trefethen's
-second form) on the nodes 0, 1, 2, 3 at the query 1 + t, t = y N - floor(y N).
+nodes b + {0..p}^d; cubic (p = 3): b = floor(y N) - 1 per axis, t = y N -
+floor(y N); quadratic (p = 2, Sec. 7): the nearest nodes, b = floor(y N +
+1/2) - 1, t = y N - (b + 1).  The weights are the tensor product of 1-D
+barycentric-Lagrange weights (Berrut and Trefethen's second form) on the
+nodes 0..p at the query 1 + t.
 
 Laplacian (eq. FD-stencil): weight -2d N^2 on the centre and N^2 on each face
 neighbour in the band; a neighbour outside the band is dropped.
@@ -49,14 +51,16 @@ class StencilHole(RuntimeError):
     """A stencil member is not a band node (the band is too narrow)."""
 
 
-def lagrange_weights_1d(t):
-    """Barycentric-Lagrange weights on nodes z = 0, 1, 2, 3 at xi = 1 + t.
-    Barycentric weights for equispaced nodes: lam_j = (-1)^j C(3, j).
-    Returns an (n, 4) array; exact node hits give the unit vector."""
+def lagrange_weights_1d(t, p=3):
+    """Barycentric-Lagrange weights of degree p on nodes z = 0, 1, .., p at
+    xi = 1 + t.  Barycentric weights for equispaced nodes: lam_j = (-1)^j
+    C(p, j).  Returns an (n, p + 1) array; exact node hits give the unit
+    vector."""
+    from math import comb
     t = np.asarray(t, dtype=np.float64)
     xi = 1.0 + t
-    lam = np.array([1.0, -3.0, 3.0, -1.0])
-    diff = xi[:, None] - np.arange(4.0)[None, :]
+    lam = np.array([(-1.0) ** j * comb(p, j) for j in range(p + 1)])
+    diff = xi[:, None] - np.arange(p + 1.0)[None, :]
     hit = diff == 0.0
     with np.errstate(divide="ignore", invalid="ignore"):
         q = lam[None, :] / diff
@@ -67,28 +71,33 @@ def lagrange_weights_1d(t):
     return W
 
 
-def stencil(Y, N, dim):
-    """Base node b (n, d) and tensor weights (n, 4^d) for query points Y.
-    Member o (0 <= o < 4^d) has offset (o % 4, (o // 4) % 4, o // 16), first
-    axis fastest."""
+def stencil(Y, N, dim, p=3):
+    """Base node b (n, d) and tensor weights (n, (p+1)^d) for query points Y:
+    the (p+1)^d nodes b + {0..p}^d around y N.  Cubic (p = 3): b = floor(y N)
+    - 1, the query at b + 1 + t with t in [0, 1).  Quadratic (p = 2): the
+    nodes nearest to y N, b = floor(y N + 1/2) - 1, t in [-1/2, 1/2).
+    Member o has offset (o % (p+1), (o // (p+1)) % (p+1), o // (p+1)^2),
+    first axis fastest."""
     S = Y * float(N)
-    F = np.floor(S)
+    F = np.floor(S) if p == 3 else np.floor(S + 0.5)
     base = F.astype(np.int64) - 1
     T = S - F
-    Wax = [lagrange_weights_1d(T[:, a]) for a in range(dim)]
+    Wax = [lagrange_weights_1d(T[:, a], p) for a in range(dim)]
+    m = p + 1
     if dim == 2:
-        W = (Wax[1][:, :, None] * Wax[0][:, None, :]).reshape(-1, 16)
+        W = (Wax[1][:, :, None] * Wax[0][:, None, :]).reshape(-1, m * m)
     else:
         W = (Wax[2][:, :, None, None] * Wax[1][:, None, :, None]
-             * Wax[0][:, None, None, :]).reshape(-1, 64)
+             * Wax[0][:, None, None, :]).reshape(-1, m ** 3)
     return base, W
 
 
-def member_offsets(dim):
-    o = np.arange(4 ** dim)
-    cols = [o % 4, (o // 4) % 4]
+def member_offsets(dim, p=3):
+    m = p + 1
+    o = np.arange(m ** dim)
+    cols = [o % m, (o // m) % m]
     if dim == 3:
-        cols.append(o // 16)
+        cols.append(o // (m * m))
     return np.stack(cols, axis=1)
 
 
@@ -123,10 +132,11 @@ class CPMSystem:
 
     def __init__(self, surface, N, ibcs=(), order=2, p=3, q=1, r=None,
                  tau_factor=0.1, check_factor=2.0, bc_types=None):
-        if p != 3:
-            raise ValueError("only cubic interpolation (p = 3) is implemented")
+        if p not in (2, 3):
+            raise ValueError("interpolation degree p must be 2 or 3")
         d = surface.dim
         self.surface, self.N, self.dim = surface, int(N), d
+        self.p = int(p)
         self.h = 1.0 / N
         self.r = band_radius(N, d, p, q) if r is None else float(r)
         self.tau = tau_factor / float(N * N)
@@ -190,7 +200,7 @@ class CPMSystem:
 
     # ------------------------------------------------------------------
     def _members(self, base):
-        offs = member_offsets(self.dim)
+        offs = member_offsets(self.dim, self.p)
         MK = base[:, None, :] + offs[None, :, :]
         cols = self.index(MK)
         holes = int(np.sum(cols < 0))
@@ -202,8 +212,8 @@ class CPMSystem:
 
     def _build_E(self):
         n_s, d = self.n_s, self.dim
-        nm = 4 ** d
-        base, W = stencil(self.CP, self.N, d)
+        nm = (self.p + 1) ** d
+        base, W = stencil(self.CP, self.N, d, self.p)
         cols0 = self._members(base)                     # (n_s, nm) PDE DOFs
         cols = cols0.copy()
         # PDE-row swaps (eq. stencil-crossing-test)
@@ -241,7 +251,7 @@ class CPMSystem:
             if not np.any(use):
                 continue
             nodes, Y, sign = nodes[use], Y[use], sign[use]
-            b2, W2 = stencil(Y, self.N, d)
+            b2, W2 = stencil(Y, self.N, d, self.p)
             M = self._members(b2)
             dot = dot_rows(st.v[nodes][:, None, :], st.v[M])
             keep_bc = (dot >= 0.0) & (amap[M] >= 0)

@@ -460,3 +460,57 @@ def test_open_arc_dirichlet_and_neumann_second_order():
                              lambda P: P[:, 0], lambda P: 3.0 * P[:, 0], lambda P: P[:, 0], 1.0)
           for N in Ns]
     assert fit_slope(1.0 / np.array(Ns), en) > 1.7, en
+
+
+# ------------------------------------------------------------ p = 2 (Sec. 7)
+def test_quadratic_weights_equal_product_form():
+    t = np.concatenate([np.linspace(-0.5, 0.5, 1001, endpoint=False), [0.25 - 1e-17]])
+    W = O.lagrange_weights_1d(t, 2)
+    # Lagrange basis on nodes -1, 0, 1 at t (product form, written out)
+    P = np.stack([t * (t - 1) / 2, (1 - t) * (1 + t), t * (t + 1) / 2], axis=1)
+    assert np.max(np.abs(W - P)) < 1e-14
+    assert np.array_equal(O.lagrange_weights_1d(np.array([0.0]), 2)[0], [0, 1, 0])
+
+
+def test_quadratic_interpolation_reproduces_quadratics_only():
+    S = G.Sphere()
+    sysm = O.CPMSystem(S, 10, p=2)
+    X = sysm.K / 10.0
+    rng = np.random.default_rng(6)
+    for _ in range(4):
+        e = rng.integers(0, 3, 3)            # per-axis degree <= 2
+        c = rng.uniform(-0.3, 0.3, 3)
+        v = np.prod((X - c) ** e, axis=1)
+        a = sysm.E @ v
+        assert np.max(np.abs(a - np.prod((sysm.CP - c) ** e, axis=1))) < 1e-12
+    v = (X[:, 0] - 0.1) ** 3
+    assert np.max(np.abs(sysm.E @ v - (sysm.CP[:, 0] - 0.1) ** 3)) > 1e-4
+
+
+def test_quadratic_band_matches_tube_volume():
+    """eq. (bandwidth) with p = 2: r = sqrt(10.75) h in R^3; the band holds
+    the shell of that radius (within 1%) and no stencil hole."""
+    N = 32
+    sysm = O.CPMSystem(G.Sphere(), N, p=2)
+    r = np.sqrt(10.75) / N
+    assert abs(sysm.r - r) < 1e-15
+    vol = 4 * np.pi / 3 * ((1 + r) ** 3 - (1 - r) ** 3) * N ** 3
+    assert abs(sysm.n_s - vol) / vol < 0.01
+
+
+def test_latitude_closed_form_quadratic():
+    """Second-order Dirichlet IBC with quadratic stencils: converges at about
+    second order, less regularly than cubic (the paper's observation)."""
+    Ns = [16, 24, 32]
+    errs = []
+    for N in Ns:
+        C = G.LatitudeC(G.Sphere(), 0.3)
+        sysm = O.CPMSystem(G.Sphere(), N, [C], order=2, p=2)
+        g = np.sin(2 * np.arctan2(sysm.bc_cpc[:, 1], sysm.bc_cpc[:, 0]))
+        b = sysm.rhs(np.zeros(sysm.n_s), g, -1.0)
+        u, info = KR.bicgstab(lambda x: sysm.apply(x, 0.0, -1.0), b, tol=1e-10)
+        assert info["converged"]
+        errs.append(np.max(np.abs(sysm.surface_values(u, g) - latitude_harmonic(sysm.CP, 0.3))))
+    assert errs[0] > errs[1] > errs[2], errs
+    assert fit_slope(1.0 / np.array(Ns), errs) > 1.3, errs
+    assert errs[-1] < 2e-3
