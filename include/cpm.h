@@ -102,7 +102,8 @@ typedef struct {
 
 typedef struct {
   int N;               /* h = 1/N                                             */
-  int p;               /* interpolation degree; only 3 is supported           */
+  int p;               /* interpolation degree: 3 (cubic) or 2 (quadratic,
+                          nearest-node stencils, Sec. 7)                     */
   int order;           /* IBC order (Dirichlet and Neumann): 1 or 2 (Sec. 4.3) */
   int check_reach;     /* 1: reject h above the reach bound (Sec. 8 grid
                           resolution in practice)                           */

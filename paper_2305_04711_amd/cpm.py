@@ -79,12 +79,12 @@ class Band:
     for one surface and grid (h = 1/N)."""
 
     def __init__(self, surface, ibcs=(), N=64, order=2, r_band=0.0, tau_factor=0.0,
-                 check_factor=0.0, check_reach=False):
+                 check_factor=0.0, check_reach=False, p=3):
         lib = capi.load()
         self._lib = lib
         self.handle = None
         arr = (capi.IBC * max(1, len(ibcs)))(*ibcs) if ibcs else None
-        grid = capi.Grid(int(N), 3, int(order), int(bool(check_reach)), float(r_band),
+        grid = capi.Grid(int(N), int(p), int(order), int(bool(check_reach)), float(r_band),
                          float(tau_factor), float(check_factor))
         out = C.c_void_p()
         capi.check(lib.cpm_build_band(C.byref(surface), arr, len(ibcs), C.byref(grid),

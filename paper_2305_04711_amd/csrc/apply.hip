@@ -69,11 +69,12 @@ struct TileView {
   const float* frac32;
   const unsigned* lbase;
   int ntr;
+  int p;                  // interpolation degree: 3, or 2 (fourth weight 0)
 };
 
 static TileView tview(const cpm_band* b) {
   return TileView{b->tile_inst, b->inst_skip, b->tile_meta, b->tile_blk, b->tile_start, b->perm,
-                  b->frac64, b->frac32, b->lbase, b->n_tile_rows};
+                  b->frac64, b->frac32, b->lbase, b->n_tile_rows, b->p};
 }
 
 template <int DIM> struct Cube {
@@ -172,9 +173,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void k_
   __syncthreads();
   for (int pos = beg + lane; pos < end; pos += 64) {
     T wx[4], wy[4], wz[4];
-    lagrange4<T>(tt[0], wx);
-    lagrange4<T>(tt[1], wy);
-    if (DIM == 3) lagrange4<T>(tt[2], wz);
+    lagrange_p<T>(tv.p, tt[0], wx);
+    lagrange_p<T>(tv.p, tt[1], wy);
+    if (DIM == 3) lagrange_p<T>(tv.p, tt[2], wz);
     const int lx = lb[0], ly = lb[1], lz = lb[2];
     const int dof = tv.perm[pos];
     if (pos + 64 < end) row_stencil<T, DIM>(tv, pos + 64, N, lb, tt);
@@ -456,10 +457,10 @@ __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const
       int lb[3];
       T tt[3];
       row_stencil<T, DIM>(tv, pos, N, lb, tt);
-      lagrange4<T>(tt[0], wx);
-      lagrange4<T>(tt[1], wy);
+      lagrange_p<T>(tv.p, tt[0], wx);
+      lagrange_p<T>(tv.p, tt[1], wy);
       if (DIM == 3) {
-        lagrange4<T>(tt[2], wz);
+        lagrange_p<T>(tv.p, tt[2], wz);
 #pragma unroll
         for (int k = 0; k < 4; ++k) wz[k] *= ci;
       } else {

@@ -329,12 +329,14 @@ void build_composite(cpm_batch* B, hipStream_t st) {
   const cpm_band* b0 = B->bands[0];
   c->dim = b0->dim;
   c->N = b0->N;
+  c->p = b0->p;
   c->composite = true;
   int64_t nb = 0, nt = 0, ntr = 0, ne = 0, nl = 0;
   B->D.assign(ni + 1, 0);
   for (int i = 0; i < ni; ++i) {
     const cpm_band* b = B->bands[i];
     if (b->dim != c->dim) CPM_FAIL(CPM_E_INVALID, "a batch needs bands of one dimension");
+    if (b->p != c->p) CPM_FAIL(CPM_E_INVALID, "a batch needs bands of one interpolation degree");
     B->D[i + 1] = B->D[i] + b->n;
     nb += b->nb;
     nt += b->ntiles;

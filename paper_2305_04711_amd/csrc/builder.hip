@@ -65,6 +65,7 @@ struct Blocks {
   const unsigned long long* hkeys;
   const int* hvals;
   unsigned hcap;
+  int p;   // interpolation degree: 3 (cubic) or 2 (quadratic)
 };
 
 // DOF of the node at local coordinates (mx, my, mz) relative to block blk;
@@ -89,13 +90,16 @@ __device__ __forceinline__ int block_of(const Blocks& B, int kx, int ky, int kz)
                    block_key(kx >> G::SH, ky >> G::SH, DIM == 3 ? (kz >> G::SH) : 0));
 }
 
-// Stencil base (floor(y N) - 1) and fraction of a query point.
+// Stencil base and fraction of a query point (eq. interp-stencil): cubic,
+// the nodes floor(y N) - 1 .. + 2 with t = y N - floor(y N); quadratic, the
+// nearest nodes floor(y N + 1/2) - 1 .. + 1 with t = y N - floor(y N + 1/2).
+// Either way the query lies at base + 1 + t.
 template <int DIM>
-__device__ __forceinline__ void stencil_base(const V3& y, int N, int base[3], double t[3]) {
+__device__ __forceinline__ void stencil_base(const V3& y, int N, int p, int base[3], double t[3]) {
   const double dn = (double)N;
   const double s[3] = {y.x * dn, y.y * dn, y.z * dn};
   for (int a = 0; a < DIM; ++a) {
-    const double F = floor(s[a]);
+    const double F = p == 3 ? floor(s[a]) : floor(s[a] + 0.5);
     base[a] = (int)F - 1;
     t[a] = s[a] - F;
   }
@@ -319,7 +323,7 @@ __global__ __launch_bounds__(256) void k_stencil_scan(Blocks B, int nb, int N, i
   const V3 y = load_v(cp, n_s, dof, DIM);
   int base[3];
   double t[3];
-  stencil_base<DIM>(y, N, base, t);
+  stencil_base<DIM>(y, N, B.p, base, t);
   const int bb = block_of<DIM>(B, base[0], base[1], base[2]);
   const int lx = base[0] & (G::BX - 1), ly = base[1] & (G::BX - 1),
             lz = DIM == 3 ? (base[2] & (G::BX - 1)) : 0;
@@ -327,8 +331,9 @@ __global__ __launch_bounds__(256) void k_stencil_scan(Blocks B, int nb, int N, i
   V3 vi{0, 0, 0};
   if (rc >= 0) vi = load_v(side_v, n_s, dof, DIM);
   int holes = 0, swaps = 0, nobc = 0;
-  for (int o = 0; o < NM; ++o) {
-    const int a = o & 3, b = (o >> 2) & 3, c = o >> 4;
+  const int np = B.p + 1, nmp = DIM == 3 ? np * np * np : np * np;
+  for (int o = 0; o < nmp; ++o) {
+    const int a = o % np, b = (o / np) % np, c = o / (np * np);
     const int j = bb < 0 ? -1 : node_dof<DIM>(B, bb, lx + a, ly + b, lz + c);
     if (j < 0) {
       ++holes;
@@ -370,7 +375,7 @@ __global__ __launch_bounds__(256) void k_tile_count2(Blocks B, int nb, int N, in
   const V3 y = load_v(cp, n_s, dof, DIM);
   int base[3];
   double t[3];
-  stencil_base<DIM>(y, N, base, t);
+  stencil_base<DIM>(y, N, B.p, base, t);
   atomicAdd(&cnt2[(int64_t)bb * 64 + local_base_code<DIM>(base)], 1);
 }
 
@@ -387,7 +392,7 @@ __global__ __launch_bounds__(256) void k_tile_fill(Blocks B, int nb, int N, int6
   const V3 y = load_v(cp, n_s, dof, DIM);
   int base[3];
   double t[3];
-  stencil_base<DIM>(y, N, base, t);
+  stencil_base<DIM>(y, N, B.p, base, t);
   const int pos = atomicAdd(&pos2[(int64_t)bb * 64 + local_base_code<DIM>(base)], 1);
   perm[pos] = dof;
   for (int a = 0; a < DIM; ++a) {
@@ -429,17 +434,24 @@ __global__ __launch_bounds__(256) void k_erow_pde(Blocks B, int nb, int N, int64
   const V3 y = load_v(cp, n_s, dof, DIM);
   int base[3];
   double t[3];
-  stencil_base<DIM>(y, N, base, t);
+  stencil_base<DIM>(y, N, B.p, base, t);
   for (int a = 0; a < DIM; ++a) ebase[r * DIM + a] = base[a];
   double w[3][4];
-  for (int a = 0; a < DIM; ++a) lagrange4<double>(t[a], w[a]);
+  for (int a = 0; a < DIM; ++a) lagrange_p<double>(B.p, t[a], w[a]);
   const int bb = block_of<DIM>(B, base[0], base[1], base[2]);
   const int lx = base[0] & (G::BX - 1), ly = base[1] & (G::BX - 1),
             lz = DIM == 3 ? (base[2] & (G::BX - 1)) : 0;
   const int rc = row_c[dof];
   const V3 vi = load_v(side_v, n_s, dof, DIM);
+  const int np = B.p + 1, nmp = DIM == 3 ? np * np * np : np * np;
   for (int o = 0; o < NM; ++o) {
-    const int a = o & 3, b = (o >> 2) & 3, c = o >> 4;
+    if (o >= nmp) {   // quadratic stencils fill the first (p+1)^d slots
+      ecol[(int64_t)r * NM + o] = -1;
+      ew[(int64_t)r * NM + o] = 0.0;
+      ew32[(int64_t)r * NM + o] = 0.0f;
+      continue;
+    }
+    const int a = o % np, b = (o / np) % np, c = o / (np * np);
     int j = node_dof<DIM>(B, bb, lx + a, ly + b, lz + c);
     if (row_c[j] == rc && alpha_of[j] >= 0 &&
         dot3<DIM>(vi, load_v(side_v, n_s, j, DIM)) < 0.0)
@@ -496,18 +508,25 @@ __global__ void k_erow_bc(Blocks B, int N, int64_t n_s, int64_t n_c, int order,
   const double sgn = neumann ? 1.0 : -1.0;
   int base[3];
   double t[3];
-  stencil_base<DIM>(y, N, base, t);
+  stencil_base<DIM>(y, N, B.p, base, t);
   for (int a = 0; a < DIM; ++a) ebase[r * DIM + a] = base[a];
   double w[3][4];
-  for (int a = 0; a < DIM; ++a) lagrange4<double>(t[a], w[a]);
+  for (int a = 0; a < DIM; ++a) lagrange_p<double>(B.p, t[a], w[a]);
   const int bb = block_of<DIM>(B, base[0], base[1], base[2]);
   const int lx = base[0] & (G::BX - 1), ly = base[1] & (G::BX - 1),
             lz = DIM == 3 ? (base[2] & (G::BX - 1)) : 0;
   const int rc = row_c[j0];
   const V3 vj = load_v(side_v, n_s, j0, DIM);
   int holes = 0;
+  const int np = B.p + 1, nmp = DIM == 3 ? np * np * np : np * np;
   for (int o = 0; o < NM; ++o) {
-    const int a = o & 3, b = (o >> 2) & 3, c = o >> 4;
+    if (o >= nmp) {
+      ecol[(int64_t)r * NM + o] = -1;
+      ew[(int64_t)r * NM + o] = 0.0;
+      ew32[(int64_t)r * NM + o] = 0.0f;
+      continue;
+    }
+    const int a = o % np, b = (o / np) % np, c = o / (np * np);
     int m = bb < 0 ? -1 : node_dof<DIM>(B, bb, lx + a, ly + b, lz + c);
     if (m < 0) {
       ++holes;
@@ -674,16 +693,19 @@ __global__ __launch_bounds__(256) void k_export_rows(Blocks B, int nb, int N, in
     const V3 y = load_v(cp, n_s, dof, DIM);
     int base[3];
     double t[3];
-    stencil_base<DIM>(y, N, base, t);
+    stencil_base<DIM>(y, N, B.p, base, t);
     if (bases)
       for (int a = 0; a < DIM; ++a) bases[(int64_t)dof * DIM + a] = base[a];
     if (ecols) {
       const int bb = block_of<DIM>(B, base[0], base[1], base[2]);
       const int lx = base[0] & (G::BX - 1), ly = base[1] & (G::BX - 1),
                 lz = DIM == 3 ? (base[2] & (G::BX - 1)) : 0;
+      const int np = B.p + 1, nmp = DIM == 3 ? np * np * np : np * np;
       for (int o = 0; o < NM; ++o)
         ecols[(int64_t)dof * NM + o] =
-            bb < 0 ? -1 : node_dof<DIM>(B, bb, lx + (o & 3), ly + ((o >> 2) & 3), lz + (o >> 4));
+            (bb < 0 || o >= nmp) ? -1
+                                 : node_dof<DIM>(B, bb, lx + o % np, ly + (o / np) % np,
+                                                 lz + o / (np * np));
     }
   }
   if (lcols) {
@@ -717,7 +739,8 @@ __global__ void k_export_lrows(int n_lrows, int nf, const int* lrow_id, const in
 namespace {
 
 Blocks view(const cpm_band* b) {
-  return Blocks{b->blk_coord, b->blk_mask, b->blk_off, b->blk_nbr, b->hkeys, b->hvals, b->hcap};
+  return Blocks{b->blk_coord, b->blk_mask, b->blk_off, b->blk_nbr, b->hkeys, b->hvals, b->hcap,
+                b->p};
 }
 
 // A temporary device buffer freed at scope exit.
@@ -888,7 +911,7 @@ void build(cpm_band* b, hipStream_t st) {
     CPM_HIP(hipStreamSynchronize(st));
     if (hc[3])
       CPM_FAIL(CPM_E_STENCIL_HOLE, "%llu interpolation-stencil members are not band nodes "
-               "(band radius %.6g = %.4g h too small for cubic stencils)",
+               "(band radius %.6g = %.4g h too small for the interpolation stencils)",
                hc[3], r, r * N);
     b->no_bc_dof_swaps = (int64_t)hc[1];
   }
@@ -1046,7 +1069,8 @@ extern "C" cpm_status cpm_build_band(const cpm_surface* surface, const cpm_ibc* 
     if (!surface || !grid || !out) CPM_FAIL(CPM_E_INVALID, "null argument");
     *out = nullptr;
     if (grid->N <= 0) CPM_FAIL(CPM_E_INVALID, "N must be positive (got %d)", grid->N);
-    if (grid->p != 3) CPM_FAIL(CPM_E_INVALID, "only p = 3 (cubic) is supported (got %d)", grid->p);
+    if (grid->p != 3 && grid->p != 2)
+      CPM_FAIL(CPM_E_INVALID, "interpolation degree p must be 2 or 3 (got %d)", grid->p);
     if (grid->order != 1 && grid->order != 2)
       CPM_FAIL(CPM_E_INVALID, "order must be 1 or 2 (got %d)", grid->order);
     if (n_ibc < 0 || n_ibc > kMaxIBC || (n_ibc && !ibcs))
@@ -1083,12 +1107,16 @@ extern "C" cpm_status cpm_build_band(const cpm_surface* surface, const cpm_ibc* 
     b->dim = kind == CPM_SURF_CIRCLE ? 2 : 3;
     b->N = grid->N;
     b->order = grid->order;
+    b->p = grid->p;
     b->surf = *surface;
     if (b->dim == 2) b->surf.center[2] = 0.0;
     b->n_ibc = n_ibc;
     b->ibcs.assign(ibcs, ibcs + n_ibc);
     b->h = 1.0 / grid->N;
-    const double K = b->dim == 3 ? 17.0 : 13.0;   // eq. (bandwidth), p = 3, q = 1
+    // eq. (bandwidth), q = 1: (d - 1) ((p + 1) / 2)^2 + (1 + (p + 1) / 2)^2, i.e.
+    // 17 / 13 (cubic, R^3 / R^2) and 10.75 / 8.5 (quadratic)
+    const double hp = 0.5 * (double)(grid->p + 1);
+    const double K = (double)(b->dim - 1) * (hp * hp) + (1.0 + hp) * (1.0 + hp);
     b->r = grid->r_band > 0 ? grid->r_band : std::sqrt(K) / (double)grid->N;
     b->tau = (grid->tau_factor > 0 ? grid->tau_factor : 0.1) / (double)((int64_t)grid->N * grid->N);
     b->check_factor = grid->check_factor > 0 ? grid->check_factor : 2.0;

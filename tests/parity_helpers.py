@@ -8,8 +8,9 @@ from oracle import geometry as G
 from oracle import operator as O
 
 
-def oracle_and_gpu(cfg, N, order=2):
-    """Build the oracle system and the GPU band for a named configuration."""
+def oracle_and_gpu(cfg, N, order=2, degree=3):
+    """Build the oracle system and the GPU band for a named configuration
+    (interpolation degree: 3 cubic, 2 quadratic)."""
     from paper_2305_04711_amd import cpm
     if cfg == "circle_point":
         S = G.Circle()
@@ -68,8 +69,8 @@ def oracle_and_gpu(cfg, N, order=2):
     else:
         raise KeyError(cfg)
     bc_types = bct if cfg in NEUMANN_CASES or cfg == "sphere_arc" else None
-    sysm = O.CPMSystem(S, N, Cs, order=order, bc_types=bc_types)
-    band = cpm.Band(gs, gi, N, order=order)
+    sysm = O.CPMSystem(S, N, Cs, order=order, bc_types=bc_types, p=degree)
+    band = cpm.Band(gs, gi, N, order=order, p=degree)
     return sysm, band
 
 
