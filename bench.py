@@ -40,8 +40,8 @@ BYTES_PER_ROW_F32 = 24.0   # tile gather: fraction 12 + base 4 + u 4 + a 4 (FP32
 # profiles/gather_torus512_pmc.md), each scaled by the same counter's reading
 # for a plain device copy of known size.  They hold only for the kernel
 # source they were taken on: `traffic` is null when its hash differs.
-GATHER_PMC = {"sources_sha1": "bf12c7b47de1a89afc33d0c11f79d912b5970fa1",
-              "fetch_bytes": 1.72562e+09, "write_bytes": 3.40212e+08}
+GATHER_PMC = {"sources_sha1": "61d9cc0e0fe7085a0e578b96b7c239df56ac46b0",
+              "fetch_bytes": 1.73132e+09, "write_bytes": 3.40667e+08}
 def gather_sources_sha1():
     """Hash of the FP64 tile gather's own source: the k_gather template, the
     row and cube helpers it calls, and the Lagrange weights."""
@@ -148,6 +148,50 @@ def run_batch(dev, args):
     return out
 
 
+def run_quadratic(dev, args, N, m, n, dt64_cubic, solves_cubic):
+    """The same torus and interior boundaries with quadratic interpolation
+    (p = 2, Sec. 7): band size, FP64 apply time and the FP64 solve to 1e-8,
+    beside the cubic figures."""
+    import torch
+    from paper_2305_04711_amd import cpm, inputs
+    t0 = time.perf_counter()
+    band = cpm.Band(cpm.torus(1.0, 0.4), [cpm.meridian_ibc(1.0, 0.0),
+                                          cpm.meridian_ibc(-1.0, 0.0)], N, order=2, p=2)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    cpm.autotune(band, torch.float64, 1, reps=10)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    u = torch.randn(band.n, device=dev, dtype=torch.float64, generator=gen)
+    for _ in range(args.warmup):
+        v = cpm.apply(band, u, m, n)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        v = cpm.apply(band, u, m, n)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / args.steps
+    del v
+    out = {"dofs": band.n, "n_s": band.n_s, "n_c": band.n_c, "build_s": build_s,
+           "apply_f64_ms": dt * 1e3, "gnodes_per_s": band.n / dt / 1e9,
+           "apply_speedup_vs_cubic": dt64_cubic / dt}
+    if solves_cubic is not None:
+        cp = band.cp()
+        f = torch.tensor(inputs.torus_field(inputs.torus_coeffs(100), cp), device=dev)
+        g = torch.tensor(inputs.meridian_dirichlet(band.bc_cpc(), seed=2), device=dev)
+        b = cpm.rhs(band, f, g, n)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x, st = cpm.solve(band, b, m, n, tol=1e-8, mode="f64", raise_noconv=False)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t
+        out["solve_f64"] = {"seconds": sec, "converged": bool(st["converged"]),
+                            "relres": st["relres"], "krylov_iters": st["krylov_iters"],
+                            "speedup_vs_cubic": solves_cubic["f64"]["seconds"] / sec}
+    log("quadratic p=2: %s" % out)
+    return out
+
+
 def run_heat(dev, N=256):
     """The heat test of Sec. 6.2 at h = 1/N: unit sphere, exact solution
     exp(-2t) z, second-order Dirichlet IBC on the circle z = 0.3 with the exact
@@ -194,6 +238,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
+    ap.add_argument("--no-quadratic", action="store_true",
+                    help="skip the quadratic-interpolation (p = 2) band")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (a kernel of known "
                          "traffic for scaling the HBM byte counters)")
@@ -333,6 +379,10 @@ def main():
                    "grad_g_norm": gr.grad.norm().item()}
         log("adjoint: %s" % adjoint)
 
+    quad = None
+    if not args.no_quadratic:
+        quad = run_quadratic(dev, args, N, m, n, dt64, solves)
+
     batch_out = None
     if not args.no_batch:
         batch_out = run_batch(dev, args)
@@ -384,6 +434,7 @@ def main():
         "adjoint": adjoint,
         "batched": batch_out,
         "heat_cn": heat_out,
+        "quadratic_p2": quad,
     }
     print(json.dumps(out))
 

@@ -5,8 +5,10 @@
 // Storage is a sparse two-level grid (Sec. 5.1): occupied blocks of 64 nodes
 // (4x4x4, or 8x8 in 2-D) found by scanning the bounding box one row of blocks
 // per workgroup, a hash table from block coordinates to block ids, and a
-// neighbour table per block.  PDE DOFs are numbered block by block
-// (lexicographic in block coordinates), slots in order inside a block.
+// neighbour table per block.  Blocks are numbered in Morton (Z) order of
+// their coordinates, so that blocks adjacent in any direction are close in
+// the numbering (and in the order the apply kernels visit them); PDE DOFs are
+// numbered block by block, slots in order inside a block.
 //
 // Compiled with -ffp-contract=off: every FP64 decision here must agree bit
 // for bit with a plain IEEE evaluation of the same formulas.
@@ -14,6 +16,8 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+
+#include <hipcub/hipcub.hpp>
 
 #include "cpm_internal.hpp"
 #include "geom.hpp"
@@ -33,6 +37,23 @@ __host__ __device__ __forceinline__ unsigned long long block_key(int bx, int by,
   return (unsigned long long)(unsigned)(bx + (1 << 20)) |
          ((unsigned long long)(unsigned)(by + (1 << 20)) << 21) |
          ((unsigned long long)(unsigned)(bz + (1 << 20)) << 42);
+}
+
+// Bits 0..20 of v moved to bits 0, 3, 6, ..., 60.
+__host__ __device__ __forceinline__ unsigned long long spread3(unsigned v) {
+  unsigned long long x = v & 0x1fffffu;
+  x = (x | (x << 32)) & 0x001f00000000ffffULL;
+  x = (x | (x << 16)) & 0x001f0000ff0000ffULL;
+  x = (x | (x << 8)) & 0x100f00f00f00f00fULL;
+  x = (x | (x << 4)) & 0x10c30c30c30c30c3ULL;
+  x = (x | (x << 2)) & 0x1249249249249249ULL;
+  return x;
+}
+
+// Morton key of a block: the offset coordinates' bits interleaved (x lowest).
+__host__ __device__ __forceinline__ unsigned long long morton_key(int bx, int by, int bz) {
+  return spread3((unsigned)(bx + (1 << 20))) | (spread3((unsigned)(by + (1 << 20))) << 1) |
+         (spread3((unsigned)(bz + (1 << 20))) << 2);
 }
 
 __device__ __forceinline__ unsigned hash_key(unsigned long long k) {
@@ -172,6 +193,24 @@ __global__ __launch_bounds__(256) void k_classify(cpm_surface S, int N, double r
     __syncthreads();
   }
   if (!WRITE && threadIdx.x == 0) row_count[row] = s_count;
+}
+
+__global__ void k_morton(const int4* coord, int nb, unsigned long long* key, int* idx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const int4 c = coord[i];
+  key[i] = morton_key(c.x, c.y, c.z);
+  idx[i] = i;
+}
+
+__global__ void k_permute_blocks(const int* idx, int nb, const int4* coord_in,
+                                 const unsigned long long* mask_in, int4* coord,
+                                 unsigned long long* mask) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const int j = idx[i];
+  coord[i] = coord_in[j];
+  mask[i] = mask_in[j];
 }
 
 __global__ void k_popcounts(const unsigned long long* mask, int nb, int* cnt) {
@@ -319,7 +358,6 @@ __global__ __launch_bounds__(256) void k_stencil_scan(Blocks B, int nb, int N, i
                                                       int* tile_cnt,
                                                       unsigned long long* counters) {
   NODE_PROLOGUE(DIM);
-  constexpr int NM = DIM == 3 ? 64 : 16;
   const V3 y = load_v(cp, n_s, dof, DIM);
   int base[3];
   double t[3];
@@ -796,7 +834,7 @@ void build(cpm_band* b, hipStream_t st) {
   const double half_diag = 0.5 * (G::BX - 1) * std::sqrt((double)DIM);
   const double thr = r + (half_diag + 0.01) / N;
 
-  // ---- pass 1: occupied blocks, in lexicographic block order
+  // ---- pass 1: occupied blocks (row by row), then sorted into Morton order
   Tmp<int> row_count(nrows), row_off(nrows);
   hipLaunchKernelGGL((k_classify<DIM, false>), dim3(nrows), dim3(256), 0, st, S, N, r, thr, box,
                      row_count.p, nullptr, nullptr, nullptr);
@@ -809,9 +847,27 @@ void build(cpm_band* b, hipStream_t st) {
   b->blk_coord = b->alloc<int4>(nb);
   b->blk_mask = b->alloc<unsigned long long>(nb);
   b->blk_off = b->alloc<int>(nb + 1);
-  hipLaunchKernelGGL((k_classify<DIM, true>), dim3(nrows), dim3(256), 0, st, S, N, r, thr, box,
-                     nullptr, row_off.p, b->blk_coord, b->blk_mask);
-  CPM_LAUNCH_CHECK();
+  {
+    Tmp<int4> coord0(nb);
+    Tmp<unsigned long long> mask0(nb), key0(nb), key1(nb);
+    Tmp<int> idx0(nb), idx1(nb);
+    hipLaunchKernelGGL((k_classify<DIM, true>), dim3(nrows), dim3(256), 0, st, S, N, r, thr, box,
+                       nullptr, row_off.p, coord0.p, mask0.p);
+    CPM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_morton, dim3(grid_for(nb, 256)), dim3(256), 0, st, coord0.p, nb, key0.p,
+                       idx0.p);
+    CPM_LAUNCH_CHECK();
+    size_t tb = 0;
+    CPM_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, key0.p, key1.p, idx0.p, idx1.p, nb, 0,
+                                               63, st));
+    Tmp<unsigned char> tmp(tb);
+    CPM_HIP(hipcub::DeviceRadixSort::SortPairs(tmp.p, tb, key0.p, key1.p, idx0.p, idx1.p, nb, 0,
+                                               63, st));
+    hipLaunchKernelGGL(k_permute_blocks, dim3(grid_for(nb, 256)), dim3(256), 0, st, idx1.p, nb,
+                       coord0.p, mask0.p, b->blk_coord, b->blk_mask);
+    CPM_LAUNCH_CHECK();
+    CPM_HIP(hipStreamSynchronize(st));
+  }
   {
     Tmp<int> cnt(nb);
     hipLaunchKernelGGL(k_popcounts, dim3(grid_for(nb, 256)), dim3(256), 0, st, b->blk_mask, nb, cnt.p);

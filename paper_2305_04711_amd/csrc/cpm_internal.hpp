@@ -103,7 +103,7 @@ struct cpm_band {
   int64_t n_s = 0, n_c = 0, n = 0;
   int device = 0;
 
-  // occupied blocks (block order = lexicographic in (bz, by, bx))
+  // occupied blocks (block order = Morton order of the block coordinates)
   int nb = 0;
   int4* blk_coord = nullptr;          // [nb] block coordinates
   unsigned long long* blk_mask = nullptr;  // [nb] occupied slots
