@@ -218,10 +218,143 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void k_
   }
 }
 
+// Persistent form of k_gather: XCD x (workgroup id mod 8) owns a contiguous
+// eighth of the tiles, and its W waves take every W-th tile of that range.
+// While a tile's blocks are staged, the wave already requests the next
+// tile's metadata and row range, so a tile costs one dependent round trip to
+// memory instead of two.
+template <class T, int DIM, int NR, int PAD>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void k_gather_ps(
+    BlockView B, TileView tv, int N, const T* __restrict__ u, T* __restrict__ a, int64_t ld,
+    int ntiles) {
+  using G = Geo<DIM>;
+  constexpr int E = Cube<DIM>::E, EP = E + PAD, NQ = 1 << DIM;
+  constexpr int CS = DIM == 3 ? E * E * EP : E * EP;
+  __shared__ T s_u[NR][CS];
+  const int lane = threadIdx.x;
+  const int x = blockIdx.x & 7, wk = blockIdx.x >> 3, W = gridDim.x >> 3;
+  const int q8 = ntiles >> 3, r8 = ntiles & 7;
+  const int lo = x * q8 + (x < r8 ? x : r8), hi = lo + q8 + (x < r8 ? 1 : 0);
+  int t = lo + wk;
+  if (t >= hi) return;
+  unsigned long long qm = 0ull;
+  int qoff = 0;
+  if (lane < NQ) {
+    const QMeta q = tv.meta[(int64_t)t * 8 + lane];
+    qm = q.mask;
+    qoff = q.off;
+  }
+  int beg = tv.tile_start[t], end = tv.tile_start[t + 1];
+  const int cx0 = G::lx(lane), cy0 = G::ly(lane), cz0 = G::lz(lane);
+  while (true) {
+    const int tn = t + W;
+    const bool more = tn < hi;
+    int lb[3] = {0, 0, 0};
+    T tt[3] = {T(0), T(0), T(0)};
+    if (beg + lane < end) row_stencil<T, DIM>(tv, beg + lane, N, lb, tt);
+    T sv[NQ][NR];
+    int sci[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const unsigned long long m = lane_u64(qm, q);
+      const int off = lane_i32(qoff, q);
+      const int qx = q & 1, qy = (q >> 1) & 1, qz = DIM == 3 ? (q >> 2) : 0;
+      const int cx = qx * G::BX + cx0, cy = qy * G::BX + cy0, cz = qz * G::BX + cz0;
+      sci[q] = DIM == 3 ? (cz * E + cy) * EP + cx : cy * EP + cx;
+      const bool on = (m >> lane) & 1ull;
+      const int dof = off + __popcll(m & ((1ull << lane) - 1ull));
+#pragma unroll
+      for (int r = 0; r < NR; ++r) sv[q][r] = on ? u[r * ld + dof] : T(0);
+    }
+    unsigned long long qm_n = 0ull;
+    int qoff_n = 0, beg_n = 0, end_n = 0;
+    if (more) {
+      if (lane < NQ) {
+        const QMeta q = tv.meta[(int64_t)tn * 8 + lane];
+        qm_n = q.mask;
+        qoff_n = q.off;
+      }
+      beg_n = tv.tile_start[tn];
+      end_n = tv.tile_start[tn + 1];
+    }
+    __syncthreads();   // the previous tile's rows are done with the cube
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) s_u[r][sci[q]] = sv[q][r];
+    __syncthreads();
+    for (int pos = beg + lane; pos < end; pos += 64) {
+      T wx[4], wy[4], wz[4];
+      lagrange_p<T>(tv.p, tt[0], wx);
+      lagrange_p<T>(tv.p, tt[1], wy);
+      if (DIM == 3) lagrange_p<T>(tv.p, tt[2], wz);
+      const int lx = lb[0], ly = lb[1], lz = lb[2];
+      const int dof = tv.perm[pos];
+      if (pos + 64 < end) row_stencil<T, DIM>(tv, pos + 64, N, lb, tt);
+      T acc[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[r] = T(0);
+      if (DIM == 3) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          T accz[NR];
+#pragma unroll
+          for (int r = 0; r < NR; ++r) accz[r] = T(0);
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int base = ((lz + c) * E + (ly + b)) * EP + lx;
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+              const T* row = &s_u[r][base];
+              const T xv = wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2] + wx[3] * row[3];
+              accz[r] += wy[b] * xv;
+            }
+          }
+#pragma unroll
+          for (int r = 0; r < NR; ++r) acc[r] += wz[c] * accz[r];
+        }
+      } else {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int base = (ly + b) * EP + lx;
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            const T* row = &s_u[r][base];
+            const T xv = wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2] + wx[3] * row[3];
+            acc[r] += wy[b] * xv;
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < NR; ++r) a[r * ld + dof] = acc[r];
+    }
+    if (!more) break;
+    t = tn;
+    qm = qm_n;
+    qoff = qoff_n;
+    beg = beg_n;
+    end = end_n;
+  }
+}
+
 template <class T>
 __device__ __forceinline__ T wave_sum(T v, int width) {
   for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, width);
   return v;
+}
+
+// Wavefront sums of d0 and d1 (every lane of the wave must call it), written
+// by lane 0 to part[idx] and part[np + idx] with idx = first + the wave's
+// index in its workgroup: the partials of a fused dot product, one per
+// wavefront, finished in a fixed order by the solver.
+__device__ __forceinline__ void wave_dot2(double d0, double d1, double* part, int np, int first) {
+  d0 = wave_sum(d0, 64);
+  d1 = wave_sum(d1, 64);
+  if ((threadIdx.x & 63) == 0) {
+    const int idx = first + (threadIdx.x >> 6);
+    part[idx] = d0;
+    part[np + idx] = d1;
+  }
 }
 
 // Explicit interpolation rows: a[id] = sum_o w_o u[col_o]; nm lanes per row
@@ -255,19 +388,22 @@ __global__ __launch_bounds__(256) void k_gather_rows(int nrows, int nm, const in
 // explicit FD stencils; ALL = true (transpose) visits every PDE row.
 constexpr int kLapBlocksPerWave = 2;
 
-template <class T, int DIM, bool ALL>
-__global__ __launch_bounds__(256) void k_lap(BlockView B, const T* __restrict__ u,
+template <class T, int DIM, bool ALL, bool DOT = false>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_lap(BlockView B, const T* __restrict__ u,
                                              const T* __restrict__ a, T* __restrict__ v,
                                              int64_t ld, int nrhs, T cd, T co,
                                              const double* __restrict__ gsum, double gscale,
                                              int xcd, const double* __restrict__ coef,
-                                             const int* __restrict__ skip) {
+                                             const int* __restrict__ skip,
+                                             const T* __restrict__ dy = nullptr,
+                                             double* __restrict__ dpart = nullptr, int dnp = 0) {
   using G = Geo<DIM>;
   constexpr int KB = kLapBlocksPerWave;
   const int wg = xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
   const int blk0 = (wg * 4 + (threadIdx.x >> 6)) * KB;
   const int slot = threadIdx.x & 63;
-  if (blk0 >= B.nb) return;
+  // with DOT every wave takes part in the workgroup's reduction
+  if (!DOT && blk0 >= B.nb) return;
   unsigned long long lm = 0ull;
   int loff = 0, lpad = 0;
   {
@@ -320,6 +456,32 @@ __global__ __launch_bounds__(256) void k_lap(BlockView B, const T* __restrict__ 
       nd[j][f] = ((mm >> s2) & 1ull) ? oo + __popcll(mm & ((1ull << s2) - 1ull)) : -1;
     }
   }
+  if constexpr (DOT) {
+    // the solver's fused dot products: one right-hand side; y is requested
+    // together with u so that it adds no round trip to memory
+    T uv[KB], yv[KB], s[KB];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      uv[j] = dof[j] >= 0 ? u[dof[j]] : T(0);
+      yv[j] = dof[j] >= 0 ? dy[dof[j]] : T(0);
+      s[j] = T(0);
+#pragma unroll
+      for (int f = 0; f < 2 * DIM; ++f)
+        if (dof[j] >= 0 && nd[j][f] >= 0) s[j] += a[nd[j][f]];
+    }
+    double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      if (dof[j] < 0) continue;
+      T o = cdj[j] * uv[j] + coj[j] * s[j];
+      if (gsum) o += (T)(gscale * gsum[0]);
+      v[dof[j]] = o;
+      d0 += (double)yv[j] * (double)o;
+      d1 += (double)o * (double)o;
+    }
+    wave_dot2(d0, d1, dpart, dnp, blockIdx.x * 4);
+    return;
+  }
   for (int r = 0; r < nrhs; ++r) {
     T out[KB];
 #pragma unroll
@@ -340,31 +502,38 @@ __global__ __launch_bounds__(256) void k_lap(BlockView B, const T* __restrict__ 
   }
 }
 
-template <class T>
+template <class T, bool DOT = false>
 __global__ void k_lap_rows(int nrows, int nf, const int* __restrict__ row_id,
                            const int* __restrict__ col, const T* __restrict__ u,
                            const T* __restrict__ a, T* __restrict__ v, int64_t ld, int nrhs,
                            T cd, T co, const double* __restrict__ gsum, double gscale,
                            const double* __restrict__ coef, const int* __restrict__ row_inst,
-                           const int* __restrict__ skip) {
+                           const int* __restrict__ skip, const T* __restrict__ dy = nullptr,
+                           double* __restrict__ dpart = nullptr, int dnp = 0, int doff = 0) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nrows) return;
-  const int id = row_id[i];
-  if (coef) {
-    if (skip && skip[row_inst[i]]) return;
-    cd = (T)coef[2 * row_inst[i]];
-    co = (T)coef[2 * row_inst[i] + 1];
-  }
-  for (int r = 0; r < nrhs; ++r) {
-    T s = T(0);
-    for (int f = 0; f < nf; ++f) {
-      const int c = col[i * nf + f];
-      if (c >= 0) s += a[r * ld + c];
+  double d0 = 0.0, d1 = 0.0;
+  if (i < nrows && !(coef && skip && skip[row_inst[i]])) {
+    const int id = row_id[i];
+    if (coef) {
+      cd = (T)coef[2 * row_inst[i]];
+      co = (T)coef[2 * row_inst[i] + 1];
     }
-    T out = cd * u[r * ld + id] + co * s;
-    if (gsum) out += (T)(gscale * gsum[r]);
-    v[r * ld + id] = out;
+    for (int r = 0; r < nrhs; ++r) {
+      T s = T(0);
+      for (int f = 0; f < nf; ++f) {
+        const int c = col[i * nf + f];
+        if (c >= 0) s += a[r * ld + c];
+      }
+      T out = cd * u[r * ld + id] + co * s;
+      if (gsum) out += (T)(gscale * gsum[r]);
+      v[r * ld + id] = out;
+      if (DOT && r == 0) {
+        d0 = (double)dy[id] * (double)out;
+        d1 = (double)out * (double)out;
+      }
+    }
   }
+  if (DOT) wave_dot2(d0, d1, dpart, dnp, doff + blockIdx.x * 2);
 }
 
 // ---------------------------------------------------------------- gauge
@@ -571,12 +740,22 @@ __global__ void k_fill(T* __restrict__ p, int64_t n, T val) {
     p[i] = val;
 }
 
-template <class T>
+template <class T, bool DOT = false>
 __global__ void k_combine(int64_t n, const T* __restrict__ w, const T* __restrict__ z,
-                          T* __restrict__ out, T cd, T nn, int64_t total) {
+                          T* __restrict__ out, T cd, T nn, int64_t total,
+                          const T* __restrict__ dy = nullptr, double* __restrict__ dpart = nullptr,
+                          int dnp = 0) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  out[i] = cd * w[i] + nn * z[i];
+  double d0 = 0.0, d1 = 0.0;
+  if (i < total) {
+    const T o = cd * w[i] + nn * z[i];
+    out[i] = o;
+    if (DOT) {
+      d0 = (double)dy[i] * (double)o;
+      d1 = (double)o * (double)o;
+    }
+  }
+  if (DOT) wave_dot2(d0, d1, dpart, dnp, blockIdx.x * 4);
   (void)n;
 }
 
@@ -696,9 +875,24 @@ static void launch_gather(const cpm_band* b, int nrhs, const T* u, T* a, hipStre
 }
 
 // ev (optional): five events recorded between the four phases.
+static int lap_groups(const cpm_band* b) {
+  return (b->nb + 4 * kLapBlocksPerWave - 1) / (4 * kLapBlocksPerWave);
+}
+static int lap_row_groups(const cpm_band* b) {
+  return b->n_lrows ? grid_for(b->n_lrows, 128) : 0;
+}
+
+// Number of partials a fused dot product of an apply writes (per value): one
+// per wavefront of the kernel that writes the output.
+int apply_dot_parts(const cpm_band* b, bool transpose) {
+  if (transpose) return 4 * grid_for(b->n, 256);
+  return 4 * lap_groups(b) + 2 * lap_row_groups(b);
+}
+
 template <class T, int DIM>
 static void apply_dim(const cpm_band* b, double m, double n, int nrhs, const T* u, T* v,
-                      hipStream_t st, const double* gsum, double gamma, hipEvent_t* ev = nullptr) {
+                      hipStream_t st, const double* gsum, double gamma, hipEvent_t* ev = nullptr,
+                      const T* dy = nullptr, double* dpart = nullptr) {
   const int64_t ld = b->n;
   T* a = static_cast<T*>(band_scratch(b, 0, sizeof(T) * (size_t)ld * nrhs));
   if (ev) CPM_HIP(hipEventRecord(ev[0], st));
@@ -707,15 +901,26 @@ static void apply_dim(const cpm_band* b, double m, double n, int nrhs, const T* 
   const T cd = (T)(m + n * (-2.0 * DIM * N2));
   const T co = (T)(n * N2);
   const double gscale = gsum ? gamma / (double)b->n_s : 0.0;
-  hipLaunchKernelGGL((k_lap<T, DIM, false>), dim3((b->nb + 4 * kLapBlocksPerWave - 1) / (4 * kLapBlocksPerWave)), dim3(256), 0, st, bview(b), u,
-                     a, v, ld, nrhs, cd, co, gsum, gscale, tune_of<T>(b).xcd, b->inst_coef,
-                     b->inst_skip);
+  const int g1 = lap_groups(b), g2 = lap_row_groups(b), np = 4 * g1 + 2 * g2;
+  if (dy)
+    hipLaunchKernelGGL((k_lap<T, DIM, false, true>), dim3(g1), dim3(256), 0, st, bview(b), u, a, v,
+                       ld, nrhs, cd, co, gsum, gscale, tune_of<T>(b).xcd, b->inst_coef,
+                       b->inst_skip, dy, dpart, np);
+  else
+    hipLaunchKernelGGL((k_lap<T, DIM, false>), dim3(g1), dim3(256), 0, st, bview(b), u, a, v, ld,
+                       nrhs, cd, co, gsum, gscale, tune_of<T>(b).xcd, b->inst_coef, b->inst_skip,
+                       nullptr, nullptr, 0);
   CPM_LAUNCH_CHECK();
   if (ev) CPM_HIP(hipEventRecord(ev[3], st));
   if (b->n_lrows) {
-    hipLaunchKernelGGL(k_lap_rows<T>, dim3(grid_for(b->n_lrows, 128)), dim3(128), 0, st,
-                       b->n_lrows, 2 * DIM, b->lrow_id, b->lcol, u, a, v, ld, nrhs, cd, co, gsum,
-                       gscale, b->inst_coef, b->lrow_inst, b->inst_skip);
+    if (dy)
+      hipLaunchKernelGGL((k_lap_rows<T, true>), dim3(g2), dim3(128), 0, st, b->n_lrows, 2 * DIM,
+                         b->lrow_id, b->lcol, u, a, v, ld, nrhs, cd, co, gsum, gscale,
+                         b->inst_coef, b->lrow_inst, b->inst_skip, dy, dpart, np, 4 * g1);
+    else
+      hipLaunchKernelGGL((k_lap_rows<T>), dim3(g2), dim3(128), 0, st, b->n_lrows, 2 * DIM,
+                         b->lrow_id, b->lcol, u, a, v, ld, nrhs, cd, co, gsum, gscale,
+                         b->inst_coef, b->lrow_inst, b->inst_skip, nullptr, nullptr, 0, 0);
     CPM_LAUNCH_CHECK();
   }
   if (ev) CPM_HIP(hipEventRecord(ev[4], st));
@@ -723,7 +928,7 @@ static void apply_dim(const cpm_band* b, double m, double n, int nrhs, const T* 
 
 template <class T>
 void apply_impl(const cpm_band* b, double m, double n, int nrhs, const T* u, T* v, hipStream_t st,
-                const double* gauge_sum, double gamma) {
+                const double* gauge_sum, double gamma, const T* dy, double* dpart) {
   double* gs = nullptr;
   if (gamma != 0.0) {
     // gauge: gamma * (sum of the PDE entries of u) / n_s on every row
@@ -736,13 +941,13 @@ void apply_impl(const cpm_band* b, double m, double n, int nrhs, const T* u, T* 
     hipLaunchKernelGGL(k_sum_final, dim3(nrhs), dim3(256), 0, st, part, np, gs);
     CPM_LAUNCH_CHECK();
   }
-  if (b->dim == 3) apply_dim<T, 3>(b, m, n, nrhs, u, v, st, gs, gamma);
-  else apply_dim<T, 2>(b, m, n, nrhs, u, v, st, gs, gamma);
+  if (b->dim == 3) apply_dim<T, 3>(b, m, n, nrhs, u, v, st, gs, gamma, nullptr, dy, dpart);
+  else apply_dim<T, 2>(b, m, n, nrhs, u, v, st, gs, gamma, nullptr, dy, dpart);
 }
 
 template <class T, int DIM>
 static void apply_T_dim(const cpm_band* b, double m, double n, int nrhs, const T* w, T* z,
-                        hipStream_t st) {
+                        hipStream_t st, const T* dy = nullptr, double* dpart = nullptr) {
   const int64_t ld = b->n;
   T* c = static_cast<T*>(band_scratch(b, 1, sizeof(T) * (size_t)ld * nrhs));
   T* e = static_cast<T*>(band_scratch(b, 2, sizeof(T) * (size_t)ld * nrhs));
@@ -786,27 +991,37 @@ static void apply_T_dim(const cpm_band* b, double m, double n, int nrhs, const T
   }
   const T cd = (T)(m + n * (-2.0 * DIM * N2));
   const int64_t total = ld * nrhs;
-  hipLaunchKernelGGL(k_combine<T>, dim3(grid_for(total, 256)), dim3(256), 0, st, ld, w, e, z, cd,
-                     (T)n, total);
+  const int gc = grid_for(total, 256);
+  if (dy) {
+    if ((int64_t)gc * 256 < total) CPM_FAIL(CPM_E_INVALID, "internal: fused dot grid too small");
+    hipLaunchKernelGGL((k_combine<T, true>), dim3(gc), dim3(256), 0, st, ld, w, e, z, cd, (T)n,
+                       total, dy, dpart, 4 * gc);
+  } else {
+    hipLaunchKernelGGL((k_combine<T>), dim3(gc), dim3(256), 0, st, ld, w, e, z, cd, (T)n, total,
+                       nullptr, nullptr, 0);
+  }
   CPM_LAUNCH_CHECK();
 }
 
 template <class T>
 void apply_transpose_impl(const cpm_band* b, double m, double n, int nrhs, const T* w, T* z,
-                          hipStream_t st, const double*, double gamma) {
+                          hipStream_t st, const double*, double gamma, const T* dy,
+                          double* dpart) {
   if (gamma != 0.0) CPM_FAIL(CPM_E_INVALID, "the gauge is not supported for the transpose");
-  if (b->dim == 3) apply_T_dim<T, 3>(b, m, n, nrhs, w, z, st);
-  else apply_T_dim<T, 2>(b, m, n, nrhs, w, z, st);
+  if (b->dim == 3) apply_T_dim<T, 3>(b, m, n, nrhs, w, z, st, dy, dpart);
+  else apply_T_dim<T, 2>(b, m, n, nrhs, w, z, st, dy, dpart);
 }
 
 template void apply_impl<double>(const cpm_band*, double, double, int, const double*, double*,
-                                 hipStream_t, const double*, double);
+                                 hipStream_t, const double*, double, const double*, double*);
 template void apply_impl<float>(const cpm_band*, double, double, int, const float*, float*,
-                                hipStream_t, const double*, double);
+                                hipStream_t, const double*, double, const float*, double*);
 template void apply_transpose_impl<double>(const cpm_band*, double, double, int, const double*,
-                                           double*, hipStream_t, const double*, double);
+                                           double*, hipStream_t, const double*, double,
+                                           const double*, double*);
 template void apply_transpose_impl<float>(const cpm_band*, double, double, int, const float*,
-                                          float*, hipStream_t, const double*, double);
+                                          float*, hipStream_t, const double*, double,
+                                          const float*, double*);
 
 }  // namespace cpm
 

@@ -200,15 +200,19 @@ void* band_scratch(const cpm_band* b, int slot, size_t bytes);
 // Device-wide exclusive scan; returns the total (synchronises the stream).
 int64_t scan_exclusive_i32(const int* in, int* out, int64_t n, hipStream_t s);
 
-// apply entry points used by the solvers (nrhs = 1, optional gauge)
+// apply entry points used by the solvers (nrhs = 1, optional gauge).  With
+// dy set, the kernel that writes v also writes the partials of (dy, v) and
+// (v, v) to dpart[0 .. np) and dpart[np .. 2 np), np = apply_dot_parts.
 template <class T>
 void apply_impl(const cpm_band* b, double m, double n, int nrhs, const T* u,
                 T* v, hipStream_t s, const double* gauge_sum = nullptr,
-                double gamma = 0.0);
+                double gamma = 0.0, const T* dy = nullptr, double* dpart = nullptr);
 template <class T>
 void apply_transpose_impl(const cpm_band* b, double m, double n, int nrhs,
                           const T* w, T* z, hipStream_t s,
-                          const double* gauge_sum = nullptr, double gamma = 0.0);
+                          const double* gauge_sum = nullptr, double gamma = 0.0,
+                          const T* dy = nullptr, double* dpart = nullptr);
+int apply_dot_parts(const cpm_band* b, bool transpose);
 // out -= n (L - diag L) e(g): the Dirichlet part of a right-hand side
 void add_dirichlet_term(const cpm_band* b, double n, const double* g, int nrhs, double* out,
                         hipStream_t st);

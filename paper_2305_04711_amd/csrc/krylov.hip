@@ -108,22 +108,33 @@ __global__ __launch_bounds__(256) void k_init(int64_t n, const T* __restrict__ b
   }
 }
 
-// alpha = rho / (rh, v)
-template <class T>
-__global__ __launch_bounds__(256) void k_dot_rv(int64_t n, const T* __restrict__ rh,
-                                                const T* __restrict__ v, double* part, Scal* S) {
+// Finishes a dot product fused into the apply that produced v (partials of
+// (y, v) in dp[0 .. np) and of (v, v) in dp[np .. 2 np)).  MODE 0: y = rh,
+// alpha = rho / (rh, v).  MODE 1: y = s, v = t, omega = (t, s) / (t, t).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_dot_fin(const double* __restrict__ dp, int np,
+                                                 double* part, Scal* S) {
   if (S->done) return;
-  double acc[1] = {0.0};
-  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kRedThreads)
-    acc[0] += (double)rh[i] * (double)v[i];
-  double tot[1];
-  if (finish_reduction<1>(acc, part, S, tot) && threadIdx.x == 0) {
-    if (tot[0] == 0.0 || !__builtin_isfinite(tot[0])) {
-      S->breakdown = 1;
-      S->done = 1;
+  double acc[2] = {0.0, 0.0};
+  for (int i = blockIdx.x * kRedThreads + threadIdx.x; i < np; i += gridDim.x * kRedThreads) {
+    acc[0] += dp[i];
+    acc[1] += dp[np + i];
+  }
+  double tot[2];
+  if (finish_reduction<2>(acc, part, S, tot) && threadIdx.x == 0) {
+    if (MODE == 0) {
+      if (tot[0] == 0.0 || !__builtin_isfinite(tot[0])) {
+        S->breakdown = 1;
+        S->done = 1;
+      } else {
+        S->alpha = S->rho / tot[0];
+      }
     } else {
-      S->alpha = S->rho / tot[0];
+      if (tot[1] == 0.0 || !__builtin_isfinite(tot[1])) {
+        S->omega = 0.0;
+      } else {
+        S->omega = tot[0] / tot[1];
+      }
     }
   }
 }
@@ -137,28 +148,6 @@ __global__ __launch_bounds__(256) void k_s(int64_t n, const T* __restrict__ r, c
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     s[i] = r[i] - al * v[i];
-}
-
-// omega = (t, s) / (t, t)
-template <class T>
-__global__ __launch_bounds__(256) void k_dot_ts(int64_t n, const T* __restrict__ t,
-                                                const T* __restrict__ s, double* part, Scal* S) {
-  if (S->done) return;
-  double acc[2] = {0.0, 0.0};
-  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kRedThreads) {
-    const double ti = (double)t[i];
-    acc[0] += ti * (double)s[i];
-    acc[1] += ti * ti;
-  }
-  double tot[2];
-  if (finish_reduction<2>(acc, part, S, tot) && threadIdx.x == 0) {
-    if (tot[1] == 0.0 || !__builtin_isfinite(tot[1])) {
-      S->omega = 0.0;
-    } else {
-      S->omega = tot[0] / tot[1];
-    }
-  }
 }
 
 // x += alpha p + omega s;  r = s - omega t;  rho = (rh, r);  rr = (r, r)
@@ -393,6 +382,8 @@ struct Bicg {
   bool transpose;
   T *r, *rh, *p, *v, *s, *t;
   double* part;
+  double* dpart;   // partials of the dot products fused into the applies
+  int dnp, fin_g;
   Scal* S;
   Pinned pin;
   int ew_grid, red_g;
@@ -412,6 +403,9 @@ struct Bicg {
     t = (T*)band_scratch(b, slot0 + 5, vb);
     part = (double*)band_scratch(b, slot0 + 6, sizeof(double) * 2 * kMaxParts);
     S = (Scal*)band_scratch(b, slot0 + 7, sizeof(Scal));
+    dnp = apply_dot_parts(b, tr);
+    dpart = (double*)band_scratch(b, slot0 + 8, sizeof(double) * 2 * (size_t)dnp);
+    fin_g = (int)std::max<int64_t>(1, std::min<int64_t>(256, (dnp + 1023) / 1024));
     CPM_HIP(hipMemsetAsync(S, 0, sizeof(Scal), st));
     ew_grid = grid_for(n, 256, 4096);
     red_g = red_grid(n);
@@ -430,9 +424,11 @@ struct Bicg {
     if (gexec) (void)hipGraphExecDestroy(gexec);
   }
 
-  void apply(const T* in, T* out) {
-    if (transpose) apply_transpose_impl<T>(b, m, nn, 1, in, out, st, nullptr, gamma);
-    else apply_impl<T>(b, m, nn, 1, in, out, st, nullptr, gamma);
+  // out = A in; with dy, also the partials of (dy, out) and (out, out)
+  void apply(const T* in, T* out, const T* dy = nullptr) {
+    double* dp = dy ? dpart : nullptr;
+    if (transpose) apply_transpose_impl<T>(b, m, nn, 1, in, out, st, nullptr, gamma, dy, dp);
+    else apply_impl<T>(b, m, nn, 1, in, out, st, nullptr, gamma, dy, dp);
   }
 
   // r = rhs - A x, rh = p = r, v = 0, beta = 0 (so the first direction
@@ -449,11 +445,11 @@ struct Bicg {
   // ends right after the new residual (where a replacement can take place).
   void iteration(T* x) {
     hipLaunchKernelGGL(k_p<T>, dim3(ew_grid), dim3(256), 0, st, n, r, p, v, S);
-    apply(p, v);
-    hipLaunchKernelGGL(k_dot_rv<T>, dim3(red_g), dim3(kRedThreads), 0, st, n, rh, v, part, S);
+    apply(p, v, rh);
+    hipLaunchKernelGGL(k_dot_fin<0>, dim3(fin_g), dim3(kRedThreads), 0, st, dpart, dnp, part, S);
     hipLaunchKernelGGL(k_s<T>, dim3(ew_grid), dim3(256), 0, st, n, r, v, s, S);
-    apply(s, t);
-    hipLaunchKernelGGL(k_dot_ts<T>, dim3(red_g), dim3(kRedThreads), 0, st, n, t, s, part, S);
+    apply(s, t, s);
+    hipLaunchKernelGGL(k_dot_fin<1>, dim3(fin_g), dim3(kRedThreads), 0, st, dpart, dnp, part, S);
     hipLaunchKernelGGL(k_xr<T>, dim3(red_g), dim3(kRedThreads), 0, st, n, x, p, s, t, r, rh, part, S);
     CPM_LAUNCH_CHECK();
   }
