@@ -428,7 +428,7 @@ def main():
                            "order": ["tile gather", "explicit E rows", "block Laplacian",
                                      "explicit L rows"]},
         "time_to_1e-8": solves,
-        "autotune": {"variants": "k = 2 * xcd + pad", "f64_ms": tune64[0], "f64_best": tune64[1],
+        "autotune": {"variants": "k = 2 * mode + pad (mode 0 block order, 1 XCD-aware, 2 persistent XCD-aware gather)", "f64_ms": tune64[0], "f64_best": tune64[1],
                      "f32_ms": tune32[0], "f32_best": tune32[1]},
         "build_band_s": build_s,
         "adjoint": adjoint,

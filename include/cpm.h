@@ -294,14 +294,24 @@ cpm_status cpm_batch_solve(cpm_batch* batch, const cpm_solve_opts* opts,
                            void* hip_stream);
 
 /* Autotuner: time every launch variant of cpm_apply for this band, dtype and
- * nrhs (LDS line padding of the staged cube x XCD-aware tile order; variant
- * k = 2 * xcd + pad) with HIP events, `reps` calls each, and keep the fastest
- * for later calls with this dtype.  u and v are scratch device arrays
- * [nrhs][n] of that dtype.  ms (may be NULL) receives the 4 mean times per
- * call; *best (may be NULL) the chosen variant.  Synchronises the stream. */
+ * nrhs with HIP events, `reps` calls each, and keep the fastest for later
+ * calls with this dtype.  Variant k = 2 * mode + pad: pad is the LDS line
+ * padding of the staged cube (0: 1 element, 1: 4 elements); mode 0 visits
+ * tiles and blocks in block order, mode 1 gives each XCD a contiguous range
+ * of them, mode 2 runs the tile gather as persistent wavefronts over such
+ * ranges (bands only; a batch's composite skips it and reports HUGE_VAL).
+ * u and v are scratch device arrays [nrhs][n] of that dtype.  ms (may be
+ * NULL) receives the 6 mean times per call; *best (may be NULL) the chosen
+ * variant.  Synchronises the stream. */
 cpm_status cpm_autotune(cpm_band* band, int dtype, int nrhs, const void* u,
                         void* v, int reps, void* hip_stream, double* ms,
                         int* best);
+
+/* Select launch variant k (numbered as by cpm_autotune, 0 <= k < 6) for
+ * later calls on this band with this dtype, without timing anything; every
+ * variant computes each output entry with the same arithmetic.  Returns
+ * CPM_E_INVALID for a k out of range.  Touches no device memory. */
+cpm_status cpm_tune_set(cpm_band* band, int dtype, int variant);
 
 const char* cpm_last_error(void);
 

@@ -68,7 +68,7 @@ EXPORTED = ["cpm_build_band", "cpm_band_free", "cpm_band_query", "cpm_band_expor
             "cpm_apply", "cpm_apply_profile", "cpm_autotune", "cpm_apply_transpose", "cpm_rhs", "cpm_rhs_adjoint", "cpm_solve",
             "cpm_solve_adjoint", "cpm_batch_create", "cpm_batch_free", "cpm_batch_offsets",
             "cpm_batch_apply", "cpm_batch_autotune", "cpm_batch_solve", "cpm_heat_cn",
-            "cpm_last_error"]
+            "cpm_tune_set", "cpm_last_error"]
 
 _lib = None
 
@@ -101,6 +101,7 @@ def load(path=LIB_PATH):
     lib.cpm_apply_profile.argtypes = [vp, d, d, i, i, vp, vp, i, vp, C.POINTER(C.c_double)]
     lib.cpm_autotune.argtypes = [vp, i, i, vp, vp, i, vp, C.POINTER(C.c_double),
                                  C.POINTER(C.c_int)]
+    lib.cpm_tune_set.argtypes = [vp, i, i]
     lib.cpm_rhs.argtypes = [vp, d, i, vp, vp, vp, vp]
     lib.cpm_rhs_adjoint.argtypes = [vp, d, i, vp, vp, vp, vp]
     lib.cpm_solve.argtypes = [vp, C.POINTER(SolveOpts), i, vp, vp, C.POINTER(SolveStats), vp]

@@ -836,8 +836,22 @@ static const Tune& tune_of(const cpm_band* b) {
 
 template <class T, int DIM, int PAD>
 static void launch_gather_k(const cpm_band* b, int k, const T* ur, T* ar, int64_t ld, int xcd,
-                            hipStream_t st) {
+                            bool ps, hipStream_t st) {
   const dim3 g(b->ntiles), t(64);
+  if (ps && !b->tile_inst) {
+    // a multiple of 8 wavefronts: every XCD gets the same number
+    int64_t gp = ((int64_t)b->ntiles + 7) / 8 * 8;
+    if (gp > 8 * (int64_t)kPersistWavesPerXcd) gp = 8 * (int64_t)kPersistWavesPerXcd;
+    const dim3 gq((unsigned)gp);
+    switch (k) {
+      case 1: hipLaunchKernelGGL((k_gather_ps<T, DIM, 1, PAD>), gq, t, 0, st, bview(b), tview(b), b->N, ur, ar, ld, b->ntiles); break;
+      case 2: hipLaunchKernelGGL((k_gather_ps<T, DIM, 2, PAD>), gq, t, 0, st, bview(b), tview(b), b->N, ur, ar, ld, b->ntiles); break;
+      case 3: hipLaunchKernelGGL((k_gather_ps<T, DIM, 3, PAD>), gq, t, 0, st, bview(b), tview(b), b->N, ur, ar, ld, b->ntiles); break;
+      default: hipLaunchKernelGGL((k_gather_ps<T, DIM, 4, PAD>), gq, t, 0, st, bview(b), tview(b), b->N, ur, ar, ld, b->ntiles); break;
+    }
+    CPM_LAUNCH_CHECK();
+    return;
+  }
   switch (k) {
     case 1: hipLaunchKernelGGL((k_gather<T, DIM, 1, PAD>), g, t, 0, st, bview(b), tview(b), b->N, ur, ar, ld, xcd); break;
     case 2: hipLaunchKernelGGL((k_gather<T, DIM, 2, PAD>), g, t, 0, st, bview(b), tview(b), b->N, ur, ar, ld, xcd); break;
@@ -858,8 +872,8 @@ static void launch_gather(const cpm_band* b, int nrhs, const T* u, T* a, hipStre
     T* ar = a + r * ld;
     if (b->ntiles) {
       const Tune& tn = tune_of<T>(b);
-      if (tn.pad) launch_gather_k<T, DIM, 4>(b, k, ur, ar, ld, tn.xcd, st);
-      else launch_gather_k<T, DIM, 1>(b, k, ur, ar, ld, tn.xcd, st);
+      if (tn.pad) launch_gather_k<T, DIM, 4>(b, k, ur, ar, ld, tn.xcd, tn.ps != 0, st);
+      else launch_gather_k<T, DIM, 1>(b, k, ur, ar, ld, tn.xcd, tn.ps != 0, st);
     }
     r += k;
   }
@@ -1095,12 +1109,17 @@ extern "C" cpm_status cpm_autotune(cpm_band* b, int dtype, int nrhs, const void*
     hipEvent_t e0, e1;
     CPM_HIP(hipEventCreate(&e0));
     CPM_HIP(hipEventCreate(&e1));
-    double t[4];
+    double t[kTuneVariants];
     int arg = 0;
     try {
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < kTuneVariants; ++k) {
         tn.pad = k & 1;
-        tn.xcd = k >> 1;
+        tn.xcd = (k >> 1) != 0;
+        tn.ps = (k >> 1) == 2;
+        if (tn.ps && b->tile_inst) {   // composites run the non-persistent gather
+          t[k] = HUGE_VAL;
+          continue;
+        }
         auto run = [&] {
           if (dtype == CPM_F64) apply_impl<double>(b, 0.0, -1.0, nrhs, (const double*)u, (double*)v, st);
           else apply_impl<float>(b, 0.0, -1.0, nrhs, (const float*)u, (float*)v, st);
@@ -1124,11 +1143,26 @@ extern "C" cpm_status cpm_autotune(cpm_band* b, int dtype, int nrhs, const void*
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     tn.pad = arg & 1;
-    tn.xcd = arg >> 1;
+    tn.xcd = (arg >> 1) != 0;
+    tn.ps = (arg >> 1) == 2;
     tn.tuned = 1;
     if (ms)
-      for (int k = 0; k < 4; ++k) ms[k] = t[k];
+      for (int k = 0; k < kTuneVariants; ++k) ms[k] = t[k];
     if (best) *best = arg;
+  });
+}
+
+extern "C" cpm_status cpm_tune_set(cpm_band* b, int dtype, int variant) {
+  return guard([&] {
+    if (!b) CPM_FAIL(CPM_E_INVALID, "null band");
+    if (dtype != CPM_F64 && dtype != CPM_F32) CPM_FAIL(CPM_E_INVALID, "unknown dtype %d", dtype);
+    if (variant < 0 || variant >= kTuneVariants)
+      CPM_FAIL(CPM_E_INVALID, "launch variant %d out of range [0, %d)", variant, kTuneVariants);
+    Tune& tn = b->tune[dtype == CPM_F64 ? 0 : 1];
+    tn.pad = variant & 1;
+    tn.xcd = (variant >> 1) != 0;
+    tn.ps = (variant >> 1) == 2;
+    tn.tuned = 1;
   });
 }
 

@@ -89,8 +89,12 @@ struct QMeta {
 struct Tune {
   int pad = 1;     // LDS x-line stride of the staged cube: 0 -> E + 1, 1 -> E + 4
   int xcd = 1;     // map consecutive tiles / blocks to one XCD
+  int ps = 0;      // tile gather as persistent wavefronts (implies xcd)
   int tuned = 0;
 };
+constexpr int kTuneVariants = 6;
+// Persistent tile gather: wavefronts per XCD (8 per SIMD at most are resident)
+constexpr int kPersistWavesPerXcd = 4096;
 
 }  // namespace cpm
 

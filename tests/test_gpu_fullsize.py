@@ -177,6 +177,38 @@ def test_fullsize_apply_sampled_rows(name):
         assert err < tol
 
 
+@pytest.mark.parametrize("name", ["sphere_lat_256", "torus_meridians_512"])
+def test_fullsize_apply_every_launch_variant(name):
+    """Each of the six launch variants (LDS padding x tile order, including
+    the persistent gather, whose wavefronts each take many tiles here) on the
+    sampled rows; the autotuned choice is restored afterwards."""
+    import torch
+    from paper_2305_04711_amd import cpm
+    S, Cs, N, band, ix, loc = _setup(name)
+    rng = np.random.default_rng(23)
+    u_np = rng.standard_normal(band.n)
+    Ks, curve, gpu_rows = _samples(S, Cs, N, band, ix, rng)
+    m, n = 0.0, -1.0
+
+    def u_of(K, c):
+        return u_np[ix.dof(K, c)]
+
+    ref = loc.apply_rows(Ks, curve, u_of, m, n)
+    scale = np.max(np.abs(ref))
+    try:
+        for td, tol in ((torch.float64, 1e-12), (torch.float32, 5e-6)):
+            u = torch.tensor(u_np, dtype=td, device="cuda")
+            for k in range(6):
+                cpm.tune_set(band, td, k)
+                v = cpm.apply(band, u, m, n).cpu().numpy().astype(np.float64)
+                err = np.max(np.abs(v[gpu_rows] - ref)) / scale
+                print(name, td, "variant", k, "rel err", err, flush=True)
+                assert err < tol
+    finally:
+        cpm.autotune(band, torch.float64)
+        cpm.autotune(band, torch.float32)
+
+
 def test_fullsize_sphere_latitude_solve():
     import torch
     from paper_2305_04711_amd import cpm
