@@ -579,10 +579,10 @@ __device__ __forceinline__ void atomic_add(T* p, T v) {
 // lane first computes the stencil base and 1-D weights of one row (c_i folded
 // into the last factor) into LDS; then the wave walks the rows with one lane
 // per stencil member (4 rows at a time in 2-D, where a stencil has 16
-// members), adding w c_i into the tile's (2 BX)^d cube in LDS.  The cube is
-// accumulated in FP64 for both precisions: LDS FP64 atomic adds are several
-// times faster than FP32 ones on gfx950.  Lanes past the last row carry zero
-// weights, so the row loop has no branches.  The cube is then added into z
+// members), adding w c_i into the tile's (2 BX)^d cube in LDS: in 3-D through
+// per-lane sums over runs of rows with the same stencil base, in 2-D with LDS
+// atomic adds (rows past the last one carry zero weights).  The cube is
+// accumulated in FP64 for both precisions.  The cube is then added into z
 // with plain loads and stores: tiles of one parity class stage disjoint
 // blocks and the classes run as successive launches, so no two waves of a
 // launch touch the same entry of z.
@@ -646,21 +646,39 @@ __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const
     }
     s_b[lane] = bs;
     __syncthreads();
-    constexpr int UR = 4;                     // rows per lane per step
-    const int nr = (nrow + UR * RPI - 1) / (UR * RPI) * (UR * RPI);
-    for (int j0 = 0; j0 < nr; j0 += UR * RPI) {
-      double v[UR];
-      int o[UR];
-#pragma unroll
-      for (int u = 0; u < UR; ++u) {
-        const int j = j0 + u * RPI + sub;
-        T w = s_w[ma][j] * s_w[4 + mb][j];
-        if (DIM == 3) w *= s_w[8 + mc][j];
-        v[u] = (double)w;
-        o[u] = s_b[j] + moff;
+    if constexpr (DIM == 3) {
+      // Rows are sorted by stencil base, and runs of rows share one: each
+      // lane sums its member's contributions in a register while the base
+      // stays the same and adds the sum into the cube when it changes.  A
+      // row's 64 members are distinct cells, and a wave's LDS operations
+      // complete in order, so these read-add-writes need no atomics.
+      double acc = 0.0;
+      int cur = __builtin_amdgcn_readfirstlane(s_b[0]);
+      for (int j = 0; j < nrow; ++j) {
+        const int bj = __builtin_amdgcn_readfirstlane(s_b[j]);
+        if (bj != cur) {
+          s_z[cur + moff] += acc;
+          acc = 0.0;
+          cur = bj;
+        }
+        acc += (double)(s_w[ma][j] * s_w[4 + mb][j] * s_w[8 + mc][j]);
       }
+      s_z[cur + moff] += acc;
+    } else {
+      constexpr int UR = 4;                   // rows per lane per step
+      const int nr = (nrow + UR * RPI - 1) / (UR * RPI) * (UR * RPI);
+      for (int j0 = 0; j0 < nr; j0 += UR * RPI) {
+        double v[UR];
+        int o[UR];
 #pragma unroll
-      for (int u = 0; u < UR; ++u) atomicAdd(&s_z[o[u]], v[u]);
+        for (int u = 0; u < UR; ++u) {
+          const int j = j0 + u * RPI + sub;
+          v[u] = (double)(s_w[ma][j] * s_w[4 + mb][j]);
+          o[u] = s_b[j] + moff;
+        }
+#pragma unroll
+        for (int u = 0; u < UR; ++u) atomicAdd(&s_z[o[u]], v[u]);
+      }
     }
     __syncthreads();
   }
