@@ -611,6 +611,18 @@ __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const
     qm = q.mask;
     qoff = q.off;
   }
+  // the old entries of z under the staged blocks, requested now so that the
+  // loads overlap the row work (no other wave of this launch writes them)
+  const int cx0 = G::lx(lane), cy0 = G::ly(lane), cz0 = G::lz(lane);
+  int zi[NQ];
+  T old[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const unsigned long long m = lane_u64(qm, q);
+    const int off = lane_i32(qoff, q);
+    zi[q] = ((m >> lane) & 1ull) ? off + __popcll(m & ((1ull << lane) - 1ull)) : -1;
+    old[q] = zi[q] >= 0 ? z[r * ld + zi[q]] : T(0);
+  }
   // this lane's stencil member and row slot within an instruction
   const int mo = lane & (M - 1), sub = lane / M;
   const int ma = mo & 3, mb = (mo >> 2) & 3, mc = DIM == 3 ? (mo >> 4) : 0;
@@ -654,14 +666,25 @@ __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const
       // complete in order, so these read-add-writes need no atomics.
       double acc = 0.0;
       int cur = __builtin_amdgcn_readfirstlane(s_b[0]);
-      for (int j = 0; j < nrow; ++j) {
-        const int bj = __builtin_amdgcn_readfirstlane(s_b[j]);
-        if (bj != cur) {
-          s_z[cur + moff] += acc;
-          acc = 0.0;
-          cur = bj;
+      for (int j = 0; j < nrow; j += 4) {
+        // four rows' bases and weights read at once (indices stay below 64)
+        int bq[4];
+        double wq[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          bq[u] = __builtin_amdgcn_readfirstlane(s_b[j + u]);
+          wq[u] = (double)(s_w[ma][j + u] * s_w[4 + mb][j + u] * s_w[8 + mc][j + u]);
         }
-        acc += (double)(s_w[ma][j] * s_w[4 + mb][j] * s_w[8 + mc][j]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (j + u >= nrow) break;
+          if (bq[u] != cur) {
+            s_z[cur + moff] += acc;
+            acc = 0.0;
+            cur = bq[u];
+          }
+          acc += wq[u];
+        }
       }
       s_z[cur + moff] += acc;
     } else {
@@ -682,25 +705,12 @@ __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const
     }
     __syncthreads();
   }
-  // all loads of z first, then the sums and stores, so that the wave waits
-  // for memory once rather than once per staged block
-  const int cx0 = G::lx(lane), cy0 = G::ly(lane), cz0 = G::lz(lane);
-  T* dst[NQ];
-  T old[NQ];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const unsigned long long m = lane_u64(qm, q);
-    const int off = lane_i32(qoff, q);
-    dst[q] = ((m >> lane) & 1ull) ? z + r * ld + off + __popcll(m & ((1ull << lane) - 1ull))
-                                  : nullptr;
-    old[q] = dst[q] ? *dst[q] : T(0);
-  }
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const int qx = q & 1, qy = (q >> 1) & 1, qz = DIM == 3 ? (q >> 2) : 0;
     const int cx = qx * G::BX + cx0, cy = qy * G::BX + cy0, cz = qz * G::BX + cz0;
     const int ci = DIM == 3 ? (cz * E + cy) * EP + cx : cy * EP + cx;
-    if (dst[q]) *dst[q] = old[q] + (T)s_z[ci];
+    if (zi[q] >= 0) z[r * ld + zi[q]] = old[q] + (T)s_z[ci];
   }
 }
 
