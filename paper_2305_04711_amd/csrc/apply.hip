@@ -576,16 +576,38 @@ __device__ __forceinline__ void atomic_add(T* p, T v) {
 }
 
 // E^T c for the tile rows of one parity class, one wavefront per tile.  Each
-// lane first computes the stencil base and 1-D weights of one row (c_i folded
-// into the last factor) into LDS; then the wave walks the rows with one lane
-// per stencil member (4 rows at a time in 2-D, where a stencil has 16
-// members), adding w c_i into the tile's (2 BX)^d cube in LDS: in 3-D through
-// per-lane sums over runs of rows with the same stencil base, in 2-D with LDS
-// atomic adds (rows past the last one carry zero weights).  The cube is
-// accumulated in FP64 for both precisions.  The cube is then added into z
+// lane first puts the stencil base of one row into LDS, with the row's
+// fractions and c_i (3-D) or its 1-D weights, c_i folded in (2-D); then the
+// wave walks the rows with one lane per stencil member (4 rows at a time in
+// 2-D, where a stencil has 16 members), adding w c_i into the tile's (2 BX)^d
+// cube in LDS.  In 3-D each lane evaluates its member's three 1-D weights as
+// cubics in Horner form (less LDS per wave, so more waves per SIMD) and sums
+// over runs of rows with the same stencil base; 2-D uses LDS atomic adds
+// (rows past the last one carry zero weights).  The cube is accumulated in
+// FP64 for both precisions.  The cube is then added into z
 // with plain loads and stores: tiles of one parity class stage disjoint
 // blocks and the classes run as successive launches, so no two waves of a
 // launch touch the same entry of z.
+// Coefficients (c3, c2, c1, c0) of the 1-D Lagrange weight of stencil node a
+// as a cubic in the fraction t (Horner form), for degree p = 3 or 2.
+template <class T>
+__device__ __forceinline__ void member_poly(int p, int a, T c[4]) {
+  const T s6 = T(1) / T(6), s3 = T(1) / T(3);
+  if (p == 3) {
+    const T k[4][4] = {{-s6, T(0.5), -s3, T(0)}, {T(0.5), T(-1), T(-0.5), T(1)},
+                       {T(-0.5), T(0.5), T(1), T(0)}, {s6, T(0), -s6, T(0)}};
+    for (int i = 0; i < 4; ++i) c[i] = k[a][i];
+  } else {
+    const T k[4][4] = {{T(0), T(0.5), T(-0.5), T(0)}, {T(0), T(-1), T(0), T(1)},
+                       {T(0), T(0.5), T(0.5), T(0)}, {T(0), T(0), T(0), T(0)}};
+    for (int i = 0; i < 4; ++i) c[i] = k[a][i];
+  }
+}
+template <class T>
+__device__ __forceinline__ T horner3(const T c[4], T t) {
+  return ((c[0] * t + c[1]) * t + c[2]) * t + c[3];
+}
+
 template <class T, int DIM>
 __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const int* __restrict__ list,
                                                  int N, const T* __restrict__ c, T* __restrict__ z,
@@ -597,7 +619,7 @@ __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const
   constexpr int RPI = 64 / M;                 // rows per wave instruction
   constexpr int NW = DIM == 3 ? 12 : 8;       // 1-D weights per row
   __shared__ double s_z[CS];
-  __shared__ T s_w[NW][64];                   // per-row 1-D weights, component major
+  __shared__ T s_w[DIM == 3 ? 4 : NW][64];                   // per-row 1-D weights, component major
   __shared__ int s_b[64];                     // per-row cube offset of member 0
   const int t = list[xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x];
   const int lane = threadIdx.x;
@@ -627,7 +649,12 @@ __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const
   const int mo = lane & (M - 1), sub = lane / M;
   const int ma = mo & 3, mb = (mo >> 2) & 3, mc = DIM == 3 ? (mo >> 4) : 0;
   const int moff = DIM == 3 ? (mc * E + mb) * EP + ma : mb * EP + ma;
+  T ca[4], cb[4], cc[4];
+  member_poly<T>(tv.p, ma, ca);
+  member_poly<T>(tv.p, mb, cb);
+  member_poly<T>(tv.p, mc, cc);
   for (int p0 = beg; p0 < end; p0 += 64) {
+    T tq[3] = {T(0), T(0), T(0)}, cq = T(0);
     const int nrow = min(64, end - p0);
     T wx[4] = {T(0), T(0), T(0), T(0)}, wy[4] = {T(0), T(0), T(0), T(0)};
     T wz[4] = {T(0), T(0), T(0), T(0)};
@@ -638,6 +665,10 @@ __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const
       int lb[3];
       T tt[3];
       row_stencil<T, DIM>(tv, pos, N, lb, tt);
+      tq[0] = tt[0];
+      tq[1] = tt[1];
+      tq[2] = tt[2];
+      cq = ci;
       lagrange_p<T>(tv.p, tt[0], wx);
       lagrange_p<T>(tv.p, tt[1], wy);
       if (DIM == 3) {
@@ -650,11 +681,17 @@ __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const
       }
       bs = DIM == 3 ? (lb[2] * E + lb[1]) * EP + lb[0] : lb[1] * EP + lb[0];
     }
+    if constexpr (DIM == 3) {
+      s_w[0][lane] = tq[0];
+      s_w[1][lane] = tq[1];
+      s_w[2][lane] = tq[2];
+      s_w[3][lane] = cq;
+    } else {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      s_w[k][lane] = wx[k];
-      s_w[4 + k][lane] = wy[k];
-      if (DIM == 3) s_w[8 + k][lane] = wz[k];
+      for (int k = 0; k < 4; ++k) {
+        s_w[k][lane] = wx[k];
+        s_w[4 + k][lane] = wy[k];
+      }
     }
     s_b[lane] = bs;
     __syncthreads();
@@ -666,17 +703,18 @@ __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const
       // complete in order, so these read-add-writes need no atomics.
       double acc = 0.0;
       int cur = __builtin_amdgcn_readfirstlane(s_b[0]);
-      for (int j = 0; j < nrow; j += 4) {
-        // four rows' bases and weights read at once (indices stay below 64)
-        int bq[4];
-        double wq[4];
+      for (int j = 0; j < nrow; j += 8) {
+        // eight rows' bases and weights read at once (indices stay below 64)
+        int bq[8];
+        double wq[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
           bq[u] = __builtin_amdgcn_readfirstlane(s_b[j + u]);
-          wq[u] = (double)(s_w[ma][j + u] * s_w[4 + mb][j + u] * s_w[8 + mc][j + u]);
+          wq[u] = (double)(horner3<T>(ca, s_w[0][j + u]) * horner3<T>(cb, s_w[1][j + u]) *
+                           horner3<T>(cc, s_w[2][j + u]) * s_w[3][j + u]);
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
           if (j + u >= nrow) break;
           if (bq[u] != cur) {
             s_z[cur + moff] += acc;
