@@ -40,17 +40,19 @@ BYTES_PER_ROW_F32 = 24.0   # tile gather: fraction 12 + base 4 + u 4 + a 4 (FP32
 # profiles/gather_torus512_pmc.md), each scaled by the same counter's reading
 # for a plain device copy of known size.  They hold only for the kernel
 # source they were taken on: `traffic` is null when its hash differs.
-GATHER_PMC = {"sources_sha1": "61d9cc0e0fe7085a0e578b96b7c239df56ac46b0",
-              "fetch_bytes": 1.73132e+09, "write_bytes": 3.40667e+08}
+GATHER_PMC = {"sources_sha1": "480842071485f7866847424de7823a08ed08e0c3",
+              "fetch_bytes": 1.49409e+09, "write_bytes": 2.96422e+08}
 def gather_sources_sha1():
-    """Hash of the FP64 tile gather's own source: the k_gather template, the
-    row and cube helpers it calls, and the Lagrange weights."""
+    """Hash of what sets the FP64 tile gather's traffic: its own source (the
+    k_gather templates, the row and cube helpers they call, the Lagrange
+    weights) and the band builder, which fixes the block order and tiles."""
     import hashlib
     src = open(os.path.join(ROOT, "paper_2305_04711_amd/csrc/apply.hip")).read()
     a = src.index("struct TileView {")
     b = src.index("template <class T>\n__device__ __forceinline__ T wave_sum")
     h = hashlib.sha1(src[a:b].encode())
-    h.update(open(os.path.join(ROOT, "paper_2305_04711_amd/csrc/lagrange.hpp"), "rb").read())
+    for f in ("lagrange.hpp", "builder.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2305_04711_amd/csrc", f), "rb").read())
     return h.hexdigest()
 
 
