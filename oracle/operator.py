@@ -16,6 +16,12 @@ nodes 0..p at the query 1 + t.
 Laplacian (eq. FD-stencil): weight -2d N^2 on the centre and N^2 on each face
 neighbour in the band; a neighbour outside the band is dropped.
 
+Band: the tube of eq. (bandwidth), or the stencil set (Sec. 5.1 cites it as
+keeping only the grid points interpolation and FD stencils need): the nodes
+of the DOFs that some interpolation stencil of the tube system uses, and the
+FD neighbours of those DOFs' rows.  The rows of the stencil-referenced DOFs
+are unchanged, so on them the solution is the tube's.
+
 Interior boundaries (Sec. 4.3), with the readings below:
   * PDE row i in K(C): an interpolation member or FD neighbour j in Omega(C)
     is replaced by its BC DOF alpha(j) when d*_i . v_j < 0 (eq.
@@ -49,6 +55,21 @@ from .band import (IBCSets, IndexMap, band_radius, dot_rows, node_coords,
 
 class StencilHole(RuntimeError):
     """A stencil member is not a band node (the band is too narrow)."""
+
+
+def stencil_set_nodes(tube):
+    """Stencil set of a tube system (Sec. 5.1): a boolean over its PDE nodes
+    (lexicographic) that keeps every node whose PDE or BC DOF is a column of
+    E (a member of some interpolation stencil), and every node carrying a DOF
+    that is an FD neighbour of such a DOF's row."""
+    used = np.zeros(tube.n, dtype=bool)
+    used[tube.E.tocsr().indices] = True
+    rows = np.nonzero(used)[0]
+    need = used.copy()
+    need[tube.L_off.tocsr()[rows].indices] = True
+    keep = need[:tube.n_s].copy()
+    keep[tube.bc_node[need[tube.n_s:]]] = True
+    return keep
 
 
 def lagrange_weights_1d(t, p=3):
@@ -131,9 +152,12 @@ class CPMSystem:
     """
 
     def __init__(self, surface, N, ibcs=(), order=2, p=3, q=1, r=None,
-                 tau_factor=0.1, check_factor=2.0, bc_types=None):
+                 tau_factor=0.1, check_factor=2.0, bc_types=None, band="tube"):
         if p not in (2, 3):
             raise ValueError("interpolation degree p must be 2 or 3")
+        if band not in ("tube", "stencil_set"):
+            raise ValueError("band is 'tube' or 'stencil_set'")
+        self.band = band
         d = surface.dim
         self.surface, self.N, self.dim = surface, int(N), d
         self.p = int(p)
@@ -143,6 +167,11 @@ class CPMSystem:
         self.inv_h2 = float(N) * float(N)
         self.order = int(order)
         K, CP = scan_band(surface, N, p, q, self.r)
+        if band == "stencil_set":
+            tube = CPMSystem(surface, N, ibcs, order, p, q, r, tau_factor, check_factor,
+                             bc_types, band="tube")
+            keep = stencil_set_nodes(tube)
+            K, CP = K[keep], CP[keep]
         self.K, self.CP = K, CP
         self.n_s = n_s = K.shape[0]
         self.index = IndexMap(K)
