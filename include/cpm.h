@@ -110,7 +110,15 @@ typedef struct {
   double r_band;       /* 0 = eq. (bandwidth) with q = 1                      */
   double tau_factor;   /* 0 = 0.1: on-C tolerance tau = tau_factor h^2 (Sec. 4.2) */
   double check_factor; /* 0 = 2: check region ||x - cp_C(x)|| < check_factor r (Sec. 4.6) */
+  int band;            /* CPM_BAND_TUBE (0): every node within r (eq.
+                          bandwidth); CPM_BAND_STENCIL_SET (1): only the nodes
+                          of the tube's DOFs that some interpolation stencil
+                          uses and the FD neighbours of their rows (Sec. 5.1
+                          cites this construction); on the stencil-referenced
+                          DOFs the system, hence the solution, is the tube's  */
 } cpm_grid;
+
+enum { CPM_BAND_TUBE = 0, CPM_BAND_STENCIL_SET = 1 };
 
 typedef struct cpm_band cpm_band;
 

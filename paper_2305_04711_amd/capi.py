@@ -40,7 +40,7 @@ class IBC(C.Structure):
 class Grid(C.Structure):
     _fields_ = [("N", C.c_int), ("p", C.c_int), ("order", C.c_int), ("check_reach", C.c_int),
                 ("r_band", C.c_double), ("tau_factor", C.c_double),
-                ("check_factor", C.c_double)]
+                ("check_factor", C.c_double), ("band", C.c_int)]
 
 
 class BandInfo(C.Structure):
@@ -63,6 +63,8 @@ class SolveStats(C.Structure):
                 ("restarts", C.c_int), ("fallback_f64", C.c_int), ("relres", C.c_double),
                 ("time_ms", C.c_double)]
 
+
+BAND_TUBE, BAND_STENCIL_SET = 0, 1
 
 EXPORTED = ["cpm_build_band", "cpm_band_free", "cpm_band_query", "cpm_band_export",
             "cpm_apply", "cpm_apply_profile", "cpm_autotune", "cpm_apply_transpose", "cpm_rhs", "cpm_rhs_adjoint", "cpm_solve",

@@ -76,16 +76,20 @@ def meridian_ibc(ex, ey, bc="dirichlet"):
 # ------------------------------------------------------------------ band
 class Band:
     """cpm_build_band: the narrow band, interior-boundary DOFs and stencils
-    for one surface and grid (h = 1/N)."""
+    for one surface and grid (h = 1/N).  band: "tube" (eq. bandwidth) or
+    "stencil_set" (only the nodes interpolation and FD stencils need)."""
 
     def __init__(self, surface, ibcs=(), N=64, order=2, r_band=0.0, tau_factor=0.0,
-                 check_factor=0.0, check_reach=False, p=3):
+                 check_factor=0.0, check_reach=False, p=3, band="tube"):
+        kinds = {"tube": capi.BAND_TUBE, "stencil_set": capi.BAND_STENCIL_SET}
+        if band not in kinds:
+            raise ValueError("band is 'tube' or 'stencil_set'")
         lib = capi.load()
         self._lib = lib
         self.handle = None
         arr = (capi.IBC * max(1, len(ibcs)))(*ibcs) if ibcs else None
         grid = capi.Grid(int(N), int(p), int(order), int(bool(check_reach)), float(r_band),
-                         float(tau_factor), float(check_factor))
+                         float(tau_factor), float(check_factor), kinds[band])
         out = C.c_void_p()
         capi.check(lib.cpm_build_band(C.byref(surface), arr, len(ibcs), C.byref(grid),
                                       _stream(), C.byref(out)))

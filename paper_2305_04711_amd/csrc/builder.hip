@@ -138,12 +138,21 @@ struct Box {
 
 // One workgroup per row of blocks (fixed by, bz); each wavefront classifies
 // one block at a time, lane = slot.  WRITE = false counts occupied blocks per
-// row; WRITE = true stores them in order at the row's offset.
+// row; WRITE = true stores them in order at the row's offset.  With a filter
+// (the stencil set, Sec. 5.1) a block keeps only the nodes of the filter's
+// mask for the same block coordinates.
+struct Filter {
+  const unsigned long long* hkeys = nullptr;   // block hash of the filtering band
+  const int* hvals = nullptr;
+  unsigned hcap = 0;
+  const unsigned long long* keep = nullptr;    // [its blocks] nodes to keep; null: no filter
+};
+
 template <int DIM, bool WRITE>
 __global__ __launch_bounds__(256) void k_classify(cpm_surface S, int N, double r,
                                                   double thr, Box box, int* row_count,
                                                   const int* row_off, int4* out_coord,
-                                                  unsigned long long* out_mask) {
+                                                  unsigned long long* out_mask, Filter F) {
   using G = Geo<DIM>;
   const int row = blockIdx.x;
   const int by = box.blo[1] + row % box.nb[1];
@@ -174,6 +183,10 @@ __global__ __launch_bounds__(256) void k_classify(cpm_surface S, int N, double r
         const V3 p = node_pos(kx, ky, kz, N);
         const bool in = dist<DIM>(p, cp_surface<DIM>(S, p)) <= r;
         m = __ballot(in);
+        if (F.keep && m) {
+          const int id = hash_find(F.hkeys, F.hvals, F.hcap, block_key(bx, by, DIM == 3 ? bz : 0));
+          m &= id >= 0 ? F.keep[id] : 0ull;
+        }
       }
     }
     if (lane == 0) s_mask[wave] = m;
@@ -804,8 +817,143 @@ double reach_of(const cpm_surface& S) {
   return S.R;
 }
 
+// ---- stencil set (Sec. 5.1), marked on a built tube band --------------
+// flag[id] = 1 for every row id of a list
+__global__ void k_ss_flag(const int* ids, int n, unsigned char* flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flag[ids[i]] = 1;
+}
+
+// used[j] = 1 for every member j of the stencil of a PDE row whose E row is
+// not explicit (an explicit row's columns are marked by k_ss_cols)
 template <int DIM>
-void build(cpm_band* b, hipStream_t st) {
+__global__ __launch_bounds__(256) void k_ss_members(Blocks B, int nb, int N, int64_t n_s,
+                                                    const double* cp, const unsigned char* isE,
+                                                    unsigned char* used) {
+  NODE_PROLOGUE(DIM);
+  if (isE[dof]) return;
+  const V3 y = load_v(cp, n_s, dof, DIM);
+  int base[3];
+  double t[3];
+  stencil_base<DIM>(y, N, B.p, base, t);
+  const int bb = block_of<DIM>(B, base[0], base[1], base[2]);
+  if (bb < 0) return;
+  const int lx = base[0] & (G::BX - 1), ly = base[1] & (G::BX - 1),
+            lz = DIM == 3 ? (base[2] & (G::BX - 1)) : 0;
+  const int np = B.p + 1, nmp = DIM == 3 ? np * np * np : np * np;
+  for (int o = 0; o < nmp; ++o) {
+    const int a = o % np, bq = (o / np) % np, c = o / (np * np);
+    const int j = node_dof<DIM>(B, bb, lx + a, ly + bq, lz + c);
+    if (j >= 0) used[j] = 1;
+  }
+}
+
+// flag[c] = 1 for every stored column c >= 0 of a [nrows][w] column table,
+// restricted to rows whose id is flagged in `only` (null: every row)
+__global__ void k_ss_cols(const int* ids, const int* col, int nrows, int w,
+                          const unsigned char* only, unsigned char* flag) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (int64_t)nrows * w) return;
+  const int i = (int)(g / w);
+  if (only && !only[ids[i]]) return;
+  const int c = col[g];
+  if (c >= 0) flag[c] = 1;
+}
+
+// need[j] = 1 for every used PDE row and its face neighbours in the band,
+// for rows whose FD stencil is not explicit (those go through k_ss_cols)
+template <int DIM>
+__global__ __launch_bounds__(256) void k_ss_fd(Blocks B, int nb, const unsigned char* used,
+                                               const unsigned char* isL, unsigned char* need) {
+  NODE_PROLOGUE(DIM);
+  if (!used[dof]) return;
+  need[dof] = 1;
+  if (isL[dof]) return;
+  const int l[3] = {G::lx(slot), G::ly(slot), G::lz(slot)};
+  for (int f = 0; f < 2 * DIM; ++f) {
+    int q[3] = {l[0], l[1], l[2]};
+    q[f >> 1] += (f & 1) ? 1 : -1;
+    const int j = node_dof<DIM>(B, blk, q[0], q[1], q[2]);
+    if (j >= 0) need[j] = 1;
+  }
+}
+
+// a needed BC DOF keeps its node; need[] over BC DOFs is also set for used
+// BC rows (their own index)
+__global__ void k_ss_bcnodes(int64_t n_s, int64_t n_c, const int* bc_node,
+                             const unsigned char* used, unsigned char* need) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_c) return;
+  if (used[n_s + k]) need[n_s + k] = 1;
+  if (need[n_s + k] || used[n_s + k]) need[bc_node[k]] = 1;
+}
+
+// keep[blk] = the block's slots whose PDE DOF is needed
+__global__ void k_ss_masks(const unsigned long long* mask, const int* off, int nb,
+                           const unsigned char* need, unsigned long long* keep) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const unsigned long long m = mask[b];
+  unsigned long long k = 0ull;
+  int d = off[b];
+  for (int s2 = 0; s2 < 64; ++s2)
+    if ((m >> s2) & 1ull) {
+      if (need[d]) k |= 1ull << s2;
+      ++d;
+    }
+  keep[b] = k;
+}
+
+template <int DIM>
+void build(cpm_band* b, hipStream_t st, const Filter& F);
+
+// The stencil set of a built tube band t: per block of t, the nodes that
+// carry a column of E (a member of some interpolation stencil) or an FD
+// neighbour of such a DOF's row, or the node of a BC DOF of either kind.
+// keep must hold t->nb entries; the filter refers to t's hash table.
+template <int DIM>
+Filter stencil_set_filter(const cpm_band* t, hipStream_t st, unsigned long long* keep) {
+  const int64_t n = t->n, n_s = t->n_s;
+  const int nm = DIM == 3 ? 64 : 16;
+  Tmp<unsigned char> isE(n), isL(n), used(n), need(n);
+  CPM_HIP(hipMemsetAsync(isE.p, 0, n, st));
+  CPM_HIP(hipMemsetAsync(isL.p, 0, n, st));
+  CPM_HIP(hipMemsetAsync(used.p, 0, n, st));
+  CPM_HIP(hipMemsetAsync(need.p, 0, n, st));
+  const Blocks B = view(t);
+  const dim3 gnode((t->nb + 3) / 4);
+  if (t->n_erows)
+    hipLaunchKernelGGL(k_ss_flag, dim3(grid_for(t->n_erows, 256)), dim3(256), 0, st, t->erow_id,
+                       t->n_erows, isE.p);
+  if (t->n_lrows)
+    hipLaunchKernelGGL(k_ss_flag, dim3(grid_for(t->n_lrows, 256)), dim3(256), 0, st, t->lrow_id,
+                       t->n_lrows, isL.p);
+  hipLaunchKernelGGL(k_ss_members<DIM>, gnode, dim3(256), 0, st, B, t->nb, t->N, n_s, t->cp,
+                     isE.p, used.p);
+  if (t->n_erows)
+    hipLaunchKernelGGL(k_ss_cols, dim3(grid_for((int64_t)t->n_erows * nm, 256)), dim3(256), 0, st,
+                       t->erow_id, t->ecol, t->n_erows, nm, nullptr, used.p);
+  hipLaunchKernelGGL(k_ss_fd<DIM>, gnode, dim3(256), 0, st, B, t->nb, used.p, isL.p, need.p);
+  if (t->n_lrows)
+    hipLaunchKernelGGL(k_ss_cols, dim3(grid_for((int64_t)t->n_lrows * 2 * DIM, 256)), dim3(256), 0,
+                       st, t->lrow_id, t->lcol, t->n_lrows, 2 * DIM, used.p, need.p);
+  if (t->n_c)
+    hipLaunchKernelGGL(k_ss_bcnodes, dim3(grid_for(t->n_c, 256)), dim3(256), 0, st, n_s, t->n_c,
+                       t->bc_node, used.p, need.p);
+  hipLaunchKernelGGL(k_ss_masks, dim3(grid_for(t->nb, 256)), dim3(256), 0, st, t->blk_mask,
+                     t->blk_off, t->nb, need.p, keep);
+  CPM_LAUNCH_CHECK();
+  CPM_HIP(hipStreamSynchronize(st));
+  Filter F;
+  F.hkeys = t->hkeys;
+  F.hvals = t->hvals;
+  F.hcap = t->hcap;
+  F.keep = keep;
+  return F;
+}
+
+template <int DIM>
+void build(cpm_band* b, hipStream_t st, const Filter& F) {
   using G = Geo<DIM>;
   const cpm_surface& S = b->surf;
   const int N = b->N;
@@ -837,7 +985,7 @@ void build(cpm_band* b, hipStream_t st) {
   // ---- pass 1: occupied blocks (row by row), then sorted into Morton order
   Tmp<int> row_count(nrows), row_off(nrows);
   hipLaunchKernelGGL((k_classify<DIM, false>), dim3(nrows), dim3(256), 0, st, S, N, r, thr, box,
-                     row_count.p, nullptr, nullptr, nullptr);
+                     row_count.p, nullptr, nullptr, nullptr, F);
   CPM_LAUNCH_CHECK();
   const int64_t nb64 = scan_exclusive_i32(row_count.p, row_off.p, nrows, st);
   if (nb64 <= 0) CPM_FAIL(CPM_E_INVALID, "the band is empty (N = %d)", N);
@@ -852,7 +1000,7 @@ void build(cpm_band* b, hipStream_t st) {
     Tmp<unsigned long long> mask0(nb), key0(nb), key1(nb);
     Tmp<int> idx0(nb), idx1(nb);
     hipLaunchKernelGGL((k_classify<DIM, true>), dim3(nrows), dim3(256), 0, st, S, N, r, thr, box,
-                       nullptr, row_off.p, coord0.p, mask0.p);
+                       nullptr, row_off.p, coord0.p, mask0.p, F);
     CPM_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_morton, dim3(grid_for(nb, 256)), dim3(256), 0, st, coord0.p, nb, key0.p,
                        idx0.p);
@@ -1179,8 +1327,37 @@ extern "C" cpm_status cpm_build_band(const cpm_surface* surface, const cpm_ibc* 
     if (grid->check_reach && !(b->r < reach_of(*surface)))
       CPM_FAIL(CPM_E_REACH, "band radius %.6g is not below the reach %.6g of the surface "
                "(h must be smaller)", b->r, reach_of(*surface));
-    if (b->dim == 3) build<3>(b.get(), st);
-    else build<2>(b.get(), st);
+    if (grid->band != CPM_BAND_TUBE && grid->band != CPM_BAND_STENCIL_SET)
+      CPM_FAIL(CPM_E_INVALID, "unknown band kind %d", grid->band);
+    if (grid->band == CPM_BAND_STENCIL_SET) {
+      // the tube first, then the same construction restricted to its
+      // stencil set (a node filter in the classification pass)
+      std::unique_ptr<cpm_band> t(new cpm_band());
+      t->device = b->device;
+      t->dim = b->dim;
+      t->N = b->N;
+      t->order = b->order;
+      t->p = b->p;
+      t->surf = b->surf;
+      t->n_ibc = b->n_ibc;
+      t->ibcs = b->ibcs;
+      t->h = b->h;
+      t->r = b->r;
+      t->tau = b->tau;
+      t->check_factor = b->check_factor;
+      if (b->dim == 3) build<3>(t.get(), st, Filter{});
+      else build<2>(t.get(), st, Filter{});
+      Tmp<unsigned long long> keep(t->nb);
+      const Filter F = b->dim == 3 ? stencil_set_filter<3>(t.get(), st, keep.p)
+                                   : stencil_set_filter<2>(t.get(), st, keep.p);
+      if (b->dim == 3) build<3>(b.get(), st, F);
+      else build<2>(b.get(), st, F);
+      CPM_HIP(hipStreamSynchronize(st));
+      b->band_kind = CPM_BAND_STENCIL_SET;
+    } else {
+      if (b->dim == 3) build<3>(b.get(), st, Filter{});
+      else build<2>(b.get(), st, Filter{});
+    }
     *out = b.release();
   });
 }

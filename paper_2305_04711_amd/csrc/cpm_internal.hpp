@@ -101,6 +101,7 @@ constexpr int kPersistWavesPerXcd = 4096;
 // The band: everything a call needs, all arrays on the device.
 struct cpm_band {
   int dim = 0, N = 0, order = 2, n_ibc = 0, p = 3;
+  int band_kind = CPM_BAND_TUBE;
   cpm_surface surf{};
   std::vector<cpm_ibc> ibcs;
   double h = 0, r = 0, tau = 0, check_factor = 2;

@@ -8,9 +8,10 @@ from oracle import geometry as G
 from oracle import operator as O
 
 
-def oracle_and_gpu(cfg, N, order=2, degree=3):
+def oracle_and_gpu(cfg, N, order=2, degree=3, band="tube"):
     """Build the oracle system and the GPU band for a named configuration
-    (interpolation degree: 3 cubic, 2 quadratic)."""
+    (interpolation degree: 3 cubic, 2 quadratic; band: "tube" or
+    "stencil_set")."""
     from paper_2305_04711_amd import cpm
     if cfg == "circle_point":
         S = G.Circle()
@@ -69,9 +70,9 @@ def oracle_and_gpu(cfg, N, order=2, degree=3):
     else:
         raise KeyError(cfg)
     bc_types = bct if cfg in NEUMANN_CASES or cfg == "sphere_arc" else None
-    sysm = O.CPMSystem(S, N, Cs, order=order, bc_types=bc_types, p=degree)
-    band = cpm.Band(gs, gi, N, order=order, p=degree)
-    return sysm, band
+    sysm = O.CPMSystem(S, N, Cs, order=order, bc_types=bc_types, p=degree, band=band)
+    gband = cpm.Band(gs, gi, N, order=order, p=degree, band=band)
+    return sysm, gband
 
 
 # configurations with a zero-Neumann side (screened operators: m = 1)

@@ -38,7 +38,7 @@ def test_struct_layouts_match_header_sizes():
     # the Python mirrors of the C structs: field order and padding
     assert ctypes.sizeof(capi.Surface) == 4 + 4 + 3 * 8 + 8 + 8
     assert ctypes.sizeof(capi.IBC) == 8 + 3 * 8 + 3 * 8 + 8 + 2 * 8 + 2 * 4 + 4 * 8
-    assert ctypes.sizeof(capi.Grid) == 4 * 4 + 3 * 8
+    assert ctypes.sizeof(capi.Grid) == 4 * 4 + 3 * 8 + 4 + 4
     assert ctypes.sizeof(capi.SolveOpts) == 3 * 8 + 2 * 4 + 8 + 2 * 4 + 8 + 8
     assert ctypes.sizeof(capi.SolveStats) == 5 * 4 + 4 + 2 * 8
 
