@@ -150,15 +150,16 @@ def run_batch(dev, args):
     return out
 
 
-def run_quadratic(dev, args, N, m, n, dt64_cubic, solves_cubic):
-    """The same torus and interior boundaries with quadratic interpolation
-    (p = 2, Sec. 7): band size, FP64 apply time and the FP64 solve to 1e-8,
-    beside the cubic figures."""
+def run_variant(dev, args, N, m, n, dt64_cubic, solves_cubic, n_tube, **kw):
+    """The same torus and interior boundaries with another discretisation
+    choice (quadratic interpolation, p = 2, Sec. 7; or the stencil-set band,
+    Sec. 5.1): band size, FP64 apply time and the FP64 solve to 1e-8, beside
+    the cubic tube's figures."""
     import torch
     from paper_2305_04711_amd import cpm, inputs
     t0 = time.perf_counter()
     band = cpm.Band(cpm.torus(1.0, 0.4), [cpm.meridian_ibc(1.0, 0.0),
-                                          cpm.meridian_ibc(-1.0, 0.0)], N, order=2, p=2)
+                                          cpm.meridian_ibc(-1.0, 0.0)], N, order=2, **kw)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     cpm.autotune(band, torch.float64, 1, reps=10)
@@ -174,9 +175,9 @@ def run_quadratic(dev, args, N, m, n, dt64_cubic, solves_cubic):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t) / args.steps
     del v
-    out = {"dofs": band.n, "n_s": band.n_s, "n_c": band.n_c, "build_s": build_s,
-           "apply_f64_ms": dt * 1e3, "gnodes_per_s": band.n / dt / 1e9,
-           "apply_speedup_vs_cubic": dt64_cubic / dt}
+    out = {"dofs": band.n, "n_s": band.n_s, "n_c": band.n_c, "dofs_vs_tube": band.n / n_tube,
+           "build_s": build_s, "apply_f64_ms": dt * 1e3, "gnodes_per_s": band.n / dt / 1e9,
+           "apply_speedup_vs_cubic_tube": dt64_cubic / dt}
     if solves_cubic is not None:
         cp = band.cp()
         f = torch.tensor(inputs.torus_field(inputs.torus_coeffs(100), cp), device=dev)
@@ -189,8 +190,8 @@ def run_quadratic(dev, args, N, m, n, dt64_cubic, solves_cubic):
         sec = time.perf_counter() - t
         out["solve_f64"] = {"seconds": sec, "converged": bool(st["converged"]),
                             "relres": st["relres"], "krylov_iters": st["krylov_iters"],
-                            "speedup_vs_cubic": solves_cubic["f64"]["seconds"] / sec}
-    log("quadratic p=2: %s" % out)
+                            "speedup_vs_cubic_tube": solves_cubic["f64"]["seconds"] / sec}
+    log("variant %s: %s" % (kw, out))
     return out
 
 
@@ -241,7 +242,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--no-quadratic", action="store_true",
-                    help="skip the quadratic-interpolation (p = 2) band")
+                    help="skip the quadratic-interpolation (p = 2) and stencil-set bands")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (a kernel of known "
                          "traffic for scaling the HBM byte counters)")
@@ -381,9 +382,10 @@ def main():
                    "grad_g_norm": gr.grad.norm().item()}
         log("adjoint: %s" % adjoint)
 
-    quad = None
+    quad = ssb = None
     if not args.no_quadratic:
-        quad = run_quadratic(dev, args, N, m, n, dt64, solves)
+        quad = run_variant(dev, args, N, m, n, dt64, solves, band.n, p=2)
+        ssb = run_variant(dev, args, N, m, n, dt64, solves, band.n, band="stencil_set")
 
     batch_out = None
     if not args.no_batch:
@@ -437,6 +439,7 @@ def main():
         "batched": batch_out,
         "heat_cn": heat_out,
         "quadratic_p2": quad,
+        "stencil_set_band": ssb,
     }
     print(json.dumps(out))
 
