@@ -240,3 +240,33 @@ def test_fullsize_sphere_latitude_solve():
     # the oracle's errors at h = 1/16 .. 1/48 (3.2e-3 .. 3.9e-4) extrapolate
     # to about 2e-5 at h = 1/256
     assert err < 4e-5
+
+
+@pytest.mark.parametrize("mode", ["mixed", "f64"])
+def test_fullsize_torus_solve_in_the_bench_configuration(mode):
+    """The solve bench.py times (torus h = 1/512, meridian Dirichlet IBCs,
+    the bench's seeded f and g, Poisson, tol 1e-8): the residual of sampled
+    rows, evaluated by the oracle row by row from the GPU solution, is
+    bounded by the 2-norm relative residual the solver reports."""
+    import torch
+    from paper_2305_04711_amd import cpm
+    S, Cs, N, band, ix, loc = _setup("torus_meridians_512")
+    cp = band.cp()
+    f = torch.tensor(inputs.torus_field(inputs.torus_coeffs(100), cp), device="cuda")
+    g = torch.tensor(inputs.meridian_dirichlet(band.bc_cpc(), seed=2), device="cuda")
+    b = cpm.rhs(band, f, g, -1.0)
+    x, st = cpm.solve(band, b, 0.0, -1.0, tol=1e-8, mode=mode)
+    print("C5 solve", mode, st, flush=True)
+    assert st["converged"] and st["relres"] <= 1e-8
+    xn = x.cpu().numpy()
+    bn = b.cpu().numpy()
+    rng = np.random.default_rng(24)
+    Ks, curve, gpu_rows = _samples(S, Cs, N, band, ix, rng)
+
+    def u_of(K, c):
+        return xn[ix.dof(K, c)]
+
+    Ax = loc.apply_rows(Ks, curve, u_of, 0.0, -1.0)
+    res = np.abs(bn[gpu_rows] - Ax)
+    assert np.max(res) <= 1e-8 * np.linalg.norm(bn) * 1.0001
+
