@@ -772,6 +772,55 @@ __global__ __launch_bounds__(256) void k_gather_rows_T(int nrows, int nm, const 
   }
 }
 
+// E^T c over the explicit rows by pull lists, in two balanced passes: every
+// entry's product w c_i (FP64), then one thread per target DOF sums its
+// contiguous segment in ascending source order and adds it to z once: the
+// same value on every run, with no atomics.
+template <class T>
+__global__ void k_et_prod(int total, const int* __restrict__ row, const T* __restrict__ w,
+                          const T* __restrict__ c, double* __restrict__ prod) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < total) prod[e] = (double)(w[e] * c[row[e]]);
+}
+
+template <class T>
+__global__ void k_et_sum(int n_tgt, const int* __restrict__ tgt, const int* __restrict__ start,
+                         const double* __restrict__ prod, T* __restrict__ z) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_tgt) return;
+  double acc = 0.0;
+  for (int e = start[k]; e < start[k + 1]; ++e) acc += prod[e];
+  z[tgt[k]] += (T)acc;
+}
+
+template <class T>
+static const T* et_w_of(const cpm_band* b);
+template <>
+const double* et_w_of<double>(const cpm_band* b) { return b->et_w; }
+template <>
+const float* et_w_of<float>(const cpm_band* b) { return b->et_w32; }
+
+// The corrections of (L - diag L)^T w for explicit FD rows by pull lists:
+// c[t] += co (sum of +w_i over rows adding to t, -w_i over swapped rows
+// moving their entry away from t), in ascending source order.
+template <class T>
+__global__ void k_lt_pull(int n_tgt, const int* __restrict__ tgt, const int* __restrict__ start,
+                          const int* __restrict__ src, const int* __restrict__ row_id,
+                          const T* __restrict__ w, T* __restrict__ c, int64_t ld, int nrhs, T co) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_tgt) return;
+  const int t = tgt[k], b0 = start[k], b1 = start[k + 1];
+  for (int r = 0; r < nrhs; ++r) {
+    double acc = 0.0;
+    for (int e = b0; e < b1; ++e) {
+      const int v = src[e];
+      const double wi = (double)(co * w[r * ld + row_id[v >> 1]]);
+      acc += (v & 1) ? -wi : wi;
+    }
+    c[r * ld + t] += (T)acc;
+  }
+}
+
 // Corrections of (L - diag L)^T w for explicit FD rows: a swapped PDE entry
 // moves its contribution from the PDE column to the BC column; a BC row adds
 // to each of its columns.
@@ -1043,7 +1092,13 @@ static void apply_T_dim(const cpm_band* b, double m, double n, int nrhs, const T
   hipLaunchKernelGGL((k_lap<T, DIM, true>), dim3((b->nb + 4 * kLapBlocksPerWave - 1) / (4 * kLapBlocksPerWave)), dim3(256), 0, st, bview(b), w,
                      w, c, ld, nrhs, T(0), co, nullptr, 0.0, tune_of<T>(b).xcd, nullptr, nullptr);
   CPM_LAUNCH_CHECK();
-  if (b->n_lrows) {
+  if (b->lt_tgt) {
+    if (b->n_lt) {
+      hipLaunchKernelGGL(k_lt_pull<T>, dim3(grid_for(b->n_lt, 256)), dim3(256), 0, st, b->n_lt,
+                         b->lt_tgt, b->lt_start, b->lt_src, b->lrow_id, w, c, ld, nrhs, co);
+      CPM_LAUNCH_CHECK();
+    }
+  } else if (b->n_lrows) {
     hipLaunchKernelGGL(k_lap_rows_T<T>, dim3(grid_for(b->n_lrows, 128)), dim3(128), 0, st,
                        b->n_lrows, 2 * DIM, b->n_s, b->lrow_id, b->lcol, b->lcol0, w, c, ld, nrhs,
                        co);
@@ -1062,7 +1117,19 @@ static void apply_T_dim(const cpm_band* b, double m, double n, int nrhs, const T
         CPM_LAUNCH_CHECK();
       }
   }
-  if (b->n_erows) {
+  if (b->et_tgt) {
+    if (b->n_et) {
+      double* prod = static_cast<double*>(
+          band_scratch(b, kEtProdSlot, sizeof(double) * (size_t)b->n_et_entries));
+      for (int r = 0; r < nrhs; ++r) {
+        hipLaunchKernelGGL(k_et_prod<T>, dim3(grid_for(b->n_et_entries, 256)), dim3(256), 0, st,
+                           b->n_et_entries, b->et_src, et_w_of<T>(b), c + r * ld, prod);
+        hipLaunchKernelGGL(k_et_sum<T>, dim3(grid_for(b->n_et, 256)), dim3(256), 0, st, b->n_et,
+                           b->et_tgt, b->et_start, prod, e + r * ld);
+      }
+      CPM_LAUNCH_CHECK();
+    }
+  } else if (b->n_erows) {
     const int nm = DIM == 3 ? 64 : 16;
     hipLaunchKernelGGL(k_gather_rows_T<T>, dim3(grid_for((int64_t)b->n_erows * nm, 256)),
                        dim3(256), 0, st, b->n_erows, nm, b->erow_id, b->ecol, ew_of<T>(b), c, e,

@@ -817,6 +817,102 @@ double reach_of(const cpm_surface& S) {
   return S.R;
 }
 
+// ---- pull lists of the transposed explicit rows --------------------------
+// The transposed apply adds every explicit row's contributions into their
+// target entries.  Sorting (target, source) pairs once per band lets a pull
+// kernel sum each target's contributions in a fixed order, with no atomics.
+constexpr int kNoTarget = 0x7fffffff;
+
+// E rows: entry g = i * nm + o targets ecol[g] (if a column)
+__global__ void k_pull_pairs_e(int64_t ne, const int* ecol, int* key, int* val) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ne) return;
+  const int c = ecol[g];
+  key[g] = c >= 0 ? c : kNoTarget;
+  val[g] = (int)g;
+}
+
+// L rows: entry (i, f, s) of explicit FD row i and neighbour f; a swapped
+// PDE entry moves its contribution from the unswapped column k0 (s = 1,
+// subtracted) to k1 (s = 0, added); a BC row adds to every column k1.
+// val = 2 i + s.
+__global__ void k_pull_pairs_l(int nrows, int nf, int64_t n_s, const int* row_id,
+                               const int* lcol, const int* lcol0, int* key, int* val) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (int64_t)nrows * nf * 2) return;
+  const int i = (int)(g / (2 * nf)), f = (int)((g / 2) % nf), sgn = (int)(g & 1);
+  const int k1 = lcol[(int64_t)i * nf + f];
+  int t = kNoTarget;
+  if (row_id[i] < n_s) {
+    const int k0 = lcol0[(int64_t)i * nf + f];
+    if (k0 != k1) {
+      if (sgn == 1 && k0 >= 0) t = k0;
+      if (sgn == 0 && k1 >= 0) t = k1;
+    }
+  } else if (sgn == 0 && k1 >= 0) {
+    t = k1;
+  }
+  key[g] = t;
+  val[g] = 2 * i + sgn;
+}
+
+// E pull entries in sorted order: the source's weights (both precisions) and
+// its row's DOF, which replaces the source index in place
+__global__ void k_pull_denorm_e(int total, int* src, int nm, const int* erow_id, const double* ew,
+                                const float* ew32, double* w64, float* w32) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int g = src[e];
+  w64[e] = ew[g];
+  w32[e] = ew32[g];
+  src[e] = erow_id[g / nm];
+}
+
+// Sorts the pairs by target (stable: sources ascending within a target) and
+// stores the distinct targets, their segment starts and the sources.
+static void build_pull(cpm_band* b, int64_t ne, Tmp<int>& key, Tmp<int>& val, hipStream_t st,
+                       int& n_tgt, int*& tgt, int*& start, int*& src) {
+  n_tgt = 0;
+  if (ne <= 0) return;
+  if (ne >= (1ll << 31)) CPM_FAIL(CPM_E_INVALID, "too many explicit-row entries");
+  const int n = (int)ne;
+  Tmp<int> key2(n), val2(n), uniq(n), cnt(n), nrun(1);
+  size_t tb = 0;
+  CPM_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, key.p, key2.p, val.p, val2.p, n, 0, 31, st));
+  {
+    Tmp<unsigned char> tmp(tb);
+    CPM_HIP(hipcub::DeviceRadixSort::SortPairs(tmp.p, tb, key.p, key2.p, val.p, val2.p, n, 0, 31,
+                                               st));
+  }
+  tb = 0;
+  CPM_HIP(hipcub::DeviceRunLengthEncode::Encode(nullptr, tb, key2.p, uniq.p, cnt.p, nrun.p, n, st));
+  {
+    Tmp<unsigned char> tmp(tb);
+    CPM_HIP(hipcub::DeviceRunLengthEncode::Encode(tmp.p, tb, key2.p, uniq.p, cnt.p, nrun.p, n, st));
+  }
+  int runs = 0;
+  CPM_HIP(hipMemcpyAsync(&runs, nrun.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  CPM_HIP(hipStreamSynchronize(st));
+  std::vector<int> hu(runs), hc(runs);
+  CPM_HIP(hipMemcpyAsync(hu.data(), uniq.p, sizeof(int) * runs, hipMemcpyDeviceToHost, st));
+  CPM_HIP(hipMemcpyAsync(hc.data(), cnt.p, sizeof(int) * runs, hipMemcpyDeviceToHost, st));
+  CPM_HIP(hipStreamSynchronize(st));
+  int nt = runs;
+  if (nt && hu[nt - 1] == kNoTarget) --nt;   // entries without a target sort last
+  std::vector<int> hs(nt + 1, 0);
+  for (int k = 0; k < nt; ++k) hs[k + 1] = hs[k] + hc[k];
+  n_tgt = nt;
+  tgt = b->alloc<int>(nt);
+  start = b->alloc<int>(nt + 1);
+  src = b->alloc<int>(hs[nt]);
+  if (nt) {
+    CPM_HIP(hipMemcpyAsync(tgt, hu.data(), sizeof(int) * nt, hipMemcpyHostToDevice, st));
+    CPM_HIP(hipMemcpyAsync(start, hs.data(), sizeof(int) * (nt + 1), hipMemcpyHostToDevice, st));
+    CPM_HIP(hipMemcpyAsync(src, val2.p, sizeof(int) * hs[nt], hipMemcpyDeviceToDevice, st));
+  }
+  CPM_HIP(hipStreamSynchronize(st));
+}
+
 // ---- stencil set (Sec. 5.1), marked on a built tube band --------------
 // flag[id] = 1 for every row id of a list
 __global__ void k_ss_flag(const int* ids, int n, unsigned char* flag) {
@@ -1209,6 +1305,36 @@ void build(cpm_band* b, hipStream_t st, const Filter& F) {
                          n_s, n_c, b->bc_node, bc_kp->p, row_c.p, alpha_of.p, side_v.p,
                          (int)nl_pde, b->lrow_id, b->lcol, b->lcol0);
     CPM_LAUNCH_CHECK();
+  }
+  // pull lists of the transposed explicit rows
+  {
+    const int64_t ne = (int64_t)b->n_erows * NM;
+    Tmp<int> key(ne ? ne : 1), val(ne ? ne : 1);
+    if (ne) {
+      hipLaunchKernelGGL(k_pull_pairs_e, dim3(grid_for(ne, 256)), dim3(256), 0, st, ne, b->ecol,
+                         key.p, val.p);
+      CPM_LAUNCH_CHECK();
+    }
+    build_pull(b, ne, key, val, st, b->n_et, b->et_tgt, b->et_start, b->et_src);
+    if (b->n_et) {
+      int total = 0;
+      CPM_HIP(hipMemcpyAsync(&total, b->et_start + b->n_et, sizeof(int), hipMemcpyDeviceToHost, st));
+      CPM_HIP(hipStreamSynchronize(st));
+      b->n_et_entries = total;
+      b->et_w = b->alloc<double>(total);
+      b->et_w32 = b->alloc<float>(total);
+      hipLaunchKernelGGL(k_pull_denorm_e, dim3(grid_for(total, 256)), dim3(256), 0, st, total,
+                         b->et_src, NM, b->erow_id, b->ew, b->ew32, b->et_w, b->et_w32);
+      CPM_LAUNCH_CHECK();
+    }
+    const int64_t nl = (int64_t)b->n_lrows * 2 * DIM * 2;
+    Tmp<int> keyl(nl ? nl : 1), vall(nl ? nl : 1);
+    if (nl) {
+      hipLaunchKernelGGL(k_pull_pairs_l, dim3(grid_for(nl, 256)), dim3(256), 0, st, b->n_lrows,
+                         2 * DIM, n_s, b->lrow_id, b->lcol, b->lcol0, keyl.p, vall.p);
+      CPM_LAUNCH_CHECK();
+    }
+    build_pull(b, nl, keyl, vall, st, b->n_lt, b->lt_tgt, b->lt_start, b->lt_src);
   }
   // metadata read by the apply kernels
   b->tile_meta = b->alloc<QMeta>((size_t)b->ntiles * 8);

@@ -156,6 +156,19 @@ struct cpm_band {
   int* lcol = nullptr;                // [n_lrows][2 dim] after swaps, -1 none
   int* lcol0 = nullptr;               // [n_lrows][2 dim] before swaps (PDE rows)
 
+  // pull lists of the transposed explicit rows (single bands; a batch's
+  // composite has none and scatters with atomics): target DOFs, segment
+  // starts and sources in ascending order per target.  E: per entry the DOF
+  // of its row and its weight (et_src, et_w, et_w32; sources i * 4^d + o,
+  // entry o of explicit E row i, in ascending order).  L: source 2 i + s,
+  // explicit FD row i, s = 1 for the subtracted unswapped column of a
+  // swapped PDE entry.
+  int n_et = 0, n_lt = 0, n_et_entries = 0;
+  int *et_tgt = nullptr, *et_start = nullptr, *et_src = nullptr;
+  double* et_w = nullptr;
+  float* et_w32 = nullptr;
+  int *lt_tgt = nullptr, *lt_start = nullptr, *lt_src = nullptr;
+
   // BC DOFs
   int* bc_node = nullptr;             // [n_c]
   double* bc_cpc = nullptr;           // [n_c][dim]
@@ -201,6 +214,8 @@ struct Workspace {
   ~Workspace();
 };
 void* band_scratch(const cpm_band* b, int slot, size_t bytes);
+// scratch slot of the transposed apply's per-entry products (E pull lists)
+constexpr int kEtProdSlot = 6;
 
 // Device-wide exclusive scan; returns the total (synchronises the stream).
 int64_t scan_exclusive_i32(const int* in, int* out, int64_t n, hipStream_t s);
