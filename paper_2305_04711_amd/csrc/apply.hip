@@ -570,11 +570,6 @@ __global__ void k_sum_final(const double* part, int np, double* out) {
 }
 
 // ---------------------------------------------------------------- transpose
-template <class T>
-__device__ __forceinline__ void atomic_add(T* p, T v) {
-  unsafeAtomicAdd(p, v);
-}
-
 // E^T c for the tile rows of one parity class, one wavefront per tile.  Each
 // lane first puts the stencil base of one row into LDS, with the row's
 // fractions and c_i (3-D) or its 1-D weights, c_i folded in (2-D); then the
@@ -752,26 +747,6 @@ __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const
   }
 }
 
-template <class T>
-__global__ __launch_bounds__(256) void k_gather_rows_T(int nrows, int nm, const int* __restrict__ row_id,
-                                                       const int* __restrict__ col,
-                                                       const T* __restrict__ w,
-                                                       const T* __restrict__ c, T* __restrict__ z,
-                                                       int64_t ld, int nrhs) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t i = g / nm;
-  const int o = (int)(g % nm);
-  if (i >= nrows) return;
-  const int cc = col[i * nm + o];
-  if (cc < 0) return;
-  const T wt = w[i * nm + o];
-  const int id = row_id[i];
-  for (int r = 0; r < nrhs; ++r) {
-    const T ci = c[r * ld + id];
-    if (ci != T(0)) atomic_add(&z[r * ld + cc], wt * ci);
-  }
-}
-
 // E^T c over the explicit rows by pull lists, in two balanced passes: every
 // entry's product w c_i (FP64), then one thread per target DOF sums its
 // contiguous segment in ascending source order and adds it to z once: the
@@ -818,33 +793,6 @@ __global__ void k_lt_pull(int n_tgt, const int* __restrict__ tgt, const int* __r
       acc += (v & 1) ? -wi : wi;
     }
     c[r * ld + t] += (T)acc;
-  }
-}
-
-// Corrections of (L - diag L)^T w for explicit FD rows: a swapped PDE entry
-// moves its contribution from the PDE column to the BC column; a BC row adds
-// to each of its columns.
-template <class T>
-__global__ void k_lap_rows_T(int nrows, int nf, int64_t n_s, const int* __restrict__ row_id,
-                             const int* __restrict__ col, const int* __restrict__ col0,
-                             const T* __restrict__ w, T* __restrict__ c, int64_t ld, int nrhs, T co) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nrows) return;
-  const int id = row_id[i];
-  for (int r = 0; r < nrhs; ++r) {
-    const T wi = co * w[r * ld + id];
-    for (int f = 0; f < nf; ++f) {
-      const int k1 = col[i * nf + f];
-      if (id < n_s) {
-        const int k0 = col0[i * nf + f];
-        if (k0 != k1) {
-          if (k0 >= 0) atomic_add(&c[r * ld + k0], -wi);
-          if (k1 >= 0) atomic_add(&c[r * ld + k1], wi);
-        }
-      } else if (k1 >= 0) {
-        atomic_add(&c[r * ld + k1], wi);
-      }
-    }
   }
 }
 
@@ -1099,10 +1047,7 @@ static void apply_T_dim(const cpm_band* b, double m, double n, int nrhs, const T
       CPM_LAUNCH_CHECK();
     }
   } else if (b->n_lrows) {
-    hipLaunchKernelGGL(k_lap_rows_T<T>, dim3(grid_for(b->n_lrows, 128)), dim3(128), 0, st,
-                       b->n_lrows, 2 * DIM, b->n_s, b->lrow_id, b->lcol, b->lcol0, w, c, ld, nrhs,
-                       co);
-    CPM_LAUNCH_CHECK();
+    CPM_FAIL(CPM_E_INVALID, "this band has no transposed FD pull lists");
   }
   // e = E^T c
   hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(ld * nrhs, 256, 4096)), dim3(256), 0, st, e, ld * nrhs, T(0));
@@ -1130,11 +1075,7 @@ static void apply_T_dim(const cpm_band* b, double m, double n, int nrhs, const T
       CPM_LAUNCH_CHECK();
     }
   } else if (b->n_erows) {
-    const int nm = DIM == 3 ? 64 : 16;
-    hipLaunchKernelGGL(k_gather_rows_T<T>, dim3(grid_for((int64_t)b->n_erows * nm, 256)),
-                       dim3(256), 0, st, b->n_erows, nm, b->erow_id, b->ecol, ew_of<T>(b), c, e,
-                       ld, nrhs);
-    CPM_LAUNCH_CHECK();
+    CPM_FAIL(CPM_E_INVALID, "this band has no transposed interpolation pull lists");
   }
   const T cd = (T)(m + n * (-2.0 * DIM * N2));
   const int64_t total = ld * nrhs;

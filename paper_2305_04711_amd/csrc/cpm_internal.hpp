@@ -157,7 +157,7 @@ struct cpm_band {
   int* lcol0 = nullptr;               // [n_lrows][2 dim] before swaps (PDE rows)
 
   // pull lists of the transposed explicit rows (single bands; a batch's
-  // composite has none and scatters with atomics): target DOFs, segment
+  // composite has none: batches apply only the forward operator): target DOFs, segment
   // starts and sources in ascending order per target.  E: per entry the DOF
   // of its row and its weight (et_src, et_w, et_w32; sources i * 4^d + o,
   // entry o of explicit E row i, in ascending order).  L: source 2 i + s,
