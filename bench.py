@@ -40,8 +40,8 @@ BYTES_PER_ROW_F32 = 24.0   # tile gather: fraction 12 + base 4 + u 4 + a 4 (FP32
 # profiles/gather_torus512_pmc.md), each scaled by the same counter's reading
 # for a plain device copy of known size.  They hold only for the kernel
 # source they were taken on: `traffic` is null when its hash differs.
-GATHER_PMC = {"sources_sha1": "d0a7c17a4b7d8a2d72b22e851aa50b0a10204459",
-              "fetch_bytes": 1.49375e+09, "write_bytes": 2.96434e+08}
+GATHER_PMC = {"sources_sha1": "b1c8cb90e7a9f14f5b26e931871ddf54e1f24d66",
+              "fetch_bytes": 1.49399e+09, "write_bytes": 2.96511e+08}
 def gather_sources_sha1():
     """Hash of what sets the FP64 tile gather's traffic: its own source (the
     k_gather templates, the row and cube helpers they call, the Lagrange
