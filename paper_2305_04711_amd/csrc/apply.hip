@@ -45,19 +45,6 @@ __device__ __forceinline__ int xcd_remap(int b, int g) {
   return x * q + (x < r ? x : r) + k;
 }
 
-template <int DIM>
-__device__ __forceinline__ int nbr_dof(const BlockView& B, int blk, int mx, int my, int mz) {
-  using G = Geo<DIM>;
-  const int dx = mx >> G::SH, dy = my >> G::SH, dz = DIM == 3 ? (mz >> G::SH) : 0;
-  int b = blk;
-  if (dx | dy | dz) b = B.nbr[blk * G::NNBR + G::code(dx, dy, dz)];
-  if (b < 0) return -1;
-  const int s = G::slot(mx & (G::BX - 1), my & (G::BX - 1), DIM == 3 ? (mz & (G::BX - 1)) : 0);
-  const unsigned long long m = B.mask[b];
-  if (!((m >> s) & 1ull)) return -1;
-  return B.off[b] + __popcll(m & ((1ull << s) - 1ull));
-}
-
 struct TileView {
   const int* tile_inst;   // batched composite: instance of each tile (else null)
   const int* skip;        // batched composite: instances to skip (else null)
