@@ -14,7 +14,8 @@
  *    grouped by interior boundary in the order given, each group in the
  *    order of its nodes' PDE DOFs.
  *  - System (Sec. 5.4): A = m I + n [diag(L) + (L - diag L) E], with E the
- *    closest-point extension by tensor-product cubic Lagrange interpolation
+ *    closest-point extension by tensor-product cubic (or quadratic, Sec. 7)
+ *    Lagrange interpolation
  *    (eq. interp-stencil) with interior-boundary swaps (eq.
  *    stencil-crossing-test, eq. FD-crossing-test) and L the 2d+1-point
  *    Laplacian (eq. FD-stencil).  The affine Dirichlet part of E is moved to
@@ -181,8 +182,10 @@ cpm_status cpm_apply(const cpm_band* band, double m, double n, int dtype,
                      int nrhs, const void* u, void* v, void* hip_stream);
 
 /* z = A^T w = m w + n diag(L) w + n E^T ((L - diag L)^T w): the transpose of
- * cpm_apply (derived from Sec. 5.4).  The E^T product scatters with atomics,
- * so the FP rounding order varies from call to call. */
+ * cpm_apply (derived from Sec. 5.4).  Every sum has a fixed order (per-tile
+ * LDS cubes added class by class; explicit rows through pull lists), so the
+ * result is the same bit for bit on every call.  Arguments as for
+ * cpm_apply; CPM_E_INVALID also for a band without a transpose schedule. */
 cpm_status cpm_apply_transpose(const cpm_band* band, double m, double n,
                                int dtype, int nrhs, const void* w, void* z,
                                void* hip_stream);
