@@ -241,6 +241,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
+    ap.add_argument("--no-heat", action="store_true", help="skip the heat-equation run")
     ap.add_argument("--no-quadratic", action="store_true",
                     help="skip the quadratic-interpolation (p = 2) and stencil-set bands")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -392,7 +393,7 @@ def main():
         batch_out = run_batch(dev, args)
 
     heat_out = None
-    if not args.no_solve:
+    if not args.no_solve and not args.no_heat:
         heat_out = run_heat(dev)
 
     if args.calibrate_copy:
