@@ -249,8 +249,9 @@ def main():
                          "traffic for scaling the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(the band would shard by surface patch, with halo exchanges per apply)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
