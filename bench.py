@@ -397,13 +397,24 @@ def main():
     if not args.no_solve and not args.no_heat:
         heat_out = run_heat(dev)
 
-    if args.calibrate_copy:
-        src = torch.ones(2 ** 27, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    # a plain 1 GiB device copy (1 GiB read + 1 GiB written per copy): the
+    # bandwidth a streaming kernel reaches on this device, beside the 8 TB/s
+    # peak; with --calibrate-copy the counter runs also see its dispatches
+    src = torch.ones(2 ** 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3 if args.calibrate_copy else 1):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_ms = e0.elapsed_time(e1) / 10
+    copy_gbs = 2.0 * src.numel() * 8 / (copy_ms * 1e-3) / 1e9
+    del src, dst
+    log("1 GiB device copy: %.3f ms, %.0f GB/s" % (copy_ms, copy_gbs))
     base = None if args.no_cpu else cpu_baseline()
     out = {
         "metric": "Gnodes/s of CPM apply (% HBM peak) + time-to-1e-8 solve, mixed vs FP64",
@@ -426,6 +437,8 @@ def main():
                      "frac": ach64 / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_row": BYTES_PER_ROW_F64, "rows_per_launch": tile_rows,
                      "launch_ms": ph64[0]},
+        "copy_ceiling": {"gbs": copy_gbs, "ms": copy_ms, "bytes_per_copy": 2 * 2 ** 30,
+                         "gather_frac_of_copy": ach64 / copy_gbs},
         "cpu_baseline": base,
         "apply_f32": {"gnodes_per_s": band.n / dt32 / 1e9, "ms": dt32 * 1e3,
                       "gather_gbs": ach32, "gather_frac": ach32 / HBM_PEAK_GBS},
