@@ -476,8 +476,9 @@ struct Bicg {
       try {
         for (int i = 0; i < k; ++i) iteration(x);
       } catch (...) {
-        hipGraph_t dummy;
-        (void)hipStreamEndCapture(st, &dummy);
+        // end the capture and drop what it recorded before passing the error on
+        hipGraph_t part = nullptr;
+        if (hipStreamEndCapture(st, &part) == hipSuccess && part) (void)hipGraphDestroy(part);
         throw;
       }
       CPM_HIP(hipStreamEndCapture(st, &g));
