@@ -165,9 +165,24 @@ def _check_vec(band, t, length):
         raise ValueError("vectors must be on the GPU (no CPU path)")
     if not t.is_contiguous():
         raise ValueError("vectors must be contiguous")
+    if t.dim() not in (1, 2):
+        raise ValueError("vectors are 1-D (n,) or 2-D (nrhs, n)")
     if t.shape[-1] != length:
         raise ValueError("last dimension must be %d (got %d)" % (length, t.shape[-1]))
     return 1 if t.dim() == 1 else t.shape[0]
+
+
+def _check_f64(t, what):
+    if t.dtype != torch.float64:
+        raise TypeError("%s must be float64" % what)
+
+
+def _check_like(x0, b):
+    """A warm start has the right-hand sides' shape, dtype and device."""
+    if (not x0.is_cuda or x0.dtype != b.dtype or tuple(x0.shape) != tuple(b.shape)
+            or x0.device != b.device):
+        raise ValueError("x0 must be a %s device tensor of shape %s"
+                         % (b.dtype, tuple(b.shape)))
 
 
 def apply(band, u, m, n):
@@ -226,11 +241,17 @@ def apply_transpose(band, w, m, n):
 def rhs(band, f, g, n):
     """b = P f - n (L - diag L) e(g); f (.., n_s), g (.., n_c) float64."""
     nrhs = _check_vec(band, f, band.n_s)
+    _check_f64(f, "f")
     shape = (band.n,) if f.dim() == 1 else (nrhs, band.n)
     b = torch.empty(shape, dtype=torch.float64, device=f.device)
     gp = None
     if band.n_c:
+        if g is None:
+            raise ValueError("g is required when the band has BC DOFs")
         _check_vec(band, g, band.n_c)
+        _check_f64(g, "g")
+        if tuple(g.shape[:-1]) != tuple(f.shape[:-1]):
+            raise ValueError("g must hold one row per right-hand side of f")
         gp = _ptr(g)
     capi.check(band._lib.cpm_rhs(band.handle, float(n), nrhs, _ptr(f), gp, _ptr(b), _stream()))
     return b
@@ -238,6 +259,7 @@ def rhs(band, f, g, n):
 
 def rhs_adjoint(band, lam, n):
     nrhs = _check_vec(band, lam, band.n)
+    _check_f64(lam, "lambda")
     lead = () if lam.dim() == 1 else (nrhs,)
     gf = torch.empty(lead + (band.n_s,), dtype=torch.float64, device=lam.device)
     gg = torch.zeros(lead + (band.n_c,), dtype=torch.float64, device=lam.device)
@@ -257,6 +279,8 @@ def _solve(fn, band, b, m, n, tol, mode, x0, maxit, inner_tol, check_every, use_
     nrhs = _check_vec(band, b, band.n)
     if b.dtype != torch.float64:
         raise TypeError("right-hand sides are float64")
+    if x0 is not None:
+        _check_like(x0, b)
     x = torch.zeros_like(b) if x0 is None else x0.clone().contiguous()
     st = capi.SolveStats()
     o = _opts(m, n, tol, mode, maxit, inner_tol, check_every, use_graph, gauge, restart)
@@ -401,6 +425,8 @@ class Batch:
         self._check(b)
         if b.dtype != torch.float64:
             raise TypeError("right-hand sides are float64")
+        if x0 is not None:
+            _check_like(x0, b)
         x = torch.zeros_like(b) if x0 is None else x0.clone().contiguous()
         ns = self.nrhs * len(self.bands)
         st = (capi.SolveStats * ns)()

@@ -87,6 +87,40 @@ def test_vector_arguments_are_checked():
     assert float(v.abs().max()) == 0.0
 
 
+def test_binding_checks_arguments_before_the_library_reads_them():
+    """Shapes and dtypes the kernels would read past (a float32 vector read as
+    double, fewer rows of g than of f, a warm start of another shape) are
+    refused by the binding before any call into the library."""
+    import torch
+    from paper_2305_04711_amd import cpm
+    band = cpm.Band(cpm.sphere(), [cpm.latitude_ibc(0.3)], 16)
+    dev = "cuda"
+    f = torch.zeros(2, band.n_s, dtype=torch.float64, device=dev)
+    g = torch.zeros(2, band.n_c, dtype=torch.float64, device=dev)
+    with pytest.raises(TypeError):
+        cpm.rhs(band, f.float(), g, -1.0)
+    with pytest.raises(TypeError):
+        cpm.rhs(band, f, g.float(), -1.0)
+    with pytest.raises(ValueError):
+        cpm.rhs(band, f, g[0].contiguous(), -1.0)
+    with pytest.raises(ValueError):
+        cpm.rhs(band, f, None, -1.0)
+    with pytest.raises(TypeError):
+        cpm.rhs_adjoint(band, torch.zeros(band.n, dtype=torch.float32, device=dev), -1.0)
+    with pytest.raises(ValueError):
+        cpm.apply(band, torch.zeros(1, 2, band.n, dtype=torch.float64, device=dev), 0.0, -1.0)
+    b = torch.ones(band.n, dtype=torch.float64, device=dev)
+    for x0 in (torch.zeros(band.n + 1, dtype=torch.float64, device=dev),
+               torch.zeros(band.n, dtype=torch.float32, device=dev),
+               torch.zeros(1, band.n, dtype=torch.float64, device=dev)):
+        with pytest.raises(ValueError):
+            cpm.solve(band, b, 0.0, -1.0, x0=x0)
+    # the same calls with matching arguments go through
+    assert cpm.rhs(band, f, g, -1.0).shape == (2, band.n)
+    x, st = cpm.solve(band, b, 1.0, -1.0, tol=1e-8, mode="f64", x0=torch.zeros_like(b))
+    assert st["converged"]
+
+
 @pytest.mark.parametrize("mode", ["f64", "mixed"])
 def test_solve_edge_cases(mode):
     """A zero right-hand side returns x = 0 at once; a maxit too small for the

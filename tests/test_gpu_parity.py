@@ -154,6 +154,42 @@ def test_apply_transpose_matches_oracle(torch_cuda, cfg, N):
         assert err < tol, (td, err)
 
 
+@pytest.mark.parametrize("cfg,N", [("circle_point", 32), ("sphere_lat", 16), ("torus_meridians", 16)])
+def test_many_right_hand_sides_match_oracle(torch_cuda, cfg, N):
+    """More right-hand sides than one gather launch takes (4): 6 = 4 + 2
+    forward and 5 transposed, FP64 and FP32, and cpm_rhs / cpm_rhs_adjoint
+    with 5; each against the oracle one right-hand side at a time."""
+    torch = torch_cuda
+    from paper_2305_04711_amd import cpm
+    sysm, band, g2o = _pair(cfg, N)
+    rng = np.random.default_rng(15)
+    U = rng.standard_normal((6, sysm.n))
+    ref = np.stack([sysm.apply(U[r], 0.7, -1.3) for r in range(6)])
+    refT = np.stack([AD.apply_transpose(sysm, U[r], 0.5, -1.0) for r in range(5)])
+    for td, tol in ((torch.float64, 1e-13), (torch.float32, 2e-6)):
+        u = torch.tensor(U[:, g2o], dtype=td, device="cuda").contiguous()
+        v = cpm.apply(band, u, 0.7, -1.3).cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(v - ref[:, g2o])) / np.max(np.abs(ref)) < tol, td
+        z = cpm.apply_transpose(band, u[:5].contiguous(), 0.5, -1.0).cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(z - refT[:, g2o])) / np.max(np.abs(refT)) < tol, td
+    F = rng.standard_normal((5, sysm.n_s))
+    Gv = rng.standard_normal((5, sysm.n_c))
+    refb = np.stack([sysm.rhs(F[r], Gv[r], -1.0) for r in range(5)])
+    f = torch.tensor(F[:, g2o[:band.n_s]], device="cuda").contiguous()
+    g = torch.tensor(Gv[:, g2o[band.n_s:] - sysm.n_s], device="cuda").contiguous()
+    b = cpm.rhs(band, f, g if band.n_c else None, -1.0).cpu().numpy()
+    assert np.max(np.abs(b - refb[:, g2o])) <= 1e-12 * np.max(np.abs(refb))
+    L = rng.standard_normal((5, sysm.n))
+    gf, gg = cpm.rhs_adjoint(band, torch.tensor(L[:, g2o], device="cuda").contiguous(), -1.0)
+    for r in range(5):
+        gf_o, gg_o = AD.rhs_gradients(sysm, L[r], -1.0)
+        assert np.max(np.abs(gf[r].cpu().numpy() - gf_o[g2o[:band.n_s]])) <= \
+            1e-12 * np.max(np.abs(gf_o))
+        if band.n_c:
+            assert np.max(np.abs(gg[r].cpu().numpy() - gg_o[g2o[band.n_s:] - sysm.n_s])) <= \
+                1e-12 * np.max(np.abs(gg_o))
+
+
 @pytest.mark.parametrize("cfg,N", [c for c in CASES if c[0] != "sphere" and c[0] != "torus"])
 def test_rhs_and_rhs_adjoint_match_oracle(torch_cuda, cfg, N):
     torch = torch_cuda
