@@ -372,9 +372,16 @@ class Batch:
     offsets[i]:offsets[i+1]."""
 
     def __init__(self, bands, m, n, nrhs=1):
+        self.handle = None
+        bands, m, n = list(bands), list(m), list(n)
+        if not bands or len(m) != len(bands) or len(n) != len(bands):
+            raise ValueError("one (m, n) pair per band (got %d bands, %d m, %d n)"
+                             % (len(bands), len(m), len(n)))
+        if int(nrhs) < 1:
+            raise ValueError("nrhs must be >= 1")
         lib = capi.load()
         self._lib = lib
-        self.bands = list(bands)          # keep the bands alive
+        self.bands = bands                # keep the bands alive
         k = len(self.bands)
         arr = (C.c_void_p * k)(*[b.handle.value for b in self.bands])
         mm = (C.c_double * k)(*[float(x) for x in m])

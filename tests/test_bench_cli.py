@@ -20,3 +20,15 @@ def test_band_kind_is_checked_before_any_device_call():
     from paper_2305_04711_amd import cpm
     with pytest.raises(ValueError):
         cpm.Band(cpm.sphere(), [], 16, band="narrow")
+
+
+def test_batch_needs_one_coefficient_pair_per_band():
+    # ctypes would zero-fill a short coefficient list; the binding refuses it
+    # before it touches the library or the bands
+    from paper_2305_04711_amd import cpm
+    for bands, m, n, nrhs in (([object(), object()], [1.0], [-1.0, -1.0], 1),
+                              ([object(), object()], [1.0, 1.0], [-1.0], 1),
+                              ([], [], [], 1),
+                              ([object()], [1.0], [-1.0], 0)):
+        with pytest.raises(ValueError):
+            cpm.Batch(bands, m, n, nrhs)
