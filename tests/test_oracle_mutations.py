@@ -37,6 +37,32 @@ def pin_cubic_exactness(p=3):
     return worst < 1e-12, worst
 
 
+def pin_quadratic_exactness():
+    """The p = 2 variant of the exactness pin (per-axis degree <= 2)."""
+    return pin_cubic_exactness(p=2)
+
+
+def pin_stencil_set_surface():
+    """The stencil-set band keeps the surface values E u of the tube system
+    with the same f and g (circle with a point IBC, N = 32; sphere with a
+    latitude IBC, N = 12: the smallest sphere grid here on which a BC DOF's
+    node is kept only for the BC DOF's sake)."""
+    worst = 0.0
+    for S, Cs, N in ((G.Circle(), [G.PointC((1.0, 0.0), (0.0, 1.0))], 32),
+                     (G.Sphere(), [G.LatitudeC(G.Sphere(), 0.3)], 12)):
+        T = O.CPMSystem(S, N, Cs)
+        Q = O.CPMSystem(S, N, Cs, band="stencil_set")
+        rng = np.random.default_rng(5)
+        fT, gT = rng.standard_normal(T.n_s), rng.standard_normal(T.n_c)
+        iT = T.index(Q.K)
+        gQ = np.array([gT[T.alpha_of[c][iT[j]] - T.n_s] for c, j in zip(Q.bc_curve, Q.bc_node)])
+        xT = spl.spsolve(T.matrix(0.0, -1.0).tocsc(), T.rhs(fT, gT, -1.0))
+        xQ = spl.spsolve(Q.matrix(0.0, -1.0).tocsc(), Q.rhs(fT[iT], gQ, -1.0))
+        sT = T.surface_values(xT, gT)[iT]
+        worst = max(worst, np.max(np.abs(sT - Q.surface_values(xQ, gQ))) / np.max(np.abs(sT)))
+    return worst < 1e-10, worst
+
+
 def pin_laplacian_quadratics():
     """The 7-point Laplacian is exact on quadratics at nodes whose six face
     neighbours are band nodes (sphere, N = 12)."""
@@ -274,6 +300,45 @@ def _swapped_axes(orig):
     return f
 
 
+def _quadratic_floor_base(orig):
+    # p = 2 stencils placed by floor (the cubic rule) instead of the nearest node
+    def f(Y, N, dim, p=3):
+        if p != 2:
+            return orig(Y, N, dim, p)
+        S = Y * float(N)
+        F = np.floor(S)
+        Wax = [O.lagrange_weights_1d((S - F)[:, a], 2) for a in range(dim)]
+        if dim == 2:
+            W = (Wax[1][:, :, None] * Wax[0][:, None, :]).reshape(-1, 9)
+        else:
+            W = (Wax[2][:, :, None, None] * Wax[1][:, None, :, None]
+                 * Wax[0][:, None, None, :]).reshape(-1, 27)
+        return F.astype(np.int64) - 1, W
+    return f
+
+
+def _stencil_set_without_fd(orig):
+    # keeps the interpolation columns and their BC nodes, not their rows' FD neighbours
+    def f(tube):
+        used = np.zeros(tube.n, dtype=bool)
+        used[tube.E.tocsr().indices] = True
+        keep = used[:tube.n_s].copy()
+        keep[tube.bc_node[used[tube.n_s:]]] = True
+        return keep
+    return f
+
+
+def _stencil_set_without_bc_nodes(orig):
+    # keeps the columns and FD neighbours, but not the nodes of the BC DOFs among them
+    def f(tube):
+        used = np.zeros(tube.n, dtype=bool)
+        used[tube.E.tocsr().indices] = True
+        need = used.copy()
+        need[tube.L_off.tocsr()[np.nonzero(used)[0]].indices] = True
+        return need[:tube.n_s].copy()
+    return f
+
+
 def _neighbour_sign_slip(orig):
     # the last face neighbour (+ along the last axis) taken with the wrong sign
     def f(dim):
@@ -398,6 +463,12 @@ MUTANTS = [
     ("sphere cp about the origin", G.Sphere, "cp", _cp_about_origin, pin_closest_point_sphere),
     ("backward Euler for Crank-Nicolson", TS, "heat_cn", _backward_euler, pin_time_second_order),
     ("BiCGSTAB direction without omega v", KR, "bicgstab", _bicgstab_stale_omega, pin_krylov_vs_lu),
+    ("quadratic weights reversed", O, "lagrange_weights_1d", _reversed_weights, pin_quadratic_exactness),
+    ("quadratic base by floor", O, "stencil", _quadratic_floor_base, pin_band_has_no_holes),
+    ("stencil set without FD neighbours", O, "stencil_set_nodes", _stencil_set_without_fd,
+     pin_stencil_set_surface),
+    ("stencil set without BC-DOF nodes", O, "stencil_set_nodes", _stencil_set_without_bc_nodes,
+     pin_stencil_set_surface),
 ]
 
 PINS = sorted({m[4] for m in MUTANTS}, key=lambda f: f.__name__)
