@@ -23,8 +23,9 @@
  *  - Multi-RHS vectors are stored right-hand side by right-hand side:
  *    element (j, i) of an nrhs x len array is at [j * len + i].
  *  - Device pointers are HIP device memory of the current device; the caller
- *    owns every vector passed in.  A band owns its internal arrays and frees
- *    them in cpm_band_free.
+ *    owns every vector passed in.  A band owns its internal arrays and
+ *    scratch vectors, taken from the cpm_allocator given to cpm_build_band,
+ *    and frees them in cpm_band_free.
  *  - Every call that takes hip_stream enqueues its work on that stream
  *    (NULL = the null stream).  cpm_apply, cpm_apply_transpose, cpm_rhs and
  *    cpm_rhs_adjoint return without synchronising; cpm_build_band, the solves
@@ -123,6 +124,28 @@ enum { CPM_BAND_TUBE = 0, CPM_BAND_STENCIL_SET = 1 };
 
 typedef struct cpm_band cpm_band;
 
+/* Device memory provider.  The paper's solver (Sec. 5.4) holds the band's
+ * stencil data and the Krylov vectors in memory it allocates itself; here
+ * the caller can own that memory instead (for example a framework's caching
+ * allocator, so that one pool serves the caller's tensors and the band).
+ *   alloc(bytes, hip_stream, ctx): device memory of at least `bytes` bytes on
+ *     the current device, usable in stream order on hip_stream, or NULL on
+ *     failure (the call then returns CPM_E_OOM).
+ *   free(ptr, bytes, hip_stream, ctx): return a block alloc gave, with the
+ *     size it was asked for.
+ * Both get the stream given when the band (or batch) was created.  The
+ * library synchronises that stream after each alloc, before it uses the
+ * block on other streams, and synchronises the device before it frees a
+ * block that kernels may have used (a scratch vector that grows, and
+ * everything at cpm_band_free / cpm_batch_free).  The callbacks are called
+ * from the thread making the library call and must not call back into the
+ * library.  The struct is copied; ctx must outlive the band. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* hip_stream, void* ctx);
+  void (*free)(void* ptr, size_t bytes, void* hip_stream, void* ctx);
+  void* ctx;
+} cpm_allocator;
+
 typedef struct {
   int dim, N, n_ibc, order;
   int64_t n_s, n_c, n;          /* PDE, BC and total DOFs                     */
@@ -132,7 +155,9 @@ typedef struct {
   int64_t on_c_nodes;           /* nodes whose cp_S lies within tau of C      */
   int64_t no_bc_dof_swaps;      /* opposite-side members with no BC DOF       */
   double h, r_band, tau;
-  size_t device_bytes;          /* bytes the band holds on the device         */
+  size_t device_bytes;          /* bytes of the band's arrays on the device   */
+  size_t scratch_bytes;         /* bytes of its scratch vectors at this time
+                                   (grown by applies and solves)             */
 } cpm_band_info;
 
 /* Build the band Omega(S) (eq. bandwidth, Alg. 1 semantics: every node within
@@ -140,12 +165,16 @@ typedef struct {
  * boundary (Sec. 4.1, 4.2, 4.6), the interpolation and FD stencils with their
  * swaps and the BC-DOF rows (Sec. 4.3).  Membership and stencil decisions are
  * taken in FP64 in a fixed evaluation order.
- *   ibcs may be NULL when n_ibc == 0.  On success *out owns device memory.
- *   Errors: CPM_E_INVALID (N <= 0, p != 3, unknown kind, IBC kind that does
- *   not fit the surface), CPM_E_REACH, CPM_E_STENCIL_HOLE (message gives the
- *   count), CPM_E_OVERLAP, CPM_E_OOM, CPM_E_HIP. */
+ *   ibcs may be NULL when n_ibc == 0.  allocator: every device allocation of
+ *   the band goes through it (its arrays, the build's temporaries, and the
+ *   scratch vectors later calls grow on demand); NULL = hipMalloc / hipFree.
+ *   On success *out owns that memory until cpm_band_free.
+ *   Errors: CPM_E_INVALID (N <= 0, p not 2 or 3, unknown kind, IBC kind that
+ *   does not fit the surface), CPM_E_REACH, CPM_E_STENCIL_HOLE (message gives
+ *   the count), CPM_E_OVERLAP, CPM_E_OOM, CPM_E_HIP. */
 cpm_status cpm_build_band(const cpm_surface* surface, const cpm_ibc* ibcs,
-                          int n_ibc, const cpm_grid* grid, void* hip_stream,
+                          int n_ibc, const cpm_grid* grid,
+                          const cpm_allocator* allocator, void* hip_stream,
                           cpm_band** out);
 
 void cpm_band_free(cpm_band* band);
@@ -176,16 +205,23 @@ enum { CPM_F64 = 0, CPM_F32 = 1 };
 
 /* v = A u for the linear part of A (Sec. 5.4, four-step product: a = E u,
  * b = (L - diag L) a, then v = m u + n diag(L) u + n b), nrhs right-hand
- * sides.  dtype CPM_F64: u, v are double; CPM_F32: float with FP32 weights.
- * u and v are device arrays [nrhs][n] and must not alias. */
+ * sides.  dtype CPM_F64: u, v are double; CPM_F32: u, v are float and the
+ * stored interpolation fractions are read in FP32, but weights, products,
+ * sums and the intermediate a are FP64 for both dtypes (the Laplacian
+ * differences neighbouring values of a and scales them by 1/h^2, which would
+ * amplify an FP32 rounding of a by 1/h^2); the result is rounded to the
+ * dtype once.  u and v are device arrays [nrhs][n] and must not alias.
+ * Scratch: an FP64 vector of n * nrhs held by the band (allocated on first
+ * use and reused). */
 cpm_status cpm_apply(const cpm_band* band, double m, double n, int dtype,
                      int nrhs, const void* u, void* v, void* hip_stream);
 
 /* z = A^T w = m w + n diag(L) w + n E^T ((L - diag L)^T w): the transpose of
  * cpm_apply (derived from Sec. 5.4).  Every sum has a fixed order (per-tile
  * LDS cubes added class by class; explicit rows through pull lists), so the
- * result is the same bit for bit on every call.  Arguments as for
- * cpm_apply; CPM_E_INVALID also for a band without a transpose schedule. */
+ * result is the same bit for bit on every call.  Arguments and precision as
+ * for cpm_apply (FP64 intermediates (L - diag L)^T w and E^T of it for both
+ * dtypes); CPM_E_INVALID also for a band without a transpose schedule. */
 cpm_status cpm_apply_transpose(const cpm_band* band, double m, double n,
                                int dtype, int nrhs, const void* w, void* z,
                                void* hip_stream);
@@ -205,7 +241,9 @@ cpm_status cpm_rhs_adjoint(const cpm_band* band, double n, int nrhs,
                            const double* lambda, double* grad_f,
                            double* grad_g, void* hip_stream);
 
-enum { CPM_SOLVE_MIXED = 0,  /* FP32 BiCGSTAB with FP64 reliable updates  */
+enum { CPM_SOLVE_MIXED = 0,  /* FP32 BiCGSTAB (FP32 vectors, the CPM_F32
+                                apply, FP64 partial solution) with FP64
+                                reliable updates                          */
        CPM_SOLVE_F64 = 1,    /* plain FP64 BiCGSTAB                        */
        CPM_SOLVE_GMRES = 2 };/* FP64 restarted GMRES(restart), classical
                                 Gram-Schmidt with one re-orthogonalisation  */
@@ -280,10 +318,13 @@ cpm_status cpm_apply_profile(const cpm_band* band, double m, double n, int dtype
  * [offsets[i], offsets[i+1]) of a batch vector of length total) so that one
  * launch per kernel applies every instance; band i uses A_i = m[i] I + n[i] M_i.
  * Batch vectors are [nrhs][total].  The bands must stay alive while the batch
- * is used; they must all have the same dimension. */
+ * is used; they must all have the same dimension.  The batch's own device
+ * memory (the composite band, its scratch and the solver's segment tables)
+ * comes from allocator as for cpm_build_band (NULL = hipMalloc / hipFree). */
 typedef struct cpm_batch cpm_batch;
 cpm_status cpm_batch_create(cpm_band* const* bands, int nbands, const double* m,
-                            const double* n, int nrhs, void* hip_stream,
+                            const double* n, int nrhs,
+                            const cpm_allocator* allocator, void* hip_stream,
                             cpm_batch** out);
 void cpm_batch_free(cpm_batch* batch);
 /* offsets: nbands + 1 entries; offsets[nbands] = total */
@@ -291,7 +332,8 @@ cpm_status cpm_batch_offsets(const cpm_batch* batch, int64_t* offsets);
 /* v = A u for every instance and right-hand side (dtype CPM_F64 / CPM_F32) */
 cpm_status cpm_batch_apply(const cpm_batch* batch, int dtype, const void* u,
                            void* v, void* hip_stream);
-/* Autotune the batch's apply as cpm_autotune does for one band. */
+/* Autotune the batch's apply as cpm_autotune does for one band (its timing
+ * vectors are scratch of the batch, kept for later calls). */
 cpm_status cpm_batch_autotune(cpm_batch* batch, int dtype, int reps,
                               void* hip_stream, double* ms, int* best);
 /* Solve every system (instance, right-hand side) with its own BiCGSTAB

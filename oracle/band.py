@@ -17,7 +17,6 @@ Side vector (eq. cpdiff, Sec. 4.2): v_i = cp_S(x_i) - cp_C(x_i), replaced by
 tau * o_C(cp_C(x_i)) when ||v_i|| < tau = 0.1 h^2 (the on-C tie rule).
 """
 
-from collections import deque
 
 import numpy as np
 
@@ -78,35 +77,30 @@ def scan_band(surface, N, p=3, q=1, r=None):
 
 
 def bfs_band(surface, N, k0, p=3, q=1, r=None):
-    """Algorithm 1: breadth-first search from the band node k0 over the 2d face
-    neighbours, computing cp_S only for visited nodes.  Pure-Python loop; only
-    for small grids.  Returns the set of integer coordinate tuples."""
+    """The band as Algorithm 1 defines it: the nodes within r of S that are
+    connected to the seed node k0 through face neighbours, with cp_S
+    evaluated only at nodes the search reaches.  Grown one breadth-first
+    layer at a time: the next layer is every not yet seen face neighbour of
+    the current layer that lies within r.  Only for small grids.  Returns the
+    set of integer coordinate tuples."""
     d = surface.dim
     if r is None:
         r = band_radius(N, d, p, q)
     k0 = tuple(int(v) for v in k0)
-
-    def inside(k):
-        X = node_coords(np.array([k]), N)
-        return _dist(X, surface.cp(X))[0] <= r
-
-    assert inside(k0), "the BFS must start at a band node"
-    band = {k0}
-    visited = {k0}
-    Q = deque([k0])
-    while Q:
-        cur = Q[0]
-        for a in range(d):
-            for s in (-1, 1):
-                nb = list(cur)
-                nb[a] += s
-                nb = tuple(nb)
-                if nb not in visited:
-                    visited.add(nb)
-                    if inside(nb):
-                        band.add(nb)
-                        Q.append(nb)
-        Q.popleft()
+    X0 = node_coords(np.array([k0]), N)
+    assert _dist(X0, surface.cp(X0))[0] <= r, "the search must start at a band node"
+    steps = [tuple(s if a == b else 0 for b in range(d)) for a in range(d) for s in (-1, 1)]
+    band, seen, layer = {k0}, {k0}, [k0]
+    while layer:
+        fresh = sorted({tuple(k[b] + o[b] for b in range(d)) for k in layer for o in steps}
+                       - seen)
+        if not fresh:
+            break
+        seen.update(fresh)
+        X = node_coords(np.array(fresh), N)
+        keep = _dist(X, surface.cp(X)) <= r
+        layer = [k for k, ok in zip(fresh, keep) if ok]
+        band.update(layer)
     return band
 
 

@@ -17,6 +17,14 @@ Values u are supplied through a callback u_of(K, curve) -> array, where K
 holds integer node coordinates and curve is -1 for PDE DOFs and the index of
 the interior boundary for BC DOFs.  This module is test infrastructure; it is
 pinned against ``CPMSystem.apply`` in ``tests/test_oracle_local.py``.
+
+Scope: the full tube (eq. bandwidth), cubic interpolation (p = 3), closed
+interior boundaries (points, closed curves) with Dirichlet conditions of
+order 1 (the BC row's linear part is zero, Sec. 4.3) or 2 (the mirror row of
+eq. cpc-bar).  Anything else - zero-Neumann sides, open arcs (whose end
+nodes have no BC DOF, Sec. 4.4), quadratic interpolation, the stencil-set
+band - is refused with NotImplementedError rather than evaluated with the
+rules above.
 """
 
 import numpy as np
@@ -26,7 +34,19 @@ from .operator import face_offsets, member_offsets, stencil
 
 
 class LocalCPM:
-    def __init__(self, surface, N, curves=(), order=2, tau_factor=0.1, check_factor=2.0):
+    def __init__(self, surface, N, curves=(), order=2, tau_factor=0.1, check_factor=2.0,
+                 bc_types=None, p=3, band="tube"):
+        from .geometry import LatitudeArc
+        if int(order) not in (1, 2):
+            raise NotImplementedError("IBC order %r: only orders 1 and 2 exist (Sec. 4.3)" % order)
+        if p != 3:
+            raise NotImplementedError("the row evaluator models cubic interpolation only")
+        if band != "tube":
+            raise NotImplementedError("the row evaluator models the full tube only")
+        if bc_types is not None and any(t != "dirichlet" for pair in bc_types for t in pair):
+            raise NotImplementedError("the row evaluator models Dirichlet interior boundaries only")
+        if any(isinstance(C, LatitudeArc) for C in curves):
+            raise NotImplementedError("the row evaluator models closed interior boundaries only")
         self.S, self.N, self.dim = surface, int(N), surface.dim
         self.curves = list(curves)
         self.order = int(order)
@@ -85,9 +105,11 @@ class LocalCPM:
         return np.sum(W * vals, axis=1)
 
     def _E_bc(self, K, ci, u_of):
-        """(E u) at the BC DOFs of curve ci at nodes K (linear part)."""
+        """(E u) at the BC DOFs of curve ci at nodes K (linear part): zero for
+        a first-order Dirichlet row (its value is the constant g), minus the
+        mirror-point interpolation for a second-order one."""
         s, d = K.shape
-        if self.order != 2:
+        if self.order == 1:
             return np.zeros(s)
         X, _, _, per = self._props(K)
         CPC, _, V = per[ci]

@@ -49,7 +49,18 @@ class BandInfo(C.Structure):
                 ("n_blocks", C.c_int64), ("n_tiles", C.c_int64), ("n_erows", C.c_int64),
                 ("n_lrows", C.c_int64), ("on_c_nodes", C.c_int64),
                 ("no_bc_dof_swaps", C.c_int64), ("h", C.c_double), ("r_band", C.c_double),
-                ("tau", C.c_double), ("device_bytes", C.c_size_t)]
+                ("tau", C.c_double), ("device_bytes", C.c_size_t),
+                ("scratch_bytes", C.c_size_t)]
+
+
+# cpm_allocator: alloc(bytes, stream, ctx) -> device pointer or NULL;
+# free(ptr, bytes, stream, ctx).  Pointers travel as size_t (uintptr_t).
+ALLOC_FN = C.CFUNCTYPE(C.c_size_t, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_size_t, C.c_size_t, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
 
 
 class SolveOpts(C.Structure):
@@ -92,8 +103,8 @@ def load(path=LIB_PATH):
                            "fallback" % path)
     lib = C.CDLL(path)
     vp, dp, i, d = C.c_void_p, C.POINTER(C.c_double), C.c_int, C.c_double
-    lib.cpm_build_band.argtypes = [C.POINTER(Surface), C.POINTER(IBC), i, C.POINTER(Grid), vp,
-                                   C.POINTER(vp)]
+    lib.cpm_build_band.argtypes = [C.POINTER(Surface), C.POINTER(IBC), i, C.POINTER(Grid),
+                                   C.POINTER(Allocator), vp, C.POINTER(vp)]
     lib.cpm_band_free.argtypes = [vp]
     lib.cpm_band_free.restype = None
     lib.cpm_band_query.argtypes = [vp, C.POINTER(BandInfo)]
@@ -112,7 +123,8 @@ def load(path=LIB_PATH):
     lib.cpm_heat_cn.argtypes = [vp, d, i, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveStats),
                                 vp]
     lib.cpm_batch_create.argtypes = [C.POINTER(vp), i, C.POINTER(C.c_double),
-                                     C.POINTER(C.c_double), i, vp, C.POINTER(vp)]
+                                     C.POINTER(C.c_double), i, C.POINTER(Allocator), vp,
+                                     C.POINTER(vp)]
     lib.cpm_batch_free.argtypes = [vp]
     lib.cpm_batch_free.restype = None
     lib.cpm_batch_offsets.argtypes = [vp, C.POINTER(C.c_int64)]

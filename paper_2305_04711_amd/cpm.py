@@ -8,7 +8,9 @@ runs in libcpm's HIP kernels.  Vectors are torch tensors on the current HIP
 device, shaped (n,) or (nrhs, n).
 """
 
+import atexit
 import ctypes as C
+import weakref
 
 import numpy as np
 import torch
@@ -22,6 +24,51 @@ def _stream():
 
 def _ptr(t):
     return C.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------------ memory
+# The torch caching allocator as the library's cpm_allocator: the band's
+# arrays and scratch vectors come from the same pool as the caller's tensors
+# (torch.cuda.memory_allocated counts them).  The callbacks run on the thread
+# that calls into the library, which holds no GIL during the call; ctypes
+# takes the GIL for them.
+def _torch_alloc(nbytes, stream, ctx):
+    try:
+        return int(torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0)))
+    except Exception:   # out of memory: the library reports CPM_E_OOM
+        return 0
+
+
+def _torch_free(ptr, nbytes, stream, ctx):
+    try:
+        torch.cuda.caching_allocator_delete(int(ptr))
+    except Exception:
+        pass
+
+
+_TORCH_ALLOCATOR = capi.Allocator(capi.ALLOC_FN(_torch_alloc), capi.FREE_FN(_torch_free), None)
+
+# Bands and batches still open at interpreter exit are freed while the
+# callbacks above (and torch) are still alive.
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for obj in list(_LIVE):
+        try:
+            obj.close()
+        except Exception:
+            pass
+
+
+def _allocator(kind):
+    """kind "torch" (default): the torch caching allocator; None: hipMalloc."""
+    if kind == "torch":
+        return C.byref(_TORCH_ALLOCATOR)
+    if kind is None:
+        return None
+    raise ValueError("allocator is 'torch' or None")
 
 
 # ------------------------------------------------------------------ geometry
@@ -80,7 +127,7 @@ class Band:
     "stencil_set" (only the nodes interpolation and FD stencils need)."""
 
     def __init__(self, surface, ibcs=(), N=64, order=2, r_band=0.0, tau_factor=0.0,
-                 check_factor=0.0, check_reach=False, p=3, band="tube"):
+                 check_factor=0.0, check_reach=False, p=3, band="tube", allocator="torch"):
         kinds = {"tube": capi.BAND_TUBE, "stencil_set": capi.BAND_STENCIL_SET}
         if band not in kinds:
             raise ValueError("band is 'tube' or 'stencil_set'")
@@ -92,8 +139,9 @@ class Band:
                          float(tau_factor), float(check_factor), kinds[band])
         out = C.c_void_p()
         capi.check(lib.cpm_build_band(C.byref(surface), arr, len(ibcs), C.byref(grid),
-                                      _stream(), C.byref(out)))
+                                      _allocator(allocator), _stream(), C.byref(out)))
         self.handle = out
+        _LIVE.add(self)
         info = capi.BandInfo()
         capi.check(lib.cpm_band_query(self.handle, C.byref(info)))
         self.info = {k: getattr(info, k) for k, _ in capi.BandInfo._fields_}
@@ -105,6 +153,12 @@ class Band:
         if self.handle is not None and self.handle.value:
             self._lib.cpm_band_free(self.handle)
         self.handle = None
+
+    def memory(self):
+        """(array bytes, scratch bytes) the band holds on the device now."""
+        info = capi.BandInfo()
+        capi.check(self._lib.cpm_band_query(self.handle, C.byref(info)))
+        return info.device_bytes, info.scratch_bytes
 
     def __del__(self):
         try:
@@ -335,23 +389,32 @@ def solve_adjoint(band, rhs_, m, n, tol=1e-8, mode="mixed", x0=None, maxit=0, in
 
 
 def _check_attained(stats, tol, what):
-    # BiCGSTAB in FP64 stagnates near relres 1e-11 on these systems; a solve
-    # that ends within 100 x tol is accepted, anything worse raises.
-    if not (stats["relres"] <= 100.0 * tol):
-        raise capi.CPMError(capi.E_NOCONV, "%s reached relative residual %.3g (tol %.3g)"
-                            % (what, stats["relres"], tol))
+    """Raise unless the solve reached its tolerance.  In FP64 the true
+    residual of an iterate cannot be driven (or even measured) below about
+    eps64 ||A|| ||x|| / ||b||, eps64 kappa for smooth solutions (a few 1e-11
+    at h = 1/128 on the test surfaces): tolerances near that floor fail here
+    rather than being accepted silently."""
+    if not (stats["relres"] <= tol):
+        raise capi.CPMError(capi.E_NOCONV, "%s reached relative residual %.3g, above tol %.3g "
+                            "(%d iterations)" % (what, stats["relres"], tol,
+                                                 stats["krylov_iters"]))
 
 
 class CPMSolve(torch.autograd.Function):
     """u = A^-1 b(f, g) with gradients with respect to f (n_s) and the interior
-    Dirichlet values g (n_c) from the adjoint solve A^T lam = dl/du."""
+    Dirichlet values g (n_c) from the adjoint solve A^T lam = dl/du.  Both
+    solves must reach tol (CPMError otherwise).  stats (optional dict)
+    receives the solver statistics under "forward" and, after backward,
+    "backward"."""
 
     @staticmethod
-    def forward(ctx, f, g, band, m, n, tol=1e-10, mode="mixed"):
+    def forward(ctx, f, g, band, m, n, tol=1e-10, mode="mixed", stats=None):
         b = rhs(band, f.detach().contiguous(), g.detach().contiguous() if band.n_c else None, n)
         u, st = solve(band, b, m, n, tol=tol, mode=mode, raise_noconv=False)
+        if stats is not None:
+            stats["forward"] = st
         _check_attained(st, tol, "forward solve")
-        ctx.band, ctx.m, ctx.n, ctx.tol, ctx.mode = band, m, n, tol, mode
+        ctx.band, ctx.m, ctx.n, ctx.tol, ctx.mode, ctx.stats = band, m, n, tol, mode, stats
         return u
 
     @staticmethod
@@ -359,9 +422,11 @@ class CPMSolve(torch.autograd.Function):
         band = ctx.band
         lam, st = solve_adjoint(band, grad_u.contiguous().to(torch.float64), ctx.m, ctx.n,
                                 tol=ctx.tol, mode=ctx.mode, raise_noconv=False)
+        if ctx.stats is not None:
+            ctx.stats["backward"] = st
         _check_attained(st, ctx.tol, "adjoint solve")
         gf, gg = rhs_adjoint(band, lam, ctx.n)
-        return gf, (gg if band.n_c else None), None, None, None, None, None
+        return gf, (gg if band.n_c else None), None, None, None, None, None, None
 
 
 # ------------------------------------------------------------------ batches
@@ -371,7 +436,7 @@ class Batch:
     Batch vectors are (nrhs, total); instance i occupies columns
     offsets[i]:offsets[i+1]."""
 
-    def __init__(self, bands, m, n, nrhs=1):
+    def __init__(self, bands, m, n, nrhs=1, allocator="torch"):
         self.handle = None
         bands, m, n = list(bands), list(m), list(n)
         if not bands or len(m) != len(bands) or len(n) != len(bands):
@@ -387,8 +452,10 @@ class Batch:
         mm = (C.c_double * k)(*[float(x) for x in m])
         nn = (C.c_double * k)(*[float(x) for x in n])
         out = C.c_void_p()
-        capi.check(lib.cpm_batch_create(arr, k, mm, nn, int(nrhs), _stream(), C.byref(out)))
+        capi.check(lib.cpm_batch_create(arr, k, mm, nn, int(nrhs), _allocator(allocator),
+                                        _stream(), C.byref(out)))
         self.handle = out
+        _LIVE.add(self)
         self.nrhs = int(nrhs)
         offs = (C.c_int64 * (k + 1))()
         capi.check(lib.cpm_batch_offsets(self.handle, offs))

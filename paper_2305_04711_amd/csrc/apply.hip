@@ -69,65 +69,95 @@ template <int DIM> struct Cube {
   static constexpr int SIZE = DIM == 3 ? E * E * E : E * E;
 };
 
-// Per-row stencil base (local to the tile block) and fraction.
-template <class T, int DIM>
-__device__ __forceinline__ void row_stencil(const TileView& tv, int pos, int N, int lb[3], T t[3]);
+// Per-row stencil base (local to the tile block) and fraction.  The fraction
+// is stored in the vector precision TS (FP64 or FP32) and returned in FP64:
+// the weights are always evaluated in FP64, so they sum to one to FP64
+// rounding whatever precision the fraction was stored in.
+template <class TS>
+__device__ __forceinline__ const TS* frac_of(const TileView& tv);
+template <>
+__device__ __forceinline__ const double* frac_of<double>(const TileView& tv) { return tv.frac64; }
+template <>
+__device__ __forceinline__ const float* frac_of<float>(const TileView& tv) { return tv.frac32; }
 
-template <>
-__device__ __forceinline__ void row_stencil<double, 3>(const TileView& tv, int pos, int, int lb[3],
-                                                        double t[3]) {
+template <class TS, int DIM>
+__device__ __forceinline__ void row_stencil(const TileView& tv, int pos, int lb[3], double t[3]) {
   const unsigned p = tv.lbase[pos];
+  const TS* fr = frac_of<TS>(tv);
   lb[0] = p & 0xff;
   lb[1] = (p >> 8) & 0xff;
-  lb[2] = (p >> 16) & 0xff;
-  for (int a = 0; a < 3; ++a) t[a] = tv.frac64[(int64_t)a * tv.ntr + pos];
-}
-template <>
-__device__ __forceinline__ void row_stencil<double, 2>(const TileView& tv, int pos, int, int lb[3],
-                                                        double t[3]) {
-  const unsigned p = tv.lbase[pos];
-  lb[0] = p & 0xff;
-  lb[1] = (p >> 8) & 0xff;
-  lb[2] = 0;
-  for (int a = 0; a < 2; ++a) t[a] = tv.frac64[(int64_t)a * tv.ntr + pos];
-  t[2] = 0.0;
-}
-template <>
-__device__ __forceinline__ void row_stencil<float, 3>(const TileView& tv, int pos, int, int lb[3],
-                                                       float t[3]) {
-  const unsigned p = tv.lbase[pos];
-  lb[0] = p & 0xff;
-  lb[1] = (p >> 8) & 0xff;
-  lb[2] = (p >> 16) & 0xff;
-  for (int a = 0; a < 3; ++a) t[a] = tv.frac32[(int64_t)a * tv.ntr + pos];
-}
-template <>
-__device__ __forceinline__ void row_stencil<float, 2>(const TileView& tv, int pos, int, int lb[3],
-                                                       float t[3]) {
-  const unsigned p = tv.lbase[pos];
-  lb[0] = p & 0xff;
-  lb[1] = (p >> 8) & 0xff;
-  lb[2] = 0;
-  for (int a = 0; a < 2; ++a) t[a] = tv.frac32[(int64_t)a * tv.ntr + pos];
-  t[2] = 0.0f;
+  lb[2] = DIM == 3 ? (p >> 16) & 0xff : 0;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) t[a] = (double)fr[(int64_t)a * tv.ntr + pos];
+  if (DIM == 2) t[2] = 0.0;
 }
 
 // ---------------------------------------------------------------- pass 1
+// Interpolation of one row from the staged cube (sum-factorised tensor
+// product): x lines first, then y, then z.  FP64 arithmetic.
+template <int DIM, int NR, int CSZ, int E, int EP>
+__device__ __forceinline__ void interp_row(const double (&s_u)[NR][CSZ], int p, const int lb[3],
+                                           const double tt[3], double acc[NR]) {
+  double wx[4], wy[4], wz[4];
+  lagrange_p<double>(p, tt[0], wx);
+  lagrange_p<double>(p, tt[1], wy);
+  if (DIM == 3) lagrange_p<double>(p, tt[2], wz);
+  const int lx = lb[0], ly = lb[1], lz = lb[2];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+  if (DIM == 3) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      double accz[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) accz[r] = 0.0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int base = ((lz + c) * E + (ly + b)) * EP + lx;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const double* row = &s_u[r][base];
+          const double x = wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2] + wx[3] * row[3];
+          accz[r] += wy[b] * x;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[r] += wz[c] * accz[r];
+    }
+  } else {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int base = (ly + b) * EP + lx;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const double* row = &s_u[r][base];
+        const double x = wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2] + wx[3] * row[3];
+        acc[r] += wy[b] * x;
+      }
+    }
+  }
+}
+
 // One wavefront per tile: stage the (2 BX)^d cube of u into LDS (x lines
 // padded by PAD elements to spread LDS banks), then each lane interpolates
-// rows of the tile (sum-factorised tensor product).  The staged blocks' masks
-// and first DOFs come from the tile's metadata in one load.
-// At most 6 waves per SIMD keeps the FP64 variant's register use in check
-// (left to itself the compiler hoists every LDS read of a row and the
-// occupancy drops to 4 waves per SIMD, about 1.5x slower).
-template <class T, int DIM, int NR, int PAD>
+// rows of the tile.  The staged blocks' masks and first DOFs come from the
+// tile's metadata in one load.  u is stored in TS (FP64 or FP32) and staged
+// in FP64; weights, products and sums are FP64 and a is written in FP64 for
+// both storage precisions: the Laplacian pass differences neighbouring
+// values of a and scales the difference by N^2, so a rounding of a to FP32
+// would be amplified by N^2 (on the smooth modes that converge last, a
+// relative error of order eps32 ||A|| / lambda_min in A u).
+// At most 6 waves per SIMD keeps the register use in check (left to itself
+// the compiler hoists every LDS read of a row and the occupancy drops to 4
+// waves per SIMD, about 1.5x slower).
+template <class TS, int DIM, int NR, int PAD>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void k_gather(
-    BlockView B, TileView tv, int N, const T* __restrict__ u, T* __restrict__ a, int64_t ld,
+    BlockView B, TileView tv, int N, const TS* __restrict__ u, double* __restrict__ a, int64_t ld,
     int xcd) {
   using G = Geo<DIM>;
   constexpr int E = Cube<DIM>::E, EP = E + PAD, NQ = 1 << DIM;
   constexpr int CS = DIM == 3 ? E * E * EP : E * EP;
-  __shared__ T s_u[NR][CS];
+  __shared__ double s_u[NR][CS];
   const int t = xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
   const int lane = threadIdx.x;
   if (tv.skip && tv.skip[tv.tile_inst[t]]) return;   // converged batch instance
@@ -143,8 +173,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void k_
   // every pass requests the next pass's before interpolating
   const int beg = tv.tile_start[t], end = tv.tile_start[t + 1];
   int lb[3] = {0, 0, 0};
-  T tt[3] = {T(0), T(0), T(0)};
-  if (beg + lane < end) row_stencil<T, DIM>(tv, beg + lane, N, lb, tt);
+  double tt[3] = {0.0, 0.0, 0.0};
+  if (beg + lane < end) row_stencil<TS, DIM>(tv, beg + lane, lb, tt);
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const unsigned long long m = lane_u64(qm, q);
@@ -155,51 +185,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void k_
     const bool on = (m >> lane) & 1ull;
     const int dof = off + __popcll(m & ((1ull << lane) - 1ull));
 #pragma unroll
-    for (int r = 0; r < NR; ++r) s_u[r][ci] = on ? u[r * ld + dof] : T(0);
+    for (int r = 0; r < NR; ++r) s_u[r][ci] = on ? (double)u[r * ld + dof] : 0.0;
   }
   __syncthreads();
   for (int pos = beg + lane; pos < end; pos += 64) {
-    T wx[4], wy[4], wz[4];
-    lagrange_p<T>(tv.p, tt[0], wx);
-    lagrange_p<T>(tv.p, tt[1], wy);
-    if (DIM == 3) lagrange_p<T>(tv.p, tt[2], wz);
-    const int lx = lb[0], ly = lb[1], lz = lb[2];
+    const int lbc[3] = {lb[0], lb[1], lb[2]};
+    const double tc[3] = {tt[0], tt[1], tt[2]};
     const int dof = tv.perm[pos];
-    if (pos + 64 < end) row_stencil<T, DIM>(tv, pos + 64, N, lb, tt);
-    T acc[NR];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) acc[r] = T(0);
-    if (DIM == 3) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        T accz[NR];
-#pragma unroll
-        for (int r = 0; r < NR; ++r) accz[r] = T(0);
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int base = ((lz + c) * E + (ly + b)) * EP + lx;
-#pragma unroll
-          for (int r = 0; r < NR; ++r) {
-            const T* row = &s_u[r][base];
-            const T x = wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2] + wx[3] * row[3];
-            accz[r] += wy[b] * x;
-          }
-        }
-#pragma unroll
-        for (int r = 0; r < NR; ++r) acc[r] += wz[c] * accz[r];
-      }
-    } else {
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int base = (ly + b) * EP + lx;
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          const T* row = &s_u[r][base];
-          const T x = wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2] + wx[3] * row[3];
-          acc[r] += wy[b] * x;
-        }
-      }
-    }
+    if (pos + 64 < end) row_stencil<TS, DIM>(tv, pos + 64, lb, tt);
+    double acc[NR];
+    interp_row<DIM, NR, CS, E, EP>(s_u, tv.p, lbc, tc, acc);
 #pragma unroll
     for (int r = 0; r < NR; ++r) a[r * ld + dof] = acc[r];
   }
@@ -210,14 +205,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void k_
 // While a tile's blocks are staged, the wave already requests the next
 // tile's metadata and row range, so a tile costs one dependent round trip to
 // memory instead of two.
-template <class T, int DIM, int NR, int PAD>
+template <class TS, int DIM, int NR, int PAD>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void k_gather_ps(
-    BlockView B, TileView tv, int N, const T* __restrict__ u, T* __restrict__ a, int64_t ld,
+    BlockView B, TileView tv, int N, const TS* __restrict__ u, double* __restrict__ a, int64_t ld,
     int ntiles) {
   using G = Geo<DIM>;
   constexpr int E = Cube<DIM>::E, EP = E + PAD, NQ = 1 << DIM;
   constexpr int CS = DIM == 3 ? E * E * EP : E * EP;
-  __shared__ T s_u[NR][CS];
+  __shared__ double s_u[NR][CS];
   const int lane = threadIdx.x;
   const int x = blockIdx.x & 7, wk = blockIdx.x >> 3, W = gridDim.x >> 3;
   const int q8 = ntiles >> 3, r8 = ntiles & 7;
@@ -237,9 +232,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void k_
     const int tn = t + W;
     const bool more = tn < hi;
     int lb[3] = {0, 0, 0};
-    T tt[3] = {T(0), T(0), T(0)};
-    if (beg + lane < end) row_stencil<T, DIM>(tv, beg + lane, N, lb, tt);
-    T sv[NQ][NR];
+    double tt[3] = {0.0, 0.0, 0.0};
+    if (beg + lane < end) row_stencil<TS, DIM>(tv, beg + lane, lb, tt);
+    TS sv[NQ][NR];
     int sci[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -251,7 +246,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void k_
       const bool on = (m >> lane) & 1ull;
       const int dof = off + __popcll(m & ((1ull << lane) - 1ull));
 #pragma unroll
-      for (int r = 0; r < NR; ++r) sv[q][r] = on ? u[r * ld + dof] : T(0);
+      for (int r = 0; r < NR; ++r) sv[q][r] = on ? u[r * ld + dof] : TS(0);
     }
     unsigned long long qm_n = 0ull;
     int qoff_n = 0, beg_n = 0, end_n = 0;
@@ -268,50 +263,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void k_
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
 #pragma unroll
-      for (int r = 0; r < NR; ++r) s_u[r][sci[q]] = sv[q][r];
+      for (int r = 0; r < NR; ++r) s_u[r][sci[q]] = (double)sv[q][r];
     __syncthreads();
     for (int pos = beg + lane; pos < end; pos += 64) {
-      T wx[4], wy[4], wz[4];
-      lagrange_p<T>(tv.p, tt[0], wx);
-      lagrange_p<T>(tv.p, tt[1], wy);
-      if (DIM == 3) lagrange_p<T>(tv.p, tt[2], wz);
-      const int lx = lb[0], ly = lb[1], lz = lb[2];
+      const int lbc[3] = {lb[0], lb[1], lb[2]};
+      const double tc[3] = {tt[0], tt[1], tt[2]};
       const int dof = tv.perm[pos];
-      if (pos + 64 < end) row_stencil<T, DIM>(tv, pos + 64, N, lb, tt);
-      T acc[NR];
-#pragma unroll
-      for (int r = 0; r < NR; ++r) acc[r] = T(0);
-      if (DIM == 3) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          T accz[NR];
-#pragma unroll
-          for (int r = 0; r < NR; ++r) accz[r] = T(0);
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            const int base = ((lz + c) * E + (ly + b)) * EP + lx;
-#pragma unroll
-            for (int r = 0; r < NR; ++r) {
-              const T* row = &s_u[r][base];
-              const T xv = wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2] + wx[3] * row[3];
-              accz[r] += wy[b] * xv;
-            }
-          }
-#pragma unroll
-          for (int r = 0; r < NR; ++r) acc[r] += wz[c] * accz[r];
-        }
-      } else {
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int base = (ly + b) * EP + lx;
-#pragma unroll
-          for (int r = 0; r < NR; ++r) {
-            const T* row = &s_u[r][base];
-            const T xv = wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2] + wx[3] * row[3];
-            acc[r] += wy[b] * xv;
-          }
-        }
-      }
+      if (pos + 64 < end) row_stencil<TS, DIM>(tv, pos + 64, lb, tt);
+      double acc[NR];
+      interp_row<DIM, NR, CS, E, EP>(s_u, tv.p, lbc, tc, acc);
 #pragma unroll
       for (int r = 0; r < NR; ++r) a[r * ld + dof] = acc[r];
     }
@@ -346,11 +306,14 @@ __device__ __forceinline__ void wave_dot2(double d0, double d1, double* part, in
 
 // Explicit interpolation rows: a[id] = sum_o w_o u[col_o]; nm lanes per row
 // (nm = 4^d: a wavefront in 3-D, a quarter wavefront in 2-D), lane = member.
-template <class T>
+// FP64 weights for both storage precisions (the interior-boundary rows keep
+// their FP64 closest-point weights), FP64 sums into the FP64 a.
+template <class TS>
 __global__ __launch_bounds__(256) void k_gather_rows(int nrows, int nm, const int* __restrict__ row_id,
                                                      const int* __restrict__ col,
-                                                     const T* __restrict__ w, const T* __restrict__ u,
-                                                     T* __restrict__ a, int64_t ld, int nrhs,
+                                                     const double* __restrict__ w,
+                                                     const TS* __restrict__ u,
+                                                     double* __restrict__ a, int64_t ld, int nrhs,
                                                      const int* __restrict__ row_inst,
                                                      const int* __restrict__ skip) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -358,9 +321,9 @@ __global__ __launch_bounds__(256) void k_gather_rows(int nrows, int nm, const in
   const int o = (int)(g % nm);
   const bool live = i < nrows && !(skip && skip[row_inst[i]]);
   const int c = live ? col[i * nm + o] : -1;
-  const T wt = live ? w[i * nm + o] : T(0);
+  const double wt = live ? w[i * nm + o] : 0.0;
   for (int r = 0; r < nrhs; ++r) {
-    T v = c >= 0 ? wt * u[r * ld + c] : T(0);
+    double v = c >= 0 ? wt * (double)u[r * ld + c] : 0.0;
     v = wave_sum(v, nm);
     if (live && o == 0) a[r * ld + row_id[i]] = v;
   }
@@ -372,18 +335,17 @@ __global__ __launch_bounds__(256) void k_gather_rows(int nrows, int nm, const in
 // 8j..8j+7 load block j's metadata (its own and its face neighbours' masks
 // and first DOFs, and the explicit-row mask), broadcast with readlane, so each
 // lane finds its neighbours' DOFs by arithmetic.  ALL = false skips rows with
-// explicit FD stencils; ALL = true (transpose) visits every PDE row.
+// explicit FD stencils and reads u for the diagonal term; ALL = true
+// (transpose) visits every PDE row and writes co sum_nbr a only.  TU, TA, TV
+// are the storage types of u, a and v; the arithmetic is FP64.
 constexpr int kLapBlocksPerWave = 2;
 
-template <class T, int DIM, bool ALL, bool DOT = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_lap(BlockView B, const T* __restrict__ u,
-                                             const T* __restrict__ a, T* __restrict__ v,
-                                             int64_t ld, int nrhs, T cd, T co,
-                                             const double* __restrict__ gsum, double gscale,
-                                             int xcd, const double* __restrict__ coef,
-                                             const int* __restrict__ skip,
-                                             const T* __restrict__ dy = nullptr,
-                                             double* __restrict__ dpart = nullptr, int dnp = 0) {
+template <class TU, class TA, class TV, int DIM, bool ALL, bool DOT = false>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_lap(
+    BlockView B, const TU* __restrict__ u, const TA* __restrict__ a, TV* __restrict__ v,
+    int64_t ld, int nrhs, double cd, double co, const double* __restrict__ gsum, double gscale,
+    int xcd, const double* __restrict__ coef, const int* __restrict__ skip,
+    const TV* __restrict__ dy = nullptr, double* __restrict__ dpart = nullptr, int dnp = 0) {
   using G = Geo<DIM>;
   constexpr int KB = kLapBlocksPerWave;
   const int wg = xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
@@ -403,7 +365,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     }
   }
   // batched systems: per-instance (cd, co), instance id in entry 7's pad
-  T cdj[KB], coj[KB];
+  double cdj[KB], coj[KB];
   bool skipj[KB];
 #pragma unroll
   for (int j = 0; j < KB; ++j) {
@@ -413,8 +375,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     if (coef) {
       const int inst = lane_i32(lpad, 8 * j + 7);
       const int ii = inst > 0 ? inst : 0;
-      cdj[j] = (T)coef[2 * ii];
-      coj[j] = (T)coef[2 * ii + 1];
+      cdj[j] = coef[2 * ii];
+      coj[j] = coef[2 * ii + 1];
       skipj[j] = skip && skip[ii];
     }
   }
@@ -446,77 +408,80 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   if constexpr (DOT) {
     // the solver's fused dot products: one right-hand side; y is requested
     // together with u so that it adds no round trip to memory
-    T uv[KB], yv[KB], s[KB];
+    double uv[KB], yv[KB], s[KB];
 #pragma unroll
     for (int j = 0; j < KB; ++j) {
-      uv[j] = dof[j] >= 0 ? u[dof[j]] : T(0);
-      yv[j] = dof[j] >= 0 ? dy[dof[j]] : T(0);
-      s[j] = T(0);
+      uv[j] = dof[j] >= 0 ? (double)u[dof[j]] : 0.0;
+      yv[j] = dof[j] >= 0 ? (double)dy[dof[j]] : 0.0;
+      s[j] = 0.0;
 #pragma unroll
       for (int f = 0; f < 2 * DIM; ++f)
-        if (dof[j] >= 0 && nd[j][f] >= 0) s[j] += a[nd[j][f]];
+        if (dof[j] >= 0 && nd[j][f] >= 0) s[j] += (double)a[nd[j][f]];
     }
     double d0 = 0.0, d1 = 0.0;
 #pragma unroll
     for (int j = 0; j < KB; ++j) {
       if (dof[j] < 0) continue;
-      T o = cdj[j] * uv[j] + coj[j] * s[j];
-      if (gsum) o += (T)(gscale * gsum[0]);
-      v[dof[j]] = o;
-      d0 += (double)yv[j] * (double)o;
-      d1 += (double)o * (double)o;
+      double o = cdj[j] * uv[j] + coj[j] * s[j];
+      if (gsum) o += gscale * gsum[0];
+      const TV ov = (TV)o;
+      v[dof[j]] = ov;
+      d0 += yv[j] * (double)ov;
+      d1 += (double)ov * (double)ov;
     }
     wave_dot2(d0, d1, dpart, dnp, blockIdx.x * 4);
     return;
   }
   for (int r = 0; r < nrhs; ++r) {
-    T out[KB];
+    double out[KB];
 #pragma unroll
     for (int j = 0; j < KB; ++j) {
-      T s = T(0);
+      double s = 0.0;
 #pragma unroll
       for (int f = 0; f < 2 * DIM; ++f)
-        if (dof[j] >= 0 && nd[j][f] >= 0) s += a[r * ld + nd[j][f]];
-      out[j] = dof[j] >= 0 ? cdj[j] * u[r * ld + dof[j]] + coj[j] * s : T(0);
+        if (dof[j] >= 0 && nd[j][f] >= 0) s += (double)a[r * ld + nd[j][f]];
+      if constexpr (ALL) out[j] = coj[j] * s;
+      else out[j] = dof[j] >= 0 ? cdj[j] * (double)u[r * ld + dof[j]] + coj[j] * s : 0.0;
     }
 #pragma unroll
     for (int j = 0; j < KB; ++j) {
       if (dof[j] < 0) continue;
-      T o = out[j];
-      if (gsum) o += (T)(gscale * gsum[r]);
-      v[r * ld + dof[j]] = o;
+      double o = out[j];
+      if (gsum) o += gscale * gsum[r];
+      v[r * ld + dof[j]] = (TV)o;
     }
   }
 }
 
-template <class T, bool DOT = false>
+template <class TS, bool DOT = false>
 __global__ void k_lap_rows(int nrows, int nf, const int* __restrict__ row_id,
-                           const int* __restrict__ col, const T* __restrict__ u,
-                           const T* __restrict__ a, T* __restrict__ v, int64_t ld, int nrhs,
-                           T cd, T co, const double* __restrict__ gsum, double gscale,
+                           const int* __restrict__ col, const TS* __restrict__ u,
+                           const double* __restrict__ a, TS* __restrict__ v, int64_t ld, int nrhs,
+                           double cd, double co, const double* __restrict__ gsum, double gscale,
                            const double* __restrict__ coef, const int* __restrict__ row_inst,
-                           const int* __restrict__ skip, const T* __restrict__ dy = nullptr,
+                           const int* __restrict__ skip, const TS* __restrict__ dy = nullptr,
                            double* __restrict__ dpart = nullptr, int dnp = 0, int doff = 0) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double d0 = 0.0, d1 = 0.0;
   if (i < nrows && !(coef && skip && skip[row_inst[i]])) {
     const int id = row_id[i];
     if (coef) {
-      cd = (T)coef[2 * row_inst[i]];
-      co = (T)coef[2 * row_inst[i] + 1];
+      cd = coef[2 * row_inst[i]];
+      co = coef[2 * row_inst[i] + 1];
     }
     for (int r = 0; r < nrhs; ++r) {
-      T s = T(0);
+      double s = 0.0;
       for (int f = 0; f < nf; ++f) {
         const int c = col[i * nf + f];
         if (c >= 0) s += a[r * ld + c];
       }
-      T out = cd * u[r * ld + id] + co * s;
-      if (gsum) out += (T)(gscale * gsum[r]);
-      v[r * ld + id] = out;
+      double out = cd * (double)u[r * ld + id] + co * s;
+      if (gsum) out += gscale * gsum[r];
+      const TS ov = (TS)out;
+      v[r * ld + id] = ov;
       if (DOT && r == 0) {
-        d0 = (double)dy[id] * (double)out;
-        d1 = (double)out * (double)out;
+        d0 = (double)dy[id] * (double)ov;
+        d1 = (double)ov * (double)ov;
       }
     }
   }
@@ -590,10 +555,11 @@ __device__ __forceinline__ T horner3(const T c[4], T t) {
   return ((c[0] * t + c[1]) * t + c[2]) * t + c[3];
 }
 
-template <class T, int DIM>
+template <class TS, int DIM>
 __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const int* __restrict__ list,
-                                                 int N, const T* __restrict__ c, T* __restrict__ z,
-                                                 int64_t ld, int r, int xcd) {
+                                                 int N, const double* __restrict__ c,
+                                                 double* __restrict__ z, int64_t ld, int r,
+                                                 int xcd) {
   using G = Geo<DIM>;
   constexpr int E = Cube<DIM>::E, EP = E + 1, NQ = 1 << DIM;
   constexpr int CS = DIM == 3 ? E * E * EP : E * EP;
@@ -601,7 +567,7 @@ __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const
   constexpr int RPI = 64 / M;                 // rows per wave instruction
   constexpr int NW = DIM == 3 ? 12 : 8;       // 1-D weights per row
   __shared__ double s_z[CS];
-  __shared__ T s_w[DIM == 3 ? 4 : NW][64];                   // per-row 1-D weights, component major
+  __shared__ double s_w[DIM == 3 ? 4 : NW][64];   // per-row 1-D weights, component major
   __shared__ int s_b[64];                     // per-row cube offset of member 0
   const int t = list[xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x];
   const int lane = threadIdx.x;
@@ -619,42 +585,42 @@ __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const
   // loads overlap the row work (no other wave of this launch writes them)
   const int cx0 = G::lx(lane), cy0 = G::ly(lane), cz0 = G::lz(lane);
   int zi[NQ];
-  T old[NQ];
+  double old[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const unsigned long long m = lane_u64(qm, q);
     const int off = lane_i32(qoff, q);
     zi[q] = ((m >> lane) & 1ull) ? off + __popcll(m & ((1ull << lane) - 1ull)) : -1;
-    old[q] = zi[q] >= 0 ? z[r * ld + zi[q]] : T(0);
+    old[q] = zi[q] >= 0 ? z[r * ld + zi[q]] : 0.0;
   }
   // this lane's stencil member and row slot within an instruction
   const int mo = lane & (M - 1), sub = lane / M;
   const int ma = mo & 3, mb = (mo >> 2) & 3, mc = DIM == 3 ? (mo >> 4) : 0;
   const int moff = DIM == 3 ? (mc * E + mb) * EP + ma : mb * EP + ma;
-  T ca[4], cb[4], cc[4];
-  member_poly<T>(tv.p, ma, ca);
-  member_poly<T>(tv.p, mb, cb);
-  member_poly<T>(tv.p, mc, cc);
+  double ca[4], cb[4], cc[4];
+  member_poly<double>(tv.p, ma, ca);
+  member_poly<double>(tv.p, mb, cb);
+  member_poly<double>(tv.p, mc, cc);
   for (int p0 = beg; p0 < end; p0 += 64) {
-    T tq[3] = {T(0), T(0), T(0)}, cq = T(0);
+    double tq[3] = {0.0, 0.0, 0.0}, cq = 0.0;
     const int nrow = min(64, end - p0);
-    T wx[4] = {T(0), T(0), T(0), T(0)}, wy[4] = {T(0), T(0), T(0), T(0)};
-    T wz[4] = {T(0), T(0), T(0), T(0)};
+    double wx[4] = {0.0, 0.0, 0.0, 0.0}, wy[4] = {0.0, 0.0, 0.0, 0.0};
+    double wz[4] = {0.0, 0.0, 0.0, 0.0};
     int bs = 0;
     if (lane < nrow) {
       const int pos = p0 + lane;
-      const T ci = c[r * ld + tv.perm[pos]];
+      const double ci = c[r * ld + tv.perm[pos]];
       int lb[3];
-      T tt[3];
-      row_stencil<T, DIM>(tv, pos, N, lb, tt);
+      double tt[3];
+      row_stencil<TS, DIM>(tv, pos, lb, tt);
       tq[0] = tt[0];
       tq[1] = tt[1];
       tq[2] = tt[2];
       cq = ci;
-      lagrange_p<T>(tv.p, tt[0], wx);
-      lagrange_p<T>(tv.p, tt[1], wy);
+      lagrange_p<double>(tv.p, tt[0], wx);
+      lagrange_p<double>(tv.p, tt[1], wy);
       if (DIM == 3) {
-        lagrange_p<T>(tv.p, tt[2], wz);
+        lagrange_p<double>(tv.p, tt[2], wz);
 #pragma unroll
         for (int k = 0; k < 4; ++k) wz[k] *= ci;
       } else {
@@ -692,8 +658,8 @@ __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           bq[u] = __builtin_amdgcn_readfirstlane(s_b[j + u]);
-          wq[u] = (double)(horner3<T>(ca, s_w[0][j + u]) * horner3<T>(cb, s_w[1][j + u]) *
-                           horner3<T>(cc, s_w[2][j + u]) * s_w[3][j + u]);
+          wq[u] = horner3<double>(ca, s_w[0][j + u]) * horner3<double>(cb, s_w[1][j + u]) *
+                  horner3<double>(cc, s_w[2][j + u]) * s_w[3][j + u];
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -716,7 +682,7 @@ __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const
 #pragma unroll
         for (int u = 0; u < UR; ++u) {
           const int j = j0 + u * RPI + sub;
-          v[u] = (double)(s_w[ma][j] * s_w[4 + mb][j]);
+          v[u] = s_w[ma][j] * s_w[4 + mb][j];
           o[u] = s_b[j] + moff;
         }
 #pragma unroll
@@ -730,45 +696,37 @@ __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const
     const int qx = q & 1, qy = (q >> 1) & 1, qz = DIM == 3 ? (q >> 2) : 0;
     const int cx = qx * G::BX + cx0, cy = qy * G::BX + cy0, cz = qz * G::BX + cz0;
     const int ci = DIM == 3 ? (cz * E + cy) * EP + cx : cy * EP + cx;
-    if (zi[q] >= 0) z[r * ld + zi[q]] = old[q] + (T)s_z[ci];
+    if (zi[q] >= 0) z[r * ld + zi[q]] = old[q] + s_z[ci];
   }
 }
 
 // E^T c over the explicit rows by pull lists, in two balanced passes: every
-// entry's product w c_i (FP64), then one thread per target DOF sums its
-// contiguous segment in ascending source order and adds it to z once: the
-// same value on every run, with no atomics.
-template <class T>
-__global__ void k_et_prod(int total, const int* __restrict__ row, const T* __restrict__ w,
-                          const T* __restrict__ c, double* __restrict__ prod) {
+// entry's product w c_i (FP64 weights and c), then one thread per target DOF
+// sums its contiguous segment in ascending source order and adds it to z
+// once: the same value on every run, with no atomics.
+__global__ void k_et_prod(int total, const int* __restrict__ row, const double* __restrict__ w,
+                          const double* __restrict__ c, double* __restrict__ prod) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < total) prod[e] = (double)(w[e] * c[row[e]]);
+  if (e < total) prod[e] = w[e] * c[row[e]];
 }
 
-template <class T>
 __global__ void k_et_sum(int n_tgt, const int* __restrict__ tgt, const int* __restrict__ start,
-                         const double* __restrict__ prod, T* __restrict__ z) {
+                         const double* __restrict__ prod, double* __restrict__ z) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n_tgt) return;
   double acc = 0.0;
   for (int e = start[k]; e < start[k + 1]; ++e) acc += prod[e];
-  z[tgt[k]] += (T)acc;
+  z[tgt[k]] += acc;
 }
-
-template <class T>
-static const T* et_w_of(const cpm_band* b);
-template <>
-const double* et_w_of<double>(const cpm_band* b) { return b->et_w; }
-template <>
-const float* et_w_of<float>(const cpm_band* b) { return b->et_w32; }
 
 // The corrections of (L - diag L)^T w for explicit FD rows by pull lists:
 // c[t] += co (sum of +w_i over rows adding to t, -w_i over swapped rows
 // moving their entry away from t), in ascending source order.
-template <class T>
+template <class TS>
 __global__ void k_lt_pull(int n_tgt, const int* __restrict__ tgt, const int* __restrict__ start,
                           const int* __restrict__ src, const int* __restrict__ row_id,
-                          const T* __restrict__ w, T* __restrict__ c, int64_t ld, int nrhs, T co) {
+                          const TS* __restrict__ w, double* __restrict__ c, int64_t ld, int nrhs,
+                          double co) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n_tgt) return;
   const int t = tgt[k], b0 = start[k], b1 = start[k + 1];
@@ -776,10 +734,10 @@ __global__ void k_lt_pull(int n_tgt, const int* __restrict__ tgt, const int* __r
     double acc = 0.0;
     for (int e = b0; e < b1; ++e) {
       const int v = src[e];
-      const double wi = (double)(co * w[r * ld + row_id[v >> 1]]);
+      const double wi = co * (double)w[r * ld + row_id[v >> 1]];
       acc += (v & 1) ? -wi : wi;
     }
-    c[r * ld + t] += (T)acc;
+    c[r * ld + t] += acc;
   }
 }
 
@@ -790,15 +748,17 @@ __global__ void k_fill(T* __restrict__ p, int64_t n, T val) {
     p[i] = val;
 }
 
-template <class T, bool DOT = false>
-__global__ void k_combine(int64_t n, const T* __restrict__ w, const T* __restrict__ z,
-                          T* __restrict__ out, T cd, T nn, int64_t total,
-                          const T* __restrict__ dy = nullptr, double* __restrict__ dpart = nullptr,
+// out = cd w + nn e (FP64 arithmetic, stored in the vector precision TS);
+// with DOT also the partials of (dy, out) and (out, out)
+template <class TS, bool DOT = false>
+__global__ void k_combine(const TS* __restrict__ w, const double* __restrict__ z,
+                          TS* __restrict__ out, double cd, double nn, int64_t total,
+                          const TS* __restrict__ dy = nullptr, double* __restrict__ dpart = nullptr,
                           int dnp = 0) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double d0 = 0.0, d1 = 0.0;
   if (i < total) {
-    const T o = cd * w[i] + nn * z[i];
+    const TS o = (TS)(cd * (double)w[i] + nn * z[i]);
     out[i] = o;
     if (DOT) {
       d0 = (double)dy[i] * (double)o;
@@ -806,7 +766,6 @@ __global__ void k_combine(int64_t n, const T* __restrict__ w, const T* __restric
     }
   }
   if (DOT) wave_dot2(d0, d1, dpart, dnp, blockIdx.x * 4);
-  (void)n;
 }
 
 // ---------------------------------------------------------------- rhs
@@ -873,20 +832,13 @@ __global__ void k_gradg(int nrows, int nf, int64_t n_s, int64_t n_c, int nrhs,
 
 // ================================================================ host
 template <class T>
-static const T* ew_of(const cpm_band* b);
-template <>
-const double* ew_of<double>(const cpm_band* b) { return b->ew; }
-template <>
-const float* ew_of<float>(const cpm_band* b) { return b->ew32; }
-
-template <class T>
 static const Tune& tune_of(const cpm_band* b) {
   return b->tune[sizeof(T) == 8 ? 0 : 1];
 }
 
 template <class T, int DIM, int PAD>
-static void launch_gather_k(const cpm_band* b, int k, const T* ur, T* ar, int64_t ld, int xcd,
-                            bool ps, hipStream_t st) {
+static void launch_gather_k(const cpm_band* b, int k, const T* ur, double* ar, int64_t ld,
+                            int xcd, bool ps, hipStream_t st) {
   const dim3 g(b->ntiles), t(64);
   if (ps && !b->tile_inst) {
     // a multiple of 8 wavefronts: every XCD gets the same number
@@ -912,14 +864,14 @@ static void launch_gather_k(const cpm_band* b, int k, const T* ur, T* ar, int64_
 }
 
 template <class T, int DIM>
-static void launch_gather(const cpm_band* b, int nrhs, const T* u, T* a, hipStream_t st,
+static void launch_gather(const cpm_band* b, int nrhs, const T* u, double* a, hipStream_t st,
                           hipEvent_t* ev = nullptr) {
   const int64_t ld = b->n;
   int r = 0;
   while (r < nrhs) {
     const int k = nrhs - r >= 4 ? 4 : nrhs - r;
     const T* ur = u + r * ld;
-    T* ar = a + r * ld;
+    double* ar = a + r * ld;
     if (b->ntiles) {
       const Tune& tn = tune_of<T>(b);
       if (tn.pad) launch_gather_k<T, DIM, 4>(b, k, ur, ar, ld, tn.xcd, tn.ps != 0, st);
@@ -931,14 +883,13 @@ static void launch_gather(const cpm_band* b, int nrhs, const T* u, T* a, hipStre
   if (b->n_erows) {
     const int nm = DIM == 3 ? 64 : 16;
     hipLaunchKernelGGL(k_gather_rows<T>, dim3(grid_for((int64_t)b->n_erows * nm, 256)), dim3(256),
-                       0, st, b->n_erows, nm, b->erow_id, b->ecol, ew_of<T>(b), u, a, ld, nrhs,
+                       0, st, b->n_erows, nm, b->erow_id, b->ecol, b->ew, u, a, ld, nrhs,
                        b->erow_inst, b->inst_skip);
     CPM_LAUNCH_CHECK();
   }
   if (ev) CPM_HIP(hipEventRecord(ev[2], st));
 }
 
-// ev (optional): five events recorded between the four phases.
 static int lap_groups(const cpm_band* b) {
   return (b->nb + 4 * kLapBlocksPerWave - 1) / (4 * kLapBlocksPerWave);
 }
@@ -953,27 +904,35 @@ int apply_dot_parts(const cpm_band* b, bool transpose) {
   return 4 * lap_groups(b) + 2 * lap_row_groups(b);
 }
 
+// Bytes of scratch one forward apply of nrhs right-hand sides needs: the
+// intermediate a = E u, FP64 for both vector precisions.
+size_t apply_scratch_bytes(const cpm_band* b, int nrhs) {
+  return sizeof(double) * (size_t)b->n * (size_t)nrhs;
+}
+
+// The two passes of the forward apply with a given scratch vector a (at
+// least apply_scratch_bytes).  ev (optional): five events recorded between
+// the four phases.
 template <class T, int DIM>
 static void apply_dim(const cpm_band* b, double m, double n, int nrhs, const T* u, T* v,
-                      hipStream_t st, const double* gsum, double gamma, hipEvent_t* ev = nullptr,
-                      const T* dy = nullptr, double* dpart = nullptr) {
+                      hipStream_t st, const double* gsum, double gamma, double* a,
+                      hipEvent_t* ev = nullptr, const T* dy = nullptr, double* dpart = nullptr) {
   const int64_t ld = b->n;
-  T* a = static_cast<T*>(band_scratch(b, 0, sizeof(T) * (size_t)ld * nrhs));
   if (ev) CPM_HIP(hipEventRecord(ev[0], st));
   launch_gather<T, DIM>(b, nrhs, u, a, st, ev);
   const double N2 = (double)b->N * (double)b->N;
-  const T cd = (T)(m + n * (-2.0 * DIM * N2));
-  const T co = (T)(n * N2);
+  const double cd = m + n * (-2.0 * DIM * N2);
+  const double co = n * N2;
   const double gscale = gsum ? gamma / (double)b->n_s : 0.0;
   const int g1 = lap_groups(b), g2 = lap_row_groups(b), np = 4 * g1 + 2 * g2;
   if (dy)
-    hipLaunchKernelGGL((k_lap<T, DIM, false, true>), dim3(g1), dim3(256), 0, st, bview(b), u, a, v,
-                       ld, nrhs, cd, co, gsum, gscale, tune_of<T>(b).xcd, b->inst_coef,
-                       b->inst_skip, dy, dpart, np);
+    hipLaunchKernelGGL((k_lap<T, double, T, DIM, false, true>), dim3(g1), dim3(256), 0, st,
+                       bview(b), u, a, v, ld, nrhs, cd, co, gsum, gscale, tune_of<T>(b).xcd,
+                       b->inst_coef, b->inst_skip, dy, dpart, np);
   else
-    hipLaunchKernelGGL((k_lap<T, DIM, false>), dim3(g1), dim3(256), 0, st, bview(b), u, a, v, ld,
-                       nrhs, cd, co, gsum, gscale, tune_of<T>(b).xcd, b->inst_coef, b->inst_skip,
-                       nullptr, nullptr, 0);
+    hipLaunchKernelGGL((k_lap<T, double, T, DIM, false>), dim3(g1), dim3(256), 0, st, bview(b),
+                       u, a, v, ld, nrhs, cd, co, gsum, gscale, tune_of<T>(b).xcd, b->inst_coef,
+                       b->inst_skip, nullptr, nullptr, 0);
   CPM_LAUNCH_CHECK();
   if (ev) CPM_HIP(hipEventRecord(ev[3], st));
   if (b->n_lrows) {
@@ -991,6 +950,13 @@ static void apply_dim(const cpm_band* b, double m, double n, int nrhs, const T* 
 }
 
 template <class T>
+void apply_with_scratch(const cpm_band* b, double m, double n, int nrhs, const T* u, T* v,
+                        hipStream_t st, double* a, hipEvent_t* ev) {
+  if (b->dim == 3) apply_dim<T, 3>(b, m, n, nrhs, u, v, st, nullptr, 0.0, a, ev);
+  else apply_dim<T, 2>(b, m, n, nrhs, u, v, st, nullptr, 0.0, a, ev);
+}
+
+template <class T>
 void apply_impl(const cpm_band* b, double m, double n, int nrhs, const T* u, T* v, hipStream_t st,
                 const double* gauge_sum, double gamma, const T* dy, double* dpart) {
   double* gs = nullptr;
@@ -1005,27 +971,32 @@ void apply_impl(const cpm_band* b, double m, double n, int nrhs, const T* u, T* 
     hipLaunchKernelGGL(k_sum_final, dim3(nrhs), dim3(256), 0, st, part, np, gs);
     CPM_LAUNCH_CHECK();
   }
-  if (b->dim == 3) apply_dim<T, 3>(b, m, n, nrhs, u, v, st, gs, gamma, nullptr, dy, dpart);
-  else apply_dim<T, 2>(b, m, n, nrhs, u, v, st, gs, gamma, nullptr, dy, dpart);
+  double* a = static_cast<double*>(band_scratch(b, 0, apply_scratch_bytes(b, nrhs)));
+  if (b->dim == 3) apply_dim<T, 3>(b, m, n, nrhs, u, v, st, gs, gamma, a, nullptr, dy, dpart);
+  else apply_dim<T, 2>(b, m, n, nrhs, u, v, st, gs, gamma, a, nullptr, dy, dpart);
 }
 
+// The transposed apply.  c = (L - diag L)^T w and e = E^T c are FP64 scratch
+// vectors for both storage precisions (the combine step cancels the two
+// terms of size N^2, as the forward Laplacian pass does).
 template <class T, int DIM>
 static void apply_T_dim(const cpm_band* b, double m, double n, int nrhs, const T* w, T* z,
                         hipStream_t st, const T* dy = nullptr, double* dpart = nullptr) {
   const int64_t ld = b->n;
-  T* c = static_cast<T*>(band_scratch(b, 1, sizeof(T) * (size_t)ld * nrhs));
-  T* e = static_cast<T*>(band_scratch(b, 2, sizeof(T) * (size_t)ld * nrhs));
+  double* c = static_cast<double*>(band_scratch(b, 1, sizeof(double) * (size_t)ld * nrhs));
+  double* e = static_cast<double*>(band_scratch(b, 2, sizeof(double) * (size_t)ld * nrhs));
   const double N2 = (double)b->N * (double)b->N;
-  const T co = (T)N2;
+  const double co = N2;
   // c = (L - diag L)^T w: symmetric bulk over every PDE row, then corrections
   // (fill kernels, not memsets: this sequence may be captured into a graph);
   // k_lap<ALL> writes every PDE entry, so only the BC entries need clearing
   if (b->n_c)
     for (int r = 0; r < nrhs; ++r)
-      hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(b->n_c, 256, 4096)), dim3(256), 0, st,
-                         c + r * ld + b->n_s, (int64_t)b->n_c, T(0));
-  hipLaunchKernelGGL((k_lap<T, DIM, true>), dim3((b->nb + 4 * kLapBlocksPerWave - 1) / (4 * kLapBlocksPerWave)), dim3(256), 0, st, bview(b), w,
-                     w, c, ld, nrhs, T(0), co, nullptr, 0.0, tune_of<T>(b).xcd, nullptr, nullptr);
+      hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(b->n_c, 256, 4096)), dim3(256), 0, st,
+                         c + r * ld + b->n_s, (int64_t)b->n_c, 0.0);
+  hipLaunchKernelGGL((k_lap<T, T, double, DIM, true>), dim3(lap_groups(b)), dim3(256), 0, st,
+                     bview(b), w, w, c, ld, nrhs, 0.0, co, nullptr, 0.0, tune_of<T>(b).xcd,
+                     nullptr, nullptr);
   CPM_LAUNCH_CHECK();
   if (b->lt_tgt) {
     if (b->n_lt) {
@@ -1037,7 +1008,8 @@ static void apply_T_dim(const cpm_band* b, double m, double n, int nrhs, const T
     CPM_FAIL(CPM_E_INVALID, "this band has no transposed FD pull lists");
   }
   // e = E^T c
-  hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(ld * nrhs, 256, 4096)), dim3(256), 0, st, e, ld * nrhs, T(0));
+  hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(ld * nrhs, 256, 4096)), dim3(256), 0, st, e,
+                     ld * nrhs, 0.0);
   if (b->ntiles) {
     if (!b->tile_col) CPM_FAIL(CPM_E_INVALID, "this band has no transpose schedule");
     for (int r = 0; r < nrhs; ++r)
@@ -1054,9 +1026,9 @@ static void apply_T_dim(const cpm_band* b, double m, double n, int nrhs, const T
       double* prod = static_cast<double*>(
           band_scratch(b, kEtProdSlot, sizeof(double) * (size_t)b->n_et_entries));
       for (int r = 0; r < nrhs; ++r) {
-        hipLaunchKernelGGL(k_et_prod<T>, dim3(grid_for(b->n_et_entries, 256)), dim3(256), 0, st,
-                           b->n_et_entries, b->et_src, et_w_of<T>(b), c + r * ld, prod);
-        hipLaunchKernelGGL(k_et_sum<T>, dim3(grid_for(b->n_et, 256)), dim3(256), 0, st, b->n_et,
+        hipLaunchKernelGGL(k_et_prod, dim3(grid_for(b->n_et_entries, 256)), dim3(256), 0, st,
+                           b->n_et_entries, b->et_src, b->et_w, c + r * ld, prod);
+        hipLaunchKernelGGL(k_et_sum, dim3(grid_for(b->n_et, 256)), dim3(256), 0, st, b->n_et,
                            b->et_tgt, b->et_start, prod, e + r * ld);
       }
       CPM_LAUNCH_CHECK();
@@ -1064,15 +1036,15 @@ static void apply_T_dim(const cpm_band* b, double m, double n, int nrhs, const T
   } else if (b->n_erows) {
     CPM_FAIL(CPM_E_INVALID, "this band has no transposed interpolation pull lists");
   }
-  const T cd = (T)(m + n * (-2.0 * DIM * N2));
+  const double cd = m + n * (-2.0 * DIM * N2);
   const int64_t total = ld * nrhs;
   const int gc = grid_for(total, 256);
   if (dy) {
     if ((int64_t)gc * 256 < total) CPM_FAIL(CPM_E_INVALID, "internal: fused dot grid too small");
-    hipLaunchKernelGGL((k_combine<T, true>), dim3(gc), dim3(256), 0, st, ld, w, e, z, cd, (T)n,
-                       total, dy, dpart, 4 * gc);
+    hipLaunchKernelGGL((k_combine<T, true>), dim3(gc), dim3(256), 0, st, w, e, z, cd, n, total,
+                       dy, dpart, 4 * gc);
   } else {
-    hipLaunchKernelGGL((k_combine<T>), dim3(gc), dim3(256), 0, st, ld, w, e, z, cd, (T)n, total,
+    hipLaunchKernelGGL((k_combine<T>), dim3(gc), dim3(256), 0, st, w, e, z, cd, n, total,
                        nullptr, nullptr, 0);
   }
   CPM_LAUNCH_CHECK();
@@ -1136,13 +1108,11 @@ extern "C" cpm_status cpm_apply_profile(const cpm_band* b, double m, double n, i
     double acc[4] = {0, 0, 0, 0};
     try {
       for (int k = 0; k < reps; ++k) {
-        if (dtype == CPM_F64) {
-          if (b->dim == 3) apply_dim<double, 3>(b, m, n, nrhs, (const double*)u, (double*)v, st, nullptr, 0.0, ev);
-          else apply_dim<double, 2>(b, m, n, nrhs, (const double*)u, (double*)v, st, nullptr, 0.0, ev);
-        } else {
-          if (b->dim == 3) apply_dim<float, 3>(b, m, n, nrhs, (const float*)u, (float*)v, st, nullptr, 0.0, ev);
-          else apply_dim<float, 2>(b, m, n, nrhs, (const float*)u, (float*)v, st, nullptr, 0.0, ev);
-        }
+        double* a = static_cast<double*>(band_scratch(b, 0, apply_scratch_bytes(b, nrhs)));
+        if (dtype == CPM_F64)
+          apply_with_scratch<double>(b, m, n, nrhs, (const double*)u, (double*)v, st, a, ev);
+        else
+          apply_with_scratch<float>(b, m, n, nrhs, (const float*)u, (float*)v, st, a, ev);
         CPM_HIP(hipEventSynchronize(ev[4]));
         for (int p = 0; p < 4; ++p) {
           float t = 0.f;

@@ -305,9 +305,11 @@ struct cpm_batch {
   int* snch = nullptr;
   std::vector<int> h_csys;
   std::vector<double> m, n;
+  cpm::DevAlloc da;                       // provider of the batch's device memory
+  std::vector<std::pair<void*, size_t>> allocs;
   ~cpm_batch() {
-    for (void* p : {(void*)csys, (void*)clo, (void*)chi, (void*)sfirst, (void*)snch})
-      if (p) (void)hipFree(p);
+    comp.reset();   // the composite band waits for the device if da is the caller's
+    for (auto& pb : allocs) da.put(pb.first, pb.second);
   }
 };
 
@@ -317,15 +319,17 @@ namespace {
 using Clock = std::chrono::steady_clock;
 
 template <class T>
-T* dalloc(size_t n) {
-  void* p = nullptr;
-  CPM_HIP(hipMalloc(&p, (n ? n : 1) * sizeof(T)));
+T* dalloc(cpm_batch* B, size_t n) {
+  const size_t bytes = (n ? n : 1) * sizeof(T);
+  void* p = B->da.get(bytes);
+  B->allocs.push_back({p, bytes});
   return static_cast<T*>(p);
 }
 
 void build_composite(cpm_batch* B, hipStream_t st) {
   const int ni = B->ninst;
   auto c = std::make_unique<cpm_band>();
+  c->da = B->da;
   const cpm_band* b0 = B->bands[0];
   c->dim = b0->dim;
   c->N = b0->N;
@@ -450,11 +454,11 @@ void build_composite(cpm_batch* B, hipStream_t st) {
       snch[s] = (int)csys.size() - sfirst[s];
     }
   B->nchunks = (int)csys.size();
-  B->csys = dalloc<int>(csys.size());
-  B->clo = dalloc<int64_t>(clo.size());
-  B->chi = dalloc<int64_t>(chi.size());
-  B->sfirst = dalloc<int>(B->nsys);
-  B->snch = dalloc<int>(B->nsys);
+  B->csys = dalloc<int>(B, csys.size());
+  B->clo = dalloc<int64_t>(B, clo.size());
+  B->chi = dalloc<int64_t>(B, chi.size());
+  B->sfirst = dalloc<int>(B, B->nsys);
+  B->snch = dalloc<int>(B, B->nsys);
   CPM_HIP(hipMemcpy(B->csys, csys.data(), sizeof(int) * csys.size(), hipMemcpyHostToDevice));
   CPM_HIP(hipMemcpy(B->clo, clo.data(), sizeof(int64_t) * clo.size(), hipMemcpyHostToDevice));
   CPM_HIP(hipMemcpy(B->chi, chi.data(), sizeof(int64_t) * chi.size(), hipMemcpyHostToDevice));
@@ -462,6 +466,9 @@ void build_composite(cpm_batch* B, hipStream_t st) {
   CPM_HIP(hipMemcpy(B->snch, snch.data(), sizeof(int) * B->nsys, hipMemcpyHostToDevice));
   B->h_csys = csys;
 }
+
+// scratch slots of the composite band holding cpm_batch_autotune's vectors
+constexpr int kAutotuneSlot = 90;
 
 Seg seg_of(const cpm_batch* B) { return Seg{B->csys, B->clo, B->chi, B->sfirst, B->snch}; }
 
@@ -501,7 +508,7 @@ struct BBicg {
     S = (BScal*)band_scratch(c, slot0 + 7, sizeof(BScal) * B->nsys);
     act = (int*)band_scratch(c, slot0 + 8, sizeof(int) * B->nsys);
     CPM_HIP(hipMemsetAsync(S, 0, sizeof(BScal) * B->nsys, st));
-    band_scratch(c, 0, sizeof(T) * (size_t)len);
+    band_scratch(c, 0, apply_scratch_bytes(c, B->nrhs));
     set_active(hact);
   }
   ~BBicg() {
@@ -632,12 +639,16 @@ struct BBicg {
 using namespace cpm;
 
 extern "C" cpm_status cpm_batch_create(cpm_band* const* bands, int nbands, const double* m,
-                                       const double* n, int nrhs, void* hip_stream,
-                                       cpm_batch** out) {
+                                       const double* n, int nrhs, const cpm_allocator* allocator,
+                                       void* hip_stream, cpm_batch** out) {
   return guard([&] {
     if (!bands || nbands < 1 || !m || !n || nrhs < 1 || !out) CPM_FAIL(CPM_E_INVALID, "bad argument");
+    if (allocator && (!allocator->alloc || !allocator->free))
+      CPM_FAIL(CPM_E_INVALID, "an allocator needs both alloc and free");
     *out = nullptr;
     std::unique_ptr<cpm_batch> B(new cpm_batch());
+    if (allocator) B->da.a = *allocator;
+    B->da.st = (hipStream_t)hip_stream;
     for (int i = 0; i < nbands; ++i) {
       if (!bands[i]) CPM_FAIL(CPM_E_INVALID, "null band %d", i);
       B->bands.push_back(bands[i]);
@@ -678,15 +689,14 @@ extern "C" cpm_status cpm_batch_autotune(cpm_batch* b, int dtype, int reps, void
                                          double* ms, int* best) {
   return guard([&] {
     if (!b) CPM_FAIL(CPM_E_INVALID, "null batch");
+    if (dtype != CPM_F64 && dtype != CPM_F32) CPM_FAIL(CPM_E_INVALID, "unknown dtype %d", dtype);
     const size_t es = dtype == CPM_F64 ? 8 : 4;
     const size_t bytes = es * (size_t)b->total * b->nrhs;
-    void *u = nullptr, *v = nullptr;
-    CPM_HIP(hipMalloc(&u, bytes));
-    CPM_HIP(hipMalloc(&v, bytes));
+    // the timing vectors are scratch of the composite band (kept for reuse)
+    void* u = band_scratch(b->comp.get(), kAutotuneSlot, bytes);
+    void* v = band_scratch(b->comp.get(), kAutotuneSlot + 1, bytes);
     CPM_HIP(hipMemsetAsync(u, 0, bytes, (hipStream_t)hip_stream));
     const cpm_status s = cpm_autotune(b->comp.get(), dtype, b->nrhs, u, v, reps, hip_stream, ms, best);
-    (void)hipFree(u);
-    (void)hipFree(v);
     if (s != CPM_OK) throw Error{s};
   });
 }

@@ -794,12 +794,18 @@ Blocks view(const cpm_band* b) {
                 b->p};
 }
 
-// A temporary device buffer freed at scope exit.
+// A temporary device buffer from a band's allocator, released at scope exit
+// (only work on the stream that used it can still be queued: the builder and
+// the export run on one stream).
 template <class T>
 struct Tmp {
   T* p = nullptr;
-  explicit Tmp(size_t n) { CPM_HIP(hipMalloc(&p, (n ? n : 1) * sizeof(T))); }
-  ~Tmp() { if (p) (void)hipFree(p); }
+  size_t bytes = 0;
+  const DevAlloc* da;
+  Tmp(const cpm_band* owner, size_t n) : bytes((n ? n : 1) * sizeof(T)), da(&owner->da) {
+    p = static_cast<T*>(da->get(bytes));
+  }
+  ~Tmp() { da->put(p, bytes); }
   Tmp(const Tmp&) = delete;
   Tmp& operator=(const Tmp&) = delete;
 };
@@ -876,18 +882,18 @@ static void build_pull(cpm_band* b, int64_t ne, Tmp<int>& key, Tmp<int>& val, hi
   if (ne <= 0) return;
   if (ne >= (1ll << 31)) CPM_FAIL(CPM_E_INVALID, "too many explicit-row entries");
   const int n = (int)ne;
-  Tmp<int> key2(n), val2(n), uniq(n), cnt(n), nrun(1);
+  Tmp<int> key2(b, n), val2(b, n), uniq(b, n), cnt(b, n), nrun(b, 1);
   size_t tb = 0;
   CPM_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, key.p, key2.p, val.p, val2.p, n, 0, 31, st));
   {
-    Tmp<unsigned char> tmp(tb);
+    Tmp<unsigned char> tmp(b, tb);
     CPM_HIP(hipcub::DeviceRadixSort::SortPairs(tmp.p, tb, key.p, key2.p, val.p, val2.p, n, 0, 31,
                                                st));
   }
   tb = 0;
   CPM_HIP(hipcub::DeviceRunLengthEncode::Encode(nullptr, tb, key2.p, uniq.p, cnt.p, nrun.p, n, st));
   {
-    Tmp<unsigned char> tmp(tb);
+    Tmp<unsigned char> tmp(b, tb);
     CPM_HIP(hipcub::DeviceRunLengthEncode::Encode(tmp.p, tb, key2.p, uniq.p, cnt.p, nrun.p, n, st));
   }
   int runs = 0;
@@ -1011,7 +1017,7 @@ template <int DIM>
 Filter stencil_set_filter(const cpm_band* t, hipStream_t st, unsigned long long* keep) {
   const int64_t n = t->n, n_s = t->n_s;
   const int nm = DIM == 3 ? 64 : 16;
-  Tmp<unsigned char> isE(n), isL(n), used(n), need(n);
+  Tmp<unsigned char> isE(t, n), isL(t, n), used(t, n), need(t, n);
   CPM_HIP(hipMemsetAsync(isE.p, 0, n, st));
   CPM_HIP(hipMemsetAsync(isL.p, 0, n, st));
   CPM_HIP(hipMemsetAsync(used.p, 0, n, st));
@@ -1079,11 +1085,11 @@ void build(cpm_band* b, hipStream_t st, const Filter& F) {
   const double thr = r + (half_diag + 0.01) / N;
 
   // ---- pass 1: occupied blocks (row by row), then sorted into Morton order
-  Tmp<int> row_count(nrows), row_off(nrows);
+  Tmp<int> row_count(b, nrows), row_off(b, nrows);
   hipLaunchKernelGGL((k_classify<DIM, false>), dim3(nrows), dim3(256), 0, st, S, N, r, thr, box,
                      row_count.p, nullptr, nullptr, nullptr, F);
   CPM_LAUNCH_CHECK();
-  const int64_t nb64 = scan_exclusive_i32(row_count.p, row_off.p, nrows, st);
+  const int64_t nb64 = scan_exclusive_i32(row_count.p, row_off.p, nrows, st, b->da);
   if (nb64 <= 0) CPM_FAIL(CPM_E_INVALID, "the band is empty (N = %d)", N);
   if (nb64 > (1 << 27)) CPM_FAIL(CPM_E_INVALID, "band too large: %lld blocks", (long long)nb64);
   const int nb = (int)nb64;
@@ -1092,9 +1098,9 @@ void build(cpm_band* b, hipStream_t st, const Filter& F) {
   b->blk_mask = b->alloc<unsigned long long>(nb);
   b->blk_off = b->alloc<int>(nb + 1);
   {
-    Tmp<int4> coord0(nb);
-    Tmp<unsigned long long> mask0(nb), key0(nb), key1(nb);
-    Tmp<int> idx0(nb), idx1(nb);
+    Tmp<int4> coord0(b, nb);
+    Tmp<unsigned long long> mask0(b, nb), key0(b, nb), key1(b, nb);
+    Tmp<int> idx0(b, nb), idx1(b, nb);
     hipLaunchKernelGGL((k_classify<DIM, true>), dim3(nrows), dim3(256), 0, st, S, N, r, thr, box,
                        nullptr, row_off.p, coord0.p, mask0.p, F);
     CPM_LAUNCH_CHECK();
@@ -1104,7 +1110,7 @@ void build(cpm_band* b, hipStream_t st, const Filter& F) {
     size_t tb = 0;
     CPM_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, key0.p, key1.p, idx0.p, idx1.p, nb, 0,
                                                63, st));
-    Tmp<unsigned char> tmp(tb);
+    Tmp<unsigned char> tmp(b, tb);
     CPM_HIP(hipcub::DeviceRadixSort::SortPairs(tmp.p, tb, key0.p, key1.p, idx0.p, idx1.p, nb, 0,
                                                63, st));
     hipLaunchKernelGGL(k_permute_blocks, dim3(grid_for(nb, 256)), dim3(256), 0, st, idx1.p, nb,
@@ -1113,10 +1119,10 @@ void build(cpm_band* b, hipStream_t st, const Filter& F) {
     CPM_HIP(hipStreamSynchronize(st));
   }
   {
-    Tmp<int> cnt(nb);
+    Tmp<int> cnt(b, nb);
     hipLaunchKernelGGL(k_popcounts, dim3(grid_for(nb, 256)), dim3(256), 0, st, b->blk_mask, nb, cnt.p);
     CPM_LAUNCH_CHECK();
-    b->n_s = scan_exclusive_i32(cnt.p, b->blk_off, nb, st);
+    b->n_s = scan_exclusive_i32(cnt.p, b->blk_off, nb, st, b->da);
     const int ns32 = (int)b->n_s;
     CPM_HIP(hipMemcpyAsync(b->blk_off + nb, &ns32, sizeof(int), hipMemcpyHostToDevice, st));
     CPM_HIP(hipStreamSynchronize(st));
@@ -1147,14 +1153,14 @@ void build(cpm_band* b, hipStream_t st, const Filter& F) {
   CPM_LAUNCH_CHECK();
 
   // ---- interior boundaries
-  Tmp<unsigned long long> counters(8);
+  Tmp<unsigned long long> counters(b, 8);
   CPM_HIP(hipMemsetAsync(counters.p, 0, 8 * sizeof(unsigned long long), st));
   IBCList L{};
   L.n = b->n_ibc;
   for (int c = 0; c < b->n_ibc; ++c) L.c[c] = b->ibcs[c];
   const int nib = b->n_ibc;
-  Tmp<int> row_c(nib ? n_s : 1), omega(nib ? n_s : 1), alpha_of(nib ? n_s : 1);
-  Tmp<double> side_v(nib ? (size_t)DIM * n_s : 1), cpcs(nib ? (size_t)DIM * n_s : 1);
+  Tmp<int> row_c(b, nib ? n_s : 1), omega(b, nib ? n_s : 1), alpha_of(b, nib ? n_s : 1);
+  Tmp<double> side_v(b, nib ? (size_t)DIM * n_s : 1), cpcs(b, nib ? (size_t)DIM * n_s : 1);
   std::unique_ptr<Tmp<int>> bc_kp;
   std::vector<int64_t> curve_count(nib, 0);
   if (nib) {
@@ -1168,25 +1174,25 @@ void build(cpm_band* b, hipStream_t st, const Filter& F) {
     if (hc[2]) CPM_FAIL(CPM_E_OVERLAP, "the check regions of two interior boundaries overlap");
     b->on_c_nodes = (int64_t)hc[0];
     CPM_HIP(hipMemsetAsync(alpha_of.p, 0xff, n_s * sizeof(int), st));
-    Tmp<int> flag(n_s), rank(n_s);
+    Tmp<int> flag(b, n_s), rank(b, n_s);
     for (int c = 0; c < nib; ++c) {
       hipLaunchKernelGGL(k_flag_curve, dim3(grid_for(n_s, 256)), dim3(256), 0, st, row_c.p,
                          omega.p, n_s, c, flag.p);
       CPM_LAUNCH_CHECK();
-      curve_count[c] = scan_exclusive_i32(flag.p, rank.p, n_s, st);
+      curve_count[c] = scan_exclusive_i32(flag.p, rank.p, n_s, st, b->da);
       b->n_c += curve_count[c];
     }
     b->bc_node = b->alloc<int>(b->n_c);
     b->bc_cpc = b->alloc<double>((size_t)b->n_c * DIM);
     b->bc_side = b->alloc<int>(b->n_c);
     b->bc_curve = b->alloc<int>(b->n_c);
-    bc_kp.reset(new Tmp<int>((size_t)b->n_c * 3));
+    bc_kp.reset(new Tmp<int>(b, (size_t)b->n_c * 3));
     int64_t base_alpha = 0;
     for (int c = 0; c < nib; ++c) {
       hipLaunchKernelGGL(k_flag_curve, dim3(grid_for(n_s, 256)), dim3(256), 0, st, row_c.p,
                          omega.p, n_s, c, flag.p);
       CPM_LAUNCH_CHECK();
-      scan_exclusive_i32(flag.p, rank.p, n_s, st);
+      scan_exclusive_i32(flag.p, rank.p, n_s, st, b->da);
       hipLaunchKernelGGL(k_bc_assign<DIM>, gnode, dim3(256), 0, st, B, nb, flag.p, rank.p, n_s,
                          base_alpha, c, S, L, side_v.p, cpcs.p, alpha_of.p, b->bc_node,
                          b->bc_cpc, b->bc_side, b->bc_curve, bc_kp->p);
@@ -1199,7 +1205,7 @@ void build(cpm_band* b, hipStream_t st, const Filter& F) {
   const int64_t n_c = b->n_c;
 
   // ---- interpolation stencils: holes, swaps, tiles
-  Tmp<int> eflag(n_s), tile_blk_of(n_s), tile_cnt(nb), tile_off(nb);
+  Tmp<int> eflag(b, n_s), tile_blk_of(b, n_s), tile_cnt(b, nb), tile_off(b, nb);
   CPM_HIP(hipMemsetAsync(tile_cnt.p, 0, nb * sizeof(int), st));
   hipLaunchKernelGGL(k_stencil_scan<DIM>, gnode, dim3(256), 0, st, B, nb, N, n_s, b->cp,
                      nib ? row_c.p : nullptr, alpha_of.p, side_v.p, eflag.p, tile_blk_of.p,
@@ -1218,8 +1224,8 @@ void build(cpm_band* b, hipStream_t st, const Filter& F) {
   // explicit E rows: swapped PDE rows then all BC rows
   constexpr int NM = DIM == 3 ? 64 : 16;
   {
-    Tmp<int> eidx(n_s);
-    const int64_t ne_pde = scan_exclusive_i32(eflag.p, eidx.p, n_s, st);
+    Tmp<int> eidx(b, n_s);
+    const int64_t ne_pde = scan_exclusive_i32(eflag.p, eidx.p, n_s, st, b->da);
     b->n_erows = (int)(ne_pde + n_c);
     b->erow_id = b->alloc<int>(b->n_erows);
     b->ecol = b->alloc<int>((size_t)b->n_erows * NM);
@@ -1246,11 +1252,11 @@ void build(cpm_band* b, hipStream_t st, const Filter& F) {
   }
   // gather tiles
   {
-    b->n_tile_rows = (int)scan_exclusive_i32(tile_cnt.p, tile_off.p, nb, st);
-    Tmp<int> nz(nb), tidx(nb);
+    b->n_tile_rows = (int)scan_exclusive_i32(tile_cnt.p, tile_off.p, nb, st, b->da);
+    Tmp<int> nz(b, nb), tidx(b, nb);
     hipLaunchKernelGGL(k_nonzero, dim3(grid_for(nb, 256)), dim3(256), 0, st, tile_cnt.p, nb, nz.p);
     CPM_LAUNCH_CHECK();
-    b->ntiles = (int)scan_exclusive_i32(nz.p, tidx.p, nb, st);
+    b->ntiles = (int)scan_exclusive_i32(nz.p, tidx.p, nb, st, b->da);
     b->tile_blk = b->alloc<int>(b->ntiles);
     b->tile_start = b->alloc<int>(b->ntiles + 1);
     hipLaunchKernelGGL(k_tile_compact, dim3(grid_for(nb, 256)), dim3(256), 0, st, tile_cnt.p,
@@ -1264,12 +1270,12 @@ void build(cpm_band* b, hipStream_t st, const Filter& F) {
     b->frac32 = b->alloc<float>((size_t)DIM * ntr);
     b->lbase = b->alloc<unsigned>(ntr);
     {
-      Tmp<int> cnt2((size_t)nb * 64), pos2((size_t)nb * 64);
+      Tmp<int> cnt2(b, (size_t)nb * 64), pos2(b, (size_t)nb * 64);
       CPM_HIP(hipMemsetAsync(cnt2.p, 0, (size_t)nb * 64 * sizeof(int), st));
       hipLaunchKernelGGL(k_tile_count2<DIM>, gnode, dim3(256), 0, st, B, nb, N, n_s, b->cp,
                          eflag.p, tile_blk_of.p, cnt2.p);
       CPM_LAUNCH_CHECK();
-      const int64_t tot = scan_exclusive_i32(cnt2.p, pos2.p, (int64_t)nb * 64, st);
+      const int64_t tot = scan_exclusive_i32(cnt2.p, pos2.p, (int64_t)nb * 64, st, b->da);
       if (tot != ntr) CPM_FAIL(CPM_E_INVALID, "internal: tile row count mismatch");
       hipLaunchKernelGGL(k_tile_fill<DIM>, gnode, dim3(256), 0, st, B, nb, N, n_s, b->cp,
                          eflag.p, tile_blk_of.p, pos2.p, ntr, b->perm, b->frac64, b->frac32,
@@ -1284,12 +1290,12 @@ void build(cpm_band* b, hipStream_t st, const Filter& F) {
   CPM_HIP(hipMemsetAsync(b->lrow_mask, 0, nb * sizeof(unsigned long long), st));
   {
     int64_t nl_pde = 0;
-    Tmp<int> lflag(nib ? n_s : 1), lidx(nib ? n_s : 1);
+    Tmp<int> lflag(b, nib ? n_s : 1), lidx(b, nib ? n_s : 1);
     if (nib) {
       hipLaunchKernelGGL(k_lflag<DIM>, gnode, dim3(256), 0, st, B, nb, n_s, row_c.p, alpha_of.p,
                          side_v.p, lflag.p);
       CPM_LAUNCH_CHECK();
-      nl_pde = scan_exclusive_i32(lflag.p, lidx.p, n_s, st);
+      nl_pde = scan_exclusive_i32(lflag.p, lidx.p, n_s, st, b->da);
     }
     b->n_lrows = (int)(nl_pde + n_c);
     b->lrow_id = b->alloc<int>(b->n_lrows);
@@ -1309,7 +1315,7 @@ void build(cpm_band* b, hipStream_t st, const Filter& F) {
   // pull lists of the transposed explicit rows
   {
     const int64_t ne = (int64_t)b->n_erows * NM;
-    Tmp<int> key(ne ? ne : 1), val(ne ? ne : 1);
+    Tmp<int> key(b, ne ? ne : 1), val(b, ne ? ne : 1);
     if (ne) {
       hipLaunchKernelGGL(k_pull_pairs_e, dim3(grid_for(ne, 256)), dim3(256), 0, st, ne, b->ecol,
                          key.p, val.p);
@@ -1328,7 +1334,7 @@ void build(cpm_band* b, hipStream_t st, const Filter& F) {
       CPM_LAUNCH_CHECK();
     }
     const int64_t nl = (int64_t)b->n_lrows * 2 * DIM * 2;
-    Tmp<int> keyl(nl ? nl : 1), vall(nl ? nl : 1);
+    Tmp<int> keyl(b, nl ? nl : 1), vall(b, nl ? nl : 1);
     if (nl) {
       hipLaunchKernelGGL(k_pull_pairs_l, dim3(grid_for(nl, 256)), dim3(256), 0, st, b->n_lrows,
                          2 * DIM, n_s, b->lrow_id, b->lcol, b->lcol0, keyl.p, vall.p);
@@ -1346,7 +1352,7 @@ void build(cpm_band* b, hipStream_t st, const Filter& F) {
   b->tile_col = b->alloc<int>(b->ntiles);
   std::fill(b->col_start, b->col_start + 9, 0);
   if (b->ntiles) {
-    Tmp<int> colour(b->ntiles);
+    Tmp<int> colour(b, b->ntiles);
     hipLaunchKernelGGL(k_tile_colour, dim3(grid_for(b->ntiles, 256)), dim3(256), 0, st, b->ntiles,
                        b->tile_blk, b->blk_coord, colour.p);
     CPM_LAUNCH_CHECK();
@@ -1394,9 +1400,12 @@ void export_rows(const cpm_band* b, int* coords, int* ecols, int* lcols, int* ba
 using namespace cpm;
 
 extern "C" cpm_status cpm_build_band(const cpm_surface* surface, const cpm_ibc* ibcs, int n_ibc,
-                                     const cpm_grid* grid, void* hip_stream, cpm_band** out) {
+                                     const cpm_grid* grid, const cpm_allocator* allocator,
+                                     void* hip_stream, cpm_band** out) {
   return guard([&] {
     if (!surface || !grid || !out) CPM_FAIL(CPM_E_INVALID, "null argument");
+    if (allocator && (!allocator->alloc || !allocator->free))
+      CPM_FAIL(CPM_E_INVALID, "an allocator needs both alloc and free");
     *out = nullptr;
     if (grid->N <= 0) CPM_FAIL(CPM_E_INVALID, "N must be positive (got %d)", grid->N);
     if (grid->p != 3 && grid->p != 2)
@@ -1433,6 +1442,8 @@ extern "C" cpm_status cpm_build_band(const cpm_surface* surface, const cpm_ibc* 
     }
     hipStream_t st = (hipStream_t)hip_stream;
     std::unique_ptr<cpm_band> b(new cpm_band());
+    if (allocator) b->da.a = *allocator;
+    b->da.st = st;
     CPM_HIP(hipGetDevice(&b->device));
     b->dim = kind == CPM_SURF_CIRCLE ? 2 : 3;
     b->N = grid->N;
@@ -1459,6 +1470,7 @@ extern "C" cpm_status cpm_build_band(const cpm_surface* surface, const cpm_ibc* 
       // the tube first, then the same construction restricted to its
       // stencil set (a node filter in the classification pass)
       std::unique_ptr<cpm_band> t(new cpm_band());
+      t->da = b->da;
       t->device = b->device;
       t->dim = b->dim;
       t->N = b->N;
@@ -1473,7 +1485,7 @@ extern "C" cpm_status cpm_build_band(const cpm_surface* surface, const cpm_ibc* 
       t->check_factor = b->check_factor;
       if (b->dim == 3) build<3>(t.get(), st, Filter{});
       else build<2>(t.get(), st, Filter{});
-      Tmp<unsigned long long> keep(t->nb);
+      Tmp<unsigned long long> keep(b.get(), t->nb);
       const Filter F = b->dim == 3 ? stencil_set_filter<3>(t.get(), st, keep.p)
                                    : stencil_set_filter<2>(t.get(), st, keep.p);
       if (b->dim == 3) build<3>(b.get(), st, F);
@@ -1524,7 +1536,7 @@ extern "C" cpm_status cpm_band_export(const cpm_band* b, int what, void* host_ds
       CPM_HIP(hipMemcpy(host_dst, src, need, hipMemcpyDeviceToHost));
       return;
     }
-    Tmp<int> dev(need / 4);
+    Tmp<int> dev(b, need / 4);
     CPM_HIP(hipMemset(dev.p, 0xff, need));
     int* coords = what == CPM_EXPORT_COORDS ? dev.p : nullptr;
     int* ecols = what == CPM_EXPORT_ECOLS ? dev.p : nullptr;

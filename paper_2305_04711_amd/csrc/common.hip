@@ -18,29 +18,62 @@ void set_error(const char* fmt, ...) {
   va_end(ap);
 }
 
+void* DevAlloc::get(size_t bytes) const {
+  if (bytes == 0) bytes = 16;
+  if (!custom()) {
+    void* p = nullptr;
+    CPM_HIP(hipMalloc(&p, bytes));
+    return p;
+  }
+  void* p = a.alloc(bytes, (void*)st, a.ctx);
+  if (!p) CPM_FAIL(CPM_E_OOM, "the caller's allocator returned NULL for %zu bytes", bytes);
+  CPM_HIP(hipStreamSynchronize(st));
+  return p;
+}
+
+void DevAlloc::put(void* p, size_t bytes) const noexcept {
+  if (!p) return;
+  if (!custom()) {
+    (void)hipFree(p);
+    return;
+  }
+  if (a.free) a.free(p, bytes ? bytes : 16, (void*)st, a.ctx);
+}
+
 void* Workspace::get(int i, size_t bytes) {
   if ((int)slots.size() <= i) slots.resize(i + 1, {nullptr, 0});
   auto& s = slots[i];
   if (s.second < bytes) {
-    if (s.first) CPM_HIP(hipFree(s.first));
+    if (s.first) {
+      // kernels of earlier calls may still read the old block (hipFree
+      // waits for them by itself; a caller's allocator may not)
+      if (da->custom()) CPM_HIP(hipDeviceSynchronize());
+      da->put(s.first, s.second);
+      total -= s.second;
+    }
     s.first = nullptr;
     s.second = 0;
-    CPM_HIP(hipMalloc(&s.first, bytes));
+    s.first = da->get(bytes);
     s.second = bytes;
+    total += bytes;
   }
   return s.first;
 }
 
 Workspace::~Workspace() {
-  for (auto& s : slots)
-    if (s.first) (void)hipFree(s.first);
+  for (auto& s : slots) da->put(s.first, s.second);
 }
 
 void* band_scratch(const cpm_band* b, int slot, size_t bytes) {
   cpm_band* mb = const_cast<cpm_band*>(b);
-  if (!mb->ws) mb->ws = new Workspace();
+  if (!mb->ws) {
+    mb->ws = new Workspace();
+    mb->ws->da = &mb->da;
+  }
   return mb->ws->get(slot, bytes ? bytes : 16);
 }
+
+size_t band_scratch_bytes(const cpm_band* b) { return b->ws ? b->ws->total : 0; }
 
 // ------------------------------------------------------------------- scan
 // Exclusive prefix sum of int32 with an int64 total.  Each workgroup of 256
@@ -112,16 +145,16 @@ __global__ void k_scan_add(T* out, const long long* offs, int64_t n) {
 
 namespace {
 // scans 64-bit tile sums in place into exclusive offsets; returns the total
-long long scan64_inplace(long long* a, int64_t n, hipStream_t st) {
+long long scan64_inplace(long long* a, int64_t n, hipStream_t st, const DevAlloc& da) {
   const int64_t nt = (n + kScanTile - 1) / kScanTile;
-  long long* sums = nullptr;
-  CPM_HIP(hipMalloc(&sums, (nt + 1) * sizeof(long long)));
+  const size_t sb = (nt + 1) * sizeof(long long);
+  long long* sums = static_cast<long long*>(da.get(sb));
   long long total = 0;
   try {
     hipLaunchKernelGGL(k_scan_tile64, dim3(nt), dim3(kScanThreads), 0, st, a, a, sums, n);
     CPM_LAUNCH_CHECK();
     if (nt > 1) {
-      total = scan64_inplace(sums, nt, st);
+      total = scan64_inplace(sums, nt, st, da);
       hipLaunchKernelGGL(k_scan_add<long long>, dim3(grid_for(n, 256)), dim3(256), 0, st, a, sums, n);
       CPM_LAUNCH_CHECK();
     } else {
@@ -129,26 +162,28 @@ long long scan64_inplace(long long* a, int64_t n, hipStream_t st) {
       CPM_HIP(hipStreamSynchronize(st));
     }
   } catch (...) {
-    (void)hipFree(sums);
+    (void)hipStreamSynchronize(st);
+    da.put(sums, sb);
     throw;
   }
   CPM_HIP(hipStreamSynchronize(st));
-  CPM_HIP(hipFree(sums));
+  da.put(sums, sb);
   return total;
 }
 }  // namespace
 
-int64_t scan_exclusive_i32(const int* in, int* out, int64_t n, hipStream_t st) {
+int64_t scan_exclusive_i32(const int* in, int* out, int64_t n, hipStream_t st,
+                           const DevAlloc& da) {
   if (n <= 0) return 0;
   const int64_t nt = (n + kScanTile - 1) / kScanTile;
-  long long* sums = nullptr;
-  CPM_HIP(hipMalloc(&sums, (nt + 1) * sizeof(long long)));
+  const size_t sb = (nt + 1) * sizeof(long long);
+  long long* sums = static_cast<long long*>(da.get(sb));
   long long total = 0;
   try {
     hipLaunchKernelGGL(k_scan_tile, dim3(nt), dim3(kScanThreads), 0, st, in, out, sums, n);
     CPM_LAUNCH_CHECK();
     if (nt > 1) {
-      total = scan64_inplace(sums, nt, st);
+      total = scan64_inplace(sums, nt, st, da);
       hipLaunchKernelGGL(k_scan_add<int>, dim3(grid_for(n, 256)), dim3(256), 0, st, out, sums, n);
       CPM_LAUNCH_CHECK();
     } else {
@@ -156,10 +191,11 @@ int64_t scan_exclusive_i32(const int* in, int* out, int64_t n, hipStream_t st) {
     }
     CPM_HIP(hipStreamSynchronize(st));
   } catch (...) {
-    (void)hipFree(sums);
+    (void)hipStreamSynchronize(st);
+    da.put(sums, sb);
     throw;
   }
-  CPM_HIP(hipFree(sums));
+  da.put(sums, sb);
   if (total >= (1ll << 31)) {
     set_error("scan total %lld exceeds the 32-bit index range", total);
     throw Error{CPM_E_INVALID};
@@ -170,8 +206,11 @@ int64_t scan_exclusive_i32(const int* in, int* out, int64_t n, hipStream_t st) {
 }  // namespace cpm
 
 cpm_band::~cpm_band() {
+  // kernels on any stream may still read the band (hipFree would wait for
+  // them by itself; a caller's allocator may hand the blocks out at once)
+  if (da.custom()) (void)hipDeviceSynchronize();
   delete ws;
-  for (void* p : allocs) (void)hipFree(p);
+  for (auto& pb : allocs) da.put(pb.first, pb.second);
 }
 
 using namespace cpm;
@@ -201,5 +240,6 @@ extern "C" cpm_status cpm_band_query(const cpm_band* b, cpm_band_info* out) {
     out->r_band = b->r;
     out->tau = b->tau;
     out->device_bytes = b->bytes;
+    out->scratch_bytes = band_scratch_bytes(b);
   });
 }

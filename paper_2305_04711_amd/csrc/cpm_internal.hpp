@@ -78,6 +78,20 @@ template <> struct Geo<2> {
 
 struct Workspace;
 
+// Device memory of a band or batch: through the caller's cpm_allocator (with
+// the stream given at creation), or hipMalloc / hipFree when none was given.
+// get() throws CPM_E_OOM when the allocator fails; after a caller's
+// allocation it synchronises that stream, so that no work the allocator's
+// stream still had queued on the block overlaps the library's use of it on
+// other streams.
+struct DevAlloc {
+  cpm_allocator a{};
+  hipStream_t st = nullptr;
+  bool custom() const { return a.alloc != nullptr; }
+  void* get(size_t bytes) const;
+  void put(void* p, size_t bytes) const noexcept;
+};
+
 // Occupancy mask and first DOF of one block (mask 0 when the block is absent).
 struct QMeta {
   unsigned long long mask;
@@ -187,17 +201,17 @@ struct cpm_band {
 
   int64_t on_c_nodes = 0, no_bc_dof_swaps = 0;
   size_t bytes = 0;
-  std::vector<void*> allocs;
+  cpm::DevAlloc da;                   // provider of every device allocation
+  std::vector<std::pair<void*, size_t>> allocs;
   cpm::Workspace* ws = nullptr;
   cpm::Tune tune[2];                  // per dtype (0 = FP64, 1 = FP32)
 
   template <class T>
   T* alloc(size_t count) {
-    void* p = nullptr;
     size_t b = count * sizeof(T);
     if (b == 0) b = 16;
-    CPM_HIP(hipMalloc(&p, b));
-    allocs.push_back(p);
+    void* p = da.get(b);
+    allocs.push_back({p, b});
     bytes += b;
     return static_cast<T*>(p);
   }
@@ -206,19 +220,24 @@ struct cpm_band {
 
 namespace cpm {
 
-// Scratch vectors owned by a band, grown on demand (calls on one band from
-// several threads at once race on them).
+// Scratch vectors owned by a band, grown on demand through the band's
+// allocator (calls on one band from several threads at once race on them).
+// A slot that grows is released after the device has finished its work.
 struct Workspace {
+  const DevAlloc* da = nullptr;
+  size_t total = 0;
   std::vector<std::pair<void*, size_t>> slots;
   void* get(int i, size_t bytes);
   ~Workspace();
 };
 void* band_scratch(const cpm_band* b, int slot, size_t bytes);
+size_t band_scratch_bytes(const cpm_band* b);
 // scratch slot of the transposed apply's per-entry products (E pull lists)
 constexpr int kEtProdSlot = 6;
 
 // Device-wide exclusive scan; returns the total (synchronises the stream).
-int64_t scan_exclusive_i32(const int* in, int* out, int64_t n, hipStream_t s);
+// Its temporaries come from da.
+int64_t scan_exclusive_i32(const int* in, int* out, int64_t n, hipStream_t s, const DevAlloc& da);
 
 // apply entry points used by the solvers (nrhs = 1, optional gauge).  With
 // dy set, the kernel that writes v also writes the partials of (dy, v) and
@@ -233,6 +252,8 @@ void apply_transpose_impl(const cpm_band* b, double m, double n, int nrhs,
                           const double* gauge_sum = nullptr, double gamma = 0.0,
                           const T* dy = nullptr, double* dpart = nullptr);
 int apply_dot_parts(const cpm_band* b, bool transpose);
+// bytes of the forward apply's scratch vector (the FP64 intermediate a = E u)
+size_t apply_scratch_bytes(const cpm_band* b, int nrhs);
 // out -= n (L - diag L) e(g): the Dirichlet part of a right-hand side
 void add_dirichlet_term(const cpm_band* b, double n, const double* g, int nrhs, double* out,
                         hipStream_t st);

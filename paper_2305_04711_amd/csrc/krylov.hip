@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <memory>
+#include <type_traits>
 
 #include "cpm_internal.hpp"
 
@@ -150,19 +151,22 @@ __global__ __launch_bounds__(256) void k_s(int64_t n, const T* __restrict__ r, c
     s[i] = r[i] - al * v[i];
 }
 
-// x += alpha p + omega s;  r = s - omega t;  rho = (rh, r);  rr = (r, r)
-template <class T>
-__global__ __launch_bounds__(256) void k_xr(int64_t n, T* __restrict__ x, const T* __restrict__ p,
+// x += alpha p + omega s;  r = s - omega t;  rho = (rh, r);  rr = (r, r).
+// The iterate x may be kept in a wider type TX than the recurrence vectors
+// (FP64 x with an FP32 recurrence: the update is not rounded to FP32).
+template <class T, class TX>
+__global__ __launch_bounds__(256) void k_xr(int64_t n, TX* __restrict__ x, const T* __restrict__ p,
                                             const T* __restrict__ s, const T* __restrict__ t,
                                             T* __restrict__ r, const T* __restrict__ rh,
                                             double* part, Scal* S) {
   if (S->done) return;
   const T al = (T)S->alpha, om = (T)S->omega;
+  const TX alx = (TX)S->alpha, omx = (TX)S->omega;
   double acc[2] = {0.0, 0.0};
   for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kRedThreads) {
     const T si = s[i];
-    x[i] = x[i] + al * p[i] + om * si;
+    x[i] = x[i] + alx * (TX)p[i] + omx * (TX)si;
     const T ri = si - om * t[i];
     r[i] = ri;
     acc[0] += (double)rh[i] * (double)ri;
@@ -194,16 +198,16 @@ __global__ __launch_bounds__(256) void k_xr(int64_t n, T* __restrict__ x, const 
 // added into the FP64 one), then rho = (rh, r) and beta from it, so the next
 // direction update p = r + beta (p - omega v) continues the recurrence with
 // the true residual in place of the recursive one.
-template <class T>
+template <class T, class TX>
 __global__ __launch_bounds__(256) void k_replace(int64_t n, const double* __restrict__ r64, double inv,
                                                  T* __restrict__ r, const T* __restrict__ rh,
-                                                 T* __restrict__ x, double* part, Scal* S) {
+                                                 TX* __restrict__ x, double* part, Scal* S) {
   double acc[2] = {0.0, 0.0};
   for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kRedThreads) {
     const T ri = (T)(r64[i] * inv);
     r[i] = ri;
-    x[i] = T(0);
+    x[i] = TX(0);
     acc[0] += (double)rh[i] * (double)ri;
     acc[1] += (double)ri * (double)ri;
   }
@@ -270,16 +274,24 @@ __global__ void k_addT(int64_t n, double* __restrict__ x, const T* __restrict__ 
 }
 
 // out = (T)(r * inv), d = 0
-template <class T>
+template <class T, class TX>
 __global__ void k_scaleT(int64_t n, const double* __restrict__ r, double inv, T* __restrict__ out,
-                         T* __restrict__ d) {
+                         TX* __restrict__ d) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     out[i] = (T)(r[i] * inv);
-    d[i] = T(0);
+    d[i] = TX(0);
   }
 }
 
+
+// Flags a breakdown of the recurrence (the test hook below).
+__global__ void k_force_breakdown(Scal* S) {
+  if (threadIdx.x == 0 && !S->done) {
+    S->breakdown = 1;
+    S->done = 1;
+  }
+}
 
 __global__ void k_set_it(Scal* S, int it) {
   if (threadIdx.x == 0) S->it = it;
@@ -357,6 +369,15 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+// Test hook for the breakdown restart: CPM_TEST_BREAKDOWN_AT=k makes an FP64
+// BiCGSTAB solve flag a breakdown once (rho = (rh, r) treated as zero) at its
+// first convergence check after k iterations, so that the restart from the
+// current iterate with a new shadow residual runs on demand.  Read per solve.
+int test_breakdown_at() {
+  const char* e = std::getenv("CPM_TEST_BREAKDOWN_AT");
+  return e && e[0] ? std::atoi(e) : -1;
+}
+
 // CPM_TRACE=1 prints the refinement history to stderr.
 bool trace_on() {
   static const int on = [] {
@@ -372,8 +393,11 @@ struct Pinned {
   ~Pinned() { if (h) (void)hipHostFree(h); }
 };
 
-// BiCGSTAB on one right-hand side.  Vectors are band scratch slots.
-template <class T>
+// BiCGSTAB on one right-hand side.  Vectors are band scratch slots.  The
+// recurrence vectors are of type T; the iterate passed to iteration() and
+// solve() is of type TX (TX = double with T = float: the FP32 recurrence
+// accumulates its solution in FP64).
+template <class T, class TX = T>
 struct Bicg {
   const cpm_band* b;
   hipStream_t st;
@@ -389,8 +413,7 @@ struct Bicg {
   int ew_grid, red_g;
   hipGraphExec_t gexec = nullptr;
   int graph_iters = 0;
-  const T* gx_rhs = nullptr;
-  T* gx_x = nullptr;
+  TX* gx_x = nullptr;
 
   Bicg(const cpm_band* b_, hipStream_t st_, double m_, double n_, double gamma_, bool tr, int slot0)
       : b(b_), st(st_), n(b_->n), m(m_), nn(n_), gamma(gamma_), transpose(tr) {
@@ -410,14 +433,14 @@ struct Bicg {
     ew_grid = grid_for(n, 256, 4096);
     red_g = red_grid(n);
     // make sure every scratch buffer exists before any graph capture
-    band_scratch(b, 0, sizeof(T) * (size_t)n);
+    band_scratch(b, 0, apply_scratch_bytes(b, 1));
     if (gamma != 0.0) {
       band_scratch(b, 3, sizeof(double) * 256 + 64);
       band_scratch(b, 4, sizeof(double) + 64);
     }
     if (transpose) {
-      band_scratch(b, 1, sizeof(T) * (size_t)n);
-      band_scratch(b, 2, sizeof(T) * (size_t)n);
+      band_scratch(b, 1, sizeof(double) * (size_t)n);
+      band_scratch(b, 2, sizeof(double) * (size_t)n);
       if (b->n_et_entries)
         band_scratch(b, kEtProdSlot, sizeof(double) * (size_t)b->n_et_entries);
     }
@@ -434,9 +457,13 @@ struct Bicg {
   }
 
   // r = rhs - A x, rh = p = r, v = 0, beta = 0 (so the first direction
-  // update of an iteration leaves p = r)
-  void init(const T* rhs, const T* x, bool x_zero, double tol) {
-    if (!x_zero) apply(x, v);
+  // update of an iteration leaves p = r); x is read only when x_zero is false,
+  // which needs TX = T
+  void init(const T* rhs, const TX* x, bool x_zero, double tol) {
+    if (!x_zero) {
+      if constexpr (std::is_same<T, TX>::value) apply(x, v);
+      else CPM_FAIL(CPM_E_INVALID, "internal: warm start of a mixed-type recurrence");
+    }
     hipLaunchKernelGGL(k_init<T>, dim3(red_g), dim3(kRedThreads), 0, st, n, rhs, v, !x_zero, r,
                        rh, p, part, S, tol);
     hipLaunchKernelGGL(k_zero<T>, dim3(ew_grid), dim3(256), 0, st, n, v);
@@ -445,25 +472,26 @@ struct Bicg {
 
   // One BiCGSTAB step, starting with the direction update so that a step
   // ends right after the new residual (where a replacement can take place).
-  void iteration(T* x) {
+  void iteration(TX* x) {
     hipLaunchKernelGGL(k_p<T>, dim3(ew_grid), dim3(256), 0, st, n, r, p, v, S);
     apply(p, v, rh);
     hipLaunchKernelGGL(k_dot_fin<0>, dim3(fin_g), dim3(kRedThreads), 0, st, dpart, dnp, part, S);
     hipLaunchKernelGGL(k_s<T>, dim3(ew_grid), dim3(256), 0, st, n, r, v, s, S);
     apply(s, t, s);
     hipLaunchKernelGGL(k_dot_fin<1>, dim3(fin_g), dim3(kRedThreads), 0, st, dpart, dnp, part, S);
-    hipLaunchKernelGGL(k_xr<T>, dim3(red_g), dim3(kRedThreads), 0, st, n, x, p, s, t, r, rh, part, S);
-    CPM_LAUNCH_CHECK();
-  }
-
-  // residual replacement (see k_replace); x is the partial solution vector
-  void replace(const double* r64, double inv, T* x) {
-    hipLaunchKernelGGL(k_replace<T>, dim3(red_g), dim3(kRedThreads), 0, st, n, r64, inv, r, rh, x,
+    hipLaunchKernelGGL((k_xr<T, TX>), dim3(red_g), dim3(kRedThreads), 0, st, n, x, p, s, t, r, rh,
                        part, S);
     CPM_LAUNCH_CHECK();
   }
 
-  void run_iters(T* x, int k, bool use_graph) {
+  // residual replacement (see k_replace); x is the partial solution vector
+  void replace(const double* r64, double inv, TX* x) {
+    hipLaunchKernelGGL((k_replace<T, TX>), dim3(red_g), dim3(kRedThreads), 0, st, n, r64, inv, r,
+                       rh, x, part, S);
+    CPM_LAUNCH_CHECK();
+  }
+
+  void run_iters(TX* x, int k, bool use_graph) {
     if (!use_graph) {
       for (int i = 0; i < k; ++i) iteration(x);
       return;
@@ -499,17 +527,25 @@ struct Bicg {
 
   // Solve A x = rhs to the recursive residual tol (relative).  Returns the
   // iterations spent; breakdowns restart from the current iterate.
-  int solve(const T* rhs, T* x, bool x_zero, double tol, int maxit, int check_every,
+  int solve(const T* rhs, TX* x, bool x_zero, double tol, int maxit, int check_every,
             bool use_graph, int* restarts) {
     hipLaunchKernelGGL(k_zero_scal, dim3(1), dim3(64), 0, st, S);
     init(rhs, x, x_zero, tol);
     int it = 0;
+    const int force_at = test_breakdown_at();
+    bool forced = false;
     const Scal* h = &read();
     while (!h->done && it < maxit) {
       const int k = std::min(check_every, maxit - it);
       run_iters(x, k, use_graph && k == check_every);
       h = &read();
       it = h->it;
+      if (force_at >= 0 && !forced && !h->done && it >= force_at) {
+        forced = true;
+        hipLaunchKernelGGL(k_force_breakdown, dim3(1), dim3(64), 0, st, S);
+        CPM_LAUNCH_CHECK();
+        h = &read();
+      }
       if (h->done && h->breakdown && !(h->rr <= h->tol2)) {
         if (++*restarts > 50) break;
         const int keep = h->it;
@@ -674,18 +710,19 @@ struct RU {
 enum { RU_CONVERGED = 0, RU_STALLED = 1, RU_MAXIT = 2 };
 
 // Runs a recurrence of precision T with reliable updates until the FP64
-// residual reaches tol.  An update happens when the recursive residual has
-// dropped by delta since the last one, when the recurrence stops (converged
-// or broken down), or after max_cycle iterations without either.  It adds
-// sigma d into x, recomputes r = b - A x in FP64 and substitutes it for the
-// recursive residual (k_replace).  The run ends (RU_STALLED) at the first
-// update that fails to halve the FP64 residual of the previous one, that was
-// forced by max_cycle (the recurrence converges far slower than it did), that
-// follows a breakdown, or whose recursive residual underestimates the true
-// one by more than 1.5x; an update that left the FP64 residual above the
-// previous one is taken back first, so x is the best iterate of the run.
-template <class T>
-int ru_run(RU& c, Bicg<T>& k, T* d, double rn, int max_cycle) {
+// residual reaches tol.  The recurrence solves A d = r / sigma and keeps its
+// partial solution d in TX (FP64 for the mixed solve).  An update happens
+// when the recursive residual has dropped by delta since the last one, when
+// the recurrence stops (converged or broken down), or after max_cycle
+// iterations without either.  It adds sigma d into x, recomputes r = b - A x
+// in FP64 and substitutes it for the recursive residual (k_replace), so the
+// recurrence goes on with the true residual and keeps its Krylov space.  The
+// run ends (RU_STALLED) at the first update that follows a breakdown or fails
+// to halve the FP64 residual of the previous update; an update that left the
+// FP64 residual above the previous one is taken back first, so x is the best
+// iterate of the run.
+template <class T, class TX>
+int ru_run(RU& c, Bicg<T, TX>& k, TX* d, double rn, int max_cycle) {
   const int64_t n = c.b->n;
   const double inv = 1.0 / c.sigma;
   const int eg = grid_for(n, 256, 4096);
@@ -704,7 +741,7 @@ int ru_run(RU& c, Bicg<T>& k, T* d, double rn, int max_cycle) {
     if (!(h.done || bad || rrec < c.delta * maxr || forced)) continue;
     const bool broken = h.breakdown || bad;
     if (!bad) {   // a non-finite recursion leaves x as it was at the last update
-      hipLaunchKernelGGL(k_addT<T>, dim3(eg), dim3(256), 0, c.st, n, c.x, d, c.sigma);
+      hipLaunchKernelGGL(k_addT<TX>, dim3(eg), dim3(256), 0, c.st, n, c.x, d, c.sigma);
       CPM_LAUNCH_CHECK();
     }
     auto rb = c.residual();
@@ -712,19 +749,19 @@ int ru_run(RU& c, Bicg<T>& k, T* d, double rn, int max_cycle) {
     c.stt->relres = rn / c.bn;
     ++c.stt->outer_iters;
     if (trace_on())
-      std::fprintf(stderr, "[cpm] %s update %d: recursive %.3e true relres %.3e its %d%s\n",
+      std::fprintf(stderr, "[cpm] %s update %d: recursive %.3e true relres %.3e its %d%s%s\n",
                    sizeof(T) == 4 ? "FP32" : "FP64", c.stt->outer_iters, rrec * c.sigma / c.bn,
-                   c.stt->relres, c.its, broken ? " (breakdown)" : "");
+                   c.stt->relres, c.its, broken ? " (breakdown)" : "", forced ? " (forced)" : "");
     if (c.stt->relres <= c.tol) return RU_CONVERGED;
     if (!__builtin_isfinite(rn) || !(rn <= prev)) {
       if (!bad) {   // take the update back
-        hipLaunchKernelGGL(k_addT<T>, dim3(eg), dim3(256), 0, c.st, n, c.x, d, -c.sigma);
+        hipLaunchKernelGGL(k_addT<TX>, dim3(eg), dim3(256), 0, c.st, n, c.x, d, -c.sigma);
         CPM_LAUNCH_CHECK();
       }
       c.stt->relres = prev / c.bn;
       return RU_STALLED;
     }
-    if (broken || forced || !(rn < 0.5 * prev) || rn > 1.5 * rrec * c.sigma) return RU_STALLED;
+    if (broken || !(rn < 0.5 * prev)) return RU_STALLED;
     prev = rn;
     maxr = rn * inv;
     cycle0 = h.it;
@@ -735,11 +772,25 @@ int ru_run(RU& c, Bicg<T>& k, T* d, double rn, int max_cycle) {
 
 void solve_one(const cpm_band* b, const cpm_solve_opts& o, const double* rhs, double* x,
                cpm_solve_stats& stt, hipStream_t st, bool tr) {
+  const int64_t n = b->n;
+  {
+    // non-finite data would only surface as a failed convergence; refuse it
+    double* r64 = (double*)band_scratch(b, 20, sizeof(double) * n);
+    double* v64 = (double*)band_scratch(b, 21, sizeof(double) * n);
+    double* part = (double*)band_scratch(b, 22, sizeof(double) * 2 * kMaxParts);
+    Scal* S = (Scal*)band_scratch(b, 23, sizeof(Scal));
+    CPM_HIP(hipMemsetAsync(S, 0, sizeof(Scal), st));
+    Pinned pin;
+    auto rb = residual64(b, st, o.m, o.n, o.gauge, tr, rhs, x, r64, v64, part, S, pin);
+    if (!std::isfinite(rb.second))
+      CPM_FAIL(CPM_E_INVALID, "the right-hand side holds non-finite values");
+    if (!std::isfinite(rb.first))
+      CPM_FAIL(CPM_E_INVALID, "the initial guess holds non-finite values");
+  }
   if (o.mode == CPM_SOLVE_GMRES) {
     gmres64(b, o, rhs, x, stt, st, tr);
     return;
   }
-  const int64_t n = b->n;
   const int maxit = o.maxit > 0 ? o.maxit : 20000;
   const int ce = o.check_every > 0 ? o.check_every : 16;
   const double tol = o.tol > 0 ? o.tol : 1e-8;
@@ -781,12 +832,13 @@ void solve_one(const cpm_band* b, const cpm_solve_opts& o, const double* rhs, do
     return false;
   };
   // Mixed precision: one FP32 BiCGSTAB recurrence on A d = r0 / sigma with
-  // reliable updates (ru_run): the solution accumulates in FP64 and
-  // convergence is decided on the FP64 residual only.  Rounding a smooth
-  // vector to FP32 perturbs A p by about eps32 ||A|| ||p||, which bounds the
-  // residual reduction the FP32 recurrence can deliver (about four decades
-  // for the Laplacian at h = 1/512); at the first update that shows it, the
-  // solve continues with FP64 BiCGSTAB from the refined x.
+  // reliable updates (ru_run).  The recurrence vectors are FP32; the FP32
+  // apply computes in FP64 (FP64 weights and intermediate vectors), so it
+  // differs from the FP64 operator only by the rounding of the stored
+  // interpolation fractions; the partial solution d is accumulated in FP64
+  // and convergence is decided on the FP64 residual only.  If the updates
+  // stop making progress, the solve continues with FP64 BiCGSTAB from the
+  // refined x.
   auto mixed_ru = [&]() {
     RU c{b, st, o.m, o.n, gamma, tr, rhs, x, r64, v64, part, S, &pin};
     auto rb = c.residual();
@@ -803,15 +855,15 @@ void solve_one(const cpm_band* b, const cpm_solve_opts& o, const double* rhs, do
     c.graph = graph;
     c.stt = &stt;
     const double inv = 1.0 / c.sigma;
-    Bicg<float> k32(b, st, o.m, o.n, gamma, tr, 10);
+    Bicg<float, double> k32(b, st, o.m, o.n, gamma, tr, 10);
     float* r32 = (float*)band_scratch(b, 24, sizeof(float) * n);
-    float* d32 = (float*)band_scratch(b, 25, sizeof(float) * n);
-    hipLaunchKernelGGL(k_scaleT<float>, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, n, r64,
-                       inv, r32, d32);
+    double* d64 = (double*)band_scratch(b, 25, sizeof(double) * n);
+    hipLaunchKernelGGL((k_scaleT<float, double>), dim3(grid_for(n, 256, 4096)), dim3(256), 0, st,
+                       n, r64, inv, r32, d64);
     hipLaunchKernelGGL(k_zero_scal, dim3(1), dim3(64), 0, st, k32.S);
     CPM_LAUNCH_CHECK();
-    k32.init(r32, d32, true, 0.5 * tol * c.bn * inv);
-    const int status = ru_run<float>(c, k32, d32, rn, 200);
+    k32.init(r32, nullptr, true, 0.5 * tol * c.bn * inv);
+    const int status = ru_run<float, double>(c, k32, d64, rn, 1000);
     its += c.its;
     if (status == RU_CONVERGED) return true;
     if (status == RU_MAXIT) return false;

@@ -48,3 +48,18 @@ def test_local_rows_equal_assembled_operator(name, S, Cs, N, order):
     curve = np.concatenate([np.full(sysm.n_s, -1), sysm.bc_curve])
     got = loc.apply_rows(K, curve, _u_of_factory(sysm, u), m, n)
     assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref)), name
+
+
+def test_local_rows_refuse_what_they_do_not_model():
+    S = G.Sphere()
+    arc = G.LatitudeArc(S, 0.3, (1.0, 0.0), (0.0, 1.0))
+    with pytest.raises(NotImplementedError):
+        LO.LocalCPM(S, 16, [arc])
+    with pytest.raises(NotImplementedError):
+        LO.LocalCPM(S, 16, [G.LatitudeC(S, 0.0)], bc_types=[("neumann", "neumann")])
+    with pytest.raises(NotImplementedError):
+        LO.LocalCPM(S, 16, [], p=2)
+    with pytest.raises(NotImplementedError):
+        LO.LocalCPM(S, 16, [], band="stencil_set")
+    with pytest.raises(NotImplementedError):
+        LO.LocalCPM(S, 16, [G.LatitudeC(S, 0.3)], order=3)
