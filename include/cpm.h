@@ -348,19 +348,22 @@ cpm_status cpm_batch_solve(cpm_batch* batch, const cpm_solve_opts* opts,
 
 /* Autotuner: time every launch variant of cpm_apply for this band, dtype and
  * nrhs with HIP events, `reps` calls each, and keep the fastest for later
- * calls with this dtype.  Variant k = 2 * mode + pad: pad is the LDS line
- * padding of the staged cube (0: 1 element, 1: 4 elements); mode 0 visits
- * tiles and blocks in block order, mode 1 gives each XCD a contiguous range
- * of them, mode 2 runs the tile gather as persistent wavefronts over such
- * ranges (bands only; a batch's composite skips it and reports HUGE_VAL).
- * u and v are scratch device arrays [nrhs][n] of that dtype.  ms (may be
- * NULL) receives the 6 mean times per call; *best (may be NULL) the chosen
- * variant.  Synchronises the stream. */
+ * calls with this dtype.  Variant k = 8 lap + 2 mode + pad (0 <= k < 16):
+ * pad is the LDS line padding of the staged cube (0: 1 element, 1: 4
+ * elements); mode 0 visits tiles and blocks in block order, mode 1 gives each
+ * XCD a contiguous range of them, mode 2 runs the tile gather as persistent
+ * wavefronts over such ranges that request the next tile's metadata early,
+ * mode 3 also its staged values (modes 2 and 3 are for bands only: a batch's
+ * composite skips them and reports HUGE_VAL); lap 0 gathers every FD
+ * neighbour of the Laplacian pass from memory, lap 1 exchanges in-block
+ * neighbours between lanes.  u and v are scratch device arrays [nrhs][n] of
+ * that dtype.  ms (may be NULL) receives the 16 mean times per call; *best
+ * (may be NULL) the chosen variant.  Synchronises the stream. */
 cpm_status cpm_autotune(cpm_band* band, int dtype, int nrhs, const void* u,
                         void* v, int reps, void* hip_stream, double* ms,
                         int* best);
 
-/* Select launch variant k (numbered as by cpm_autotune, 0 <= k < 6) for
+/* Select launch variant k (numbered as by cpm_autotune, 0 <= k < 16) for
  * later calls on this band with this dtype, without timing anything; every
  * variant computes each output entry with the same arithmetic.  Returns
  * CPM_E_INVALID for a k out of range.  Touches no device memory. */

@@ -265,12 +265,14 @@ def apply_profile(band, u, m, n, reps=20):
 
 def autotune(band, dtype=torch.float64, nrhs=1, reps=10):
     """Pick the fastest apply launch variant for this band and dtype (kept in
-    the band).  Returns (times_ms[6], best): variant k = 2 * mode + pad (mode 0
-    block order, 1 XCD-aware order, 2 persistent XCD-aware tile gather)."""
+    the band).  Returns (times_ms[capi.TUNE_VARIANTS], best): variant
+    k = 8 lap + 2 mode + pad (mode 0 block order, 1 XCD-aware order, 2
+    persistent XCD-aware tile gather, 3 persistent and pipelined; lap 0 or 1
+    the two forms of the Laplacian pass)."""
     shape = (band.n,) if nrhs == 1 else (nrhs, band.n)
     u = torch.randn(shape, dtype=dtype, device="cuda")
     v = torch.empty_like(u)
-    ms = (C.c_double * 6)()
+    ms = (C.c_double * capi.TUNE_VARIANTS)()
     best = C.c_int()
     capi.check(band._lib.cpm_autotune(band.handle, _dtype_code(u), nrhs, _ptr(u), _ptr(v),
                                       int(reps), _stream(), ms, C.byref(best)))
@@ -486,7 +488,7 @@ class Batch:
         return v
 
     def autotune(self, dtype=torch.float64, reps=5):
-        ms = (C.c_double * 6)()
+        ms = (C.c_double * capi.TUNE_VARIANTS)()
         best = C.c_int()
         code = capi.F64 if dtype == torch.float64 else capi.F32
         capi.check(self._lib.cpm_batch_autotune(self.handle, code, int(reps), _stream(), ms,

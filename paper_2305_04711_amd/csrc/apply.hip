@@ -95,8 +95,8 @@ __device__ __forceinline__ void row_stencil(const TileView& tv, int pos, int lb[
 // ---------------------------------------------------------------- pass 1
 // Interpolation of one row from the staged cube (sum-factorised tensor
 // product): x lines first, then y, then z.  FP64 arithmetic.
-template <int DIM, int NR, int CSZ, int E, int EP>
-__device__ __forceinline__ void interp_row(const double (&s_u)[NR][CSZ], int p, const int lb[3],
+template <int DIM, int NR, int CSZ, int E, int EP, class TL>
+__device__ __forceinline__ void interp_row(const TL (&s_u)[NR][CSZ], int p, const int lb[3],
                                            const double tt[3], double acc[NR]) {
   double wx[4], wy[4], wz[4];
   lagrange_p<double>(p, tt[0], wx);
@@ -116,8 +116,9 @@ __device__ __forceinline__ void interp_row(const double (&s_u)[NR][CSZ], int p, 
         const int base = ((lz + c) * E + (ly + b)) * EP + lx;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-          const double* row = &s_u[r][base];
-          const double x = wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2] + wx[3] * row[3];
+          const TL* row = &s_u[r][base];
+          const double x = wx[0] * (double)row[0] + wx[1] * (double)row[1] +
+                           wx[2] * (double)row[2] + wx[3] * (double)row[3];
           accz[r] += wy[b] * x;
         }
       }
@@ -130,8 +131,9 @@ __device__ __forceinline__ void interp_row(const double (&s_u)[NR][CSZ], int p, 
       const int base = (ly + b) * EP + lx;
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        const double* row = &s_u[r][base];
-        const double x = wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2] + wx[3] * row[3];
+        const TL* row = &s_u[r][base];
+        const double x = wx[0] * (double)row[0] + wx[1] * (double)row[1] +
+                         wx[2] * (double)row[2] + wx[3] * (double)row[3];
         acc[r] += wy[b] * x;
       }
     }
@@ -141,9 +143,9 @@ __device__ __forceinline__ void interp_row(const double (&s_u)[NR][CSZ], int p, 
 // One wavefront per tile: stage the (2 BX)^d cube of u into LDS (x lines
 // padded by PAD elements to spread LDS banks), then each lane interpolates
 // rows of the tile.  The staged blocks' masks and first DOFs come from the
-// tile's metadata in one load.  u is stored in TS (FP64 or FP32) and staged
-// in FP64; weights, products and sums are FP64 and a is written in FP64 for
-// both storage precisions: the Laplacian pass differences neighbouring
+// tile's metadata in one load.  u is stored and staged in TS (FP64 or FP32:
+// an FP32 value is staged exactly); weights, products and sums are FP64 and
+// a is written in FP64 for both storage precisions: the Laplacian pass differences neighbouring
 // values of a and scales the difference by N^2, so a rounding of a to FP32
 // would be amplified by N^2 (on the smooth modes that converge last, a
 // relative error of order eps32 ||A|| / lambda_min in A u).
@@ -157,7 +159,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void k_
   using G = Geo<DIM>;
   constexpr int E = Cube<DIM>::E, EP = E + PAD, NQ = 1 << DIM;
   constexpr int CS = DIM == 3 ? E * E * EP : E * EP;
-  __shared__ double s_u[NR][CS];
+  __shared__ TS s_u[NR][CS];
   const int t = xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
   const int lane = threadIdx.x;
   if (tv.skip && tv.skip[tv.tile_inst[t]]) return;   // converged batch instance
@@ -185,7 +187,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void k_
     const bool on = (m >> lane) & 1ull;
     const int dof = off + __popcll(m & ((1ull << lane) - 1ull));
 #pragma unroll
-    for (int r = 0; r < NR; ++r) s_u[r][ci] = on ? (double)u[r * ld + dof] : 0.0;
+    for (int r = 0; r < NR; ++r) s_u[r][ci] = on ? u[r * ld + dof] : TS(0);
   }
   __syncthreads();
   for (int pos = beg + lane; pos < end; pos += 64) {
@@ -194,7 +196,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void k_
     const int dof = tv.perm[pos];
     if (pos + 64 < end) row_stencil<TS, DIM>(tv, pos + 64, lb, tt);
     double acc[NR];
-    interp_row<DIM, NR, CS, E, EP>(s_u, tv.p, lbc, tc, acc);
+    interp_row<DIM, NR, CS, E, EP, TS>(s_u, tv.p, lbc, tc, acc);
 #pragma unroll
     for (int r = 0; r < NR; ++r) a[r * ld + dof] = acc[r];
   }
@@ -212,7 +214,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void k_
   using G = Geo<DIM>;
   constexpr int E = Cube<DIM>::E, EP = E + PAD, NQ = 1 << DIM;
   constexpr int CS = DIM == 3 ? E * E * EP : E * EP;
-  __shared__ double s_u[NR][CS];
+  __shared__ TS s_u[NR][CS];
   const int lane = threadIdx.x;
   const int x = blockIdx.x & 7, wk = blockIdx.x >> 3, W = gridDim.x >> 3;
   const int q8 = ntiles >> 3, r8 = ntiles & 7;
@@ -263,7 +265,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void k_
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
 #pragma unroll
-      for (int r = 0; r < NR; ++r) s_u[r][sci[q]] = (double)sv[q][r];
+      for (int r = 0; r < NR; ++r) s_u[r][sci[q]] = sv[q][r];
     __syncthreads();
     for (int pos = beg + lane; pos < end; pos += 64) {
       const int lbc[3] = {lb[0], lb[1], lb[2]};
@@ -271,7 +273,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void k_
       const int dof = tv.perm[pos];
       if (pos + 64 < end) row_stencil<TS, DIM>(tv, pos + 64, lb, tt);
       double acc[NR];
-      interp_row<DIM, NR, CS, E, EP>(s_u, tv.p, lbc, tc, acc);
+      interp_row<DIM, NR, CS, E, EP, TS>(s_u, tv.p, lbc, tc, acc);
 #pragma unroll
       for (int r = 0; r < NR; ++r) a[r * ld + dof] = acc[r];
     }
@@ -281,6 +283,122 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void k_
     qoff = qoff_n;
     beg = beg_n;
     end = end_n;
+  }
+}
+
+// Persistent and pipelined form: as k_gather_ps, but the staging loads of a
+// wave's next tile (with that tile's first row data and the metadata of the
+// one after) are issued as soon as the current tile's cube is in LDS and its
+// first two passes of row data are requested, so they are in flight while
+// the current tile's rows are interpolated.  (Vector memory requests of a
+// wave complete in issue order, so everything the current tile waits for is
+// requested before the next tile's staging.)  A wave holds one tile's staged
+// values in registers at a time.
+template <class TS, int DIM, int NR, int PAD>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_gather_pp(
+    BlockView B, TileView tv, int N, const TS* __restrict__ u, double* __restrict__ a, int64_t ld,
+    int ntiles) {
+  using G = Geo<DIM>;
+  constexpr int E = Cube<DIM>::E, EP = E + PAD, NQ = 1 << DIM;
+  constexpr int CS = DIM == 3 ? E * E * EP : E * EP;
+  __shared__ TS s_u[NR][CS];
+  const int lane = threadIdx.x;
+  const int x = blockIdx.x & 7, wk = blockIdx.x >> 3, W = gridDim.x >> 3;
+  const int q8 = ntiles >> 3, r8 = ntiles & 7;
+  const int lo = x * q8 + (x < r8 ? x : r8), hi = lo + q8 + (x < r8 ? 1 : 0);
+  int t = lo + wk;
+  if (t >= hi) return;
+  const int cx0 = G::lx(lane), cy0 = G::ly(lane), cz0 = G::lz(lane);
+  int sci[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int qx = q & 1, qy = (q >> 1) & 1, qz = DIM == 3 ? (q >> 2) : 0;
+    const int cx = qx * G::BX + cx0, cy = qy * G::BX + cy0, cz = qz * G::BX + cz0;
+    sci[q] = DIM == 3 ? (cz * E + cy) * EP + cx : cy * EP + cx;
+  }
+  // staging values, first-pass row data and row range of tile tt
+  auto stage = [&](int tt, unsigned long long qm, int qoff, TS (&sv)[NQ][NR], int lb[3],
+                   double t3[3], int& dof, int& beg, int& end) {
+    beg = tv.tile_start[tt];
+    end = tv.tile_start[tt + 1];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const unsigned long long m = lane_u64(qm, q);
+      const int off = lane_i32(qoff, q);
+      const bool on = (m >> lane) & 1ull;
+      const int d = off + __popcll(m & ((1ull << lane) - 1ull));
+#pragma unroll
+      for (int r = 0; r < NR; ++r) sv[q][r] = on ? u[r * ld + d] : TS(0);
+    }
+    lb[0] = lb[1] = lb[2] = 0;
+    t3[0] = t3[1] = t3[2] = 0.0;
+    dof = -1;
+    if (beg + lane < end) {
+      row_stencil<TS, DIM>(tv, beg + lane, lb, t3);
+      dof = tv.perm[beg + lane];
+    }
+  };
+  auto meta = [&](int tt, unsigned long long& qm, int& qoff) {
+    qm = 0ull;
+    qoff = 0;
+    if (tt < hi && lane < NQ) {
+      const QMeta q = tv.meta[(int64_t)tt * 8 + lane];
+      qm = q.mask;
+      qoff = q.off;
+    }
+  };
+  auto rows = [&](const int lbr[3], const double tr[3], int dof) {
+    double acc[NR];
+    interp_row<DIM, NR, CS, E, EP, TS>(s_u, tv.p, lbr, tr, acc);
+    if (dof >= 0) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) a[r * ld + dof] = acc[r];
+    }
+  };
+  unsigned long long qm;
+  int qoff;
+  meta(t, qm, qoff);
+  TS sv[NQ][NR];
+  int lb[3], dof, beg, end;
+  double t3[3];
+  stage(t, qm, qoff, sv, lb, t3, dof, beg, end);
+  meta(t + W, qm, qoff);
+  while (true) {
+    __syncthreads();   // the previous tile's rows are done with the cube
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) s_u[r][sci[q]] = sv[q][r];
+    __syncthreads();
+    const int lb1[3] = {lb[0], lb[1], lb[2]};
+    const double t1[3] = {t3[0], t3[1], t3[2]};
+    const int dof1 = dof, cbeg = beg, cend = end;
+    // the second pass's row data before the next tile's staging
+    int lb2[3] = {0, 0, 0}, dof2 = -1;
+    double t2[3] = {0.0, 0.0, 0.0};
+    if (cbeg + 64 + lane < cend) {
+      row_stencil<TS, DIM>(tv, cbeg + 64 + lane, lb2, t2);
+      dof2 = tv.perm[cbeg + 64 + lane];
+    }
+    const int tn = t + W;
+    const bool more = tn < hi;
+    if (more) {
+      stage(tn, qm, qoff, sv, lb, t3, dof, beg, end);
+      meta(tn + W, qm, qoff);
+    }
+    if (cbeg < cend) rows(lb1, t1, dof1);
+    if (cbeg + 64 < cend) rows(lb2, t2, dof2);
+    for (int pos = cbeg + 128 + lane; pos - lane < cend; pos += 64) {
+      int lbr[3] = {0, 0, 0}, dr = -1;
+      double tr[3] = {0.0, 0.0, 0.0};
+      if (pos < cend) {
+        row_stencil<TS, DIM>(tv, pos, lbr, tr);
+        dr = tv.perm[pos];
+      }
+      rows(lbr, tr, dr);
+    }
+    if (!more) break;
+    t = tn;
   }
 }
 
@@ -330,6 +448,12 @@ __global__ __launch_bounds__(256) void k_gather_rows(int nrows, int nm, const in
 }
 
 // ---------------------------------------------------------------- pass 2
+// cd u + co s with one explicit rounding order, shared by both forms of the
+// pass so that they agree bit for bit whatever the compiler contracts.
+__device__ __forceinline__ double lap_out(double cd, double u, double co, double s) {
+  return __fma_rn(co, s, cd * u);
+}
+
 // v = cd u + co sum_nbr a (+ gauge); lane = slot; each wavefront handles KB
 // consecutive blocks so that their loads are in flight together.  Lanes
 // 8j..8j+7 load block j's metadata (its own and its face neighbours' masks
@@ -422,7 +546,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 #pragma unroll
     for (int j = 0; j < KB; ++j) {
       if (dof[j] < 0) continue;
-      double o = cdj[j] * uv[j] + coj[j] * s[j];
+      double o = lap_out(cdj[j], uv[j], coj[j], s[j]);
       if (gsum) o += gscale * gsum[0];
       const TV ov = (TV)o;
       v[dof[j]] = ov;
@@ -441,7 +565,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
       for (int f = 0; f < 2 * DIM; ++f)
         if (dof[j] >= 0 && nd[j][f] >= 0) s += (double)a[r * ld + nd[j][f]];
       if constexpr (ALL) out[j] = coj[j] * s;
-      else out[j] = dof[j] >= 0 ? cdj[j] * (double)u[r * ld + dof[j]] + coj[j] * s : 0.0;
+      else out[j] = dof[j] >= 0 ? lap_out(cdj[j], (double)u[r * ld + dof[j]], coj[j], s) : 0.0;
     }
 #pragma unroll
     for (int j = 0; j < KB; ++j) {
@@ -451,6 +575,127 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
       v[r * ld + dof[j]] = (TV)o;
     }
   }
+}
+
+// The same pass with neighbour values exchanged between lanes: each lane
+// loads u and a of its own slot (one coalesced load each: a block's DOFs are
+// contiguous), takes the values of in-block face neighbours from the lanes
+// holding them (cross-lane moves; an absent slot holds 0, which drops that
+// neighbour as the pass requires), and only the lanes on a block face load
+// the neighbour across it.  Fewer and narrower memory requests per block
+// than k_lap, which gathers every neighbour from memory.
+template <class T>
+__device__ __forceinline__ T lane_take(T v, int src) {
+  if constexpr (sizeof(T) == 8) {
+    const long long b = __double_as_longlong((double)v);
+    const int lo = __shfl((int)(unsigned)(b & 0xffffffffll), src, 64);
+    const int hi = __shfl((int)(b >> 32), src, 64);
+    return (T)__longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+  } else {
+    return __shfl(v, src, 64);
+  }
+}
+
+constexpr int kLapShBlocksPerWave = 1;
+
+template <class TU, class TA, class TV, int DIM, bool ALL, bool DOT = false>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_lap_sh(
+    BlockView B, const TU* __restrict__ u, const TA* __restrict__ a, TV* __restrict__ v,
+    int64_t ld, int nrhs, double cd, double co, const double* __restrict__ gsum, double gscale,
+    int xcd, const double* __restrict__ coef, const int* __restrict__ skip,
+    const TV* __restrict__ dy = nullptr, double* __restrict__ dpart = nullptr, int dnp = 0) {
+  using G = Geo<DIM>;
+  constexpr int KB = kLapShBlocksPerWave;
+  const int wg = xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int blk0 = (wg * 4 + (threadIdx.x >> 6)) * KB;
+  const int slot = threadIdx.x & 63;
+  if (!DOT && blk0 >= B.nb) return;
+  unsigned long long lm = 0ull;
+  int loff = 0, lpad = 0;
+  {
+    const int j = slot >> 3, e = slot & 7;
+    if (j < KB && blk0 + j < B.nb) {
+      const QMeta q = B.face[(int64_t)(blk0 + j) * 8 + e];
+      lm = q.mask;
+      loff = q.off;
+      lpad = q.pad;
+    }
+  }
+  const int l[3] = {G::lx(slot), G::ly(slot), G::lz(slot)};
+  double cdj[KB], coj[KB];
+  int own[KB], outr[KB], nsrc[KB][2 * DIM];
+#pragma unroll
+  for (int j = 0; j < KB; ++j) {
+    cdj[j] = cd;
+    coj[j] = co;
+    bool skipj = false;
+    if (coef) {
+      const int inst = lane_i32(lpad, 8 * j + 7);
+      const int ii = inst > 0 ? inst : 0;
+      cdj[j] = coef[2 * ii];
+      coj[j] = coef[2 * ii + 1];
+      skipj = skip && skip[ii];
+    }
+    const unsigned long long m = lane_u64(lm, 8 * j);
+    const int off0 = lane_i32(loff, 8 * j);
+    const unsigned long long xm = lane_u64(lm, 8 * j + 7);
+    const bool present = ((m >> slot) & 1ull) && !skipj;
+    own[j] = present ? off0 + __popcll(m & ((1ull << slot) - 1ull)) : -1;
+    outr[j] = (present && (ALL || !((xm >> slot) & 1ull))) ? own[j] : -1;
+    // per face: the lane to take the value from (in-block), or the DOF to
+    // load across the face (encoded as -2 - dof), or -1 (no neighbour)
+#pragma unroll
+    for (int f = 0; f < 2 * DIM; ++f) {
+      int q[3] = {l[0], l[1], l[2]};
+      q[f >> 1] += (f & 1) ? 1 : -1;
+      const bool out = q[f >> 1] < 0 || q[f >> 1] >= G::BX;
+      q[f >> 1] &= G::BX - 1;
+      const int s2 = G::slot(q[0], q[1], q[2]);
+      if (!out) {
+        nsrc[j][f] = s2;
+      } else {
+        const unsigned long long fmk = lane_u64(lm, 8 * j + f + 1);
+        const int fof = lane_i32(loff, 8 * j + f + 1);
+        nsrc[j][f] = ((fmk >> s2) & 1ull) ? -2 - (fof + __popcll(fmk & ((1ull << s2) - 1ull)))
+                                          : -1;
+      }
+    }
+  }
+  double d0 = 0.0, d1 = 0.0;
+  for (int r = 0; r < (DOT ? 1 : nrhs); ++r) {
+    const TA* ar = a + r * ld;
+    TA aown[KB];
+    double uv[KB], yv[KB], across[KB][2 * DIM];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      aown[j] = own[j] >= 0 ? ar[own[j]] : TA(0);
+      uv[j] = (!ALL && outr[j] >= 0) ? (double)u[r * ld + outr[j]] : 0.0;
+      yv[j] = (DOT && outr[j] >= 0) ? (double)dy[outr[j]] : 0.0;
+#pragma unroll
+      for (int f = 0; f < 2 * DIM; ++f)
+        across[j][f] = (outr[j] >= 0 && nsrc[j][f] <= -2) ? (double)ar[-2 - nsrc[j][f]] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      double sum = 0.0;
+#pragma unroll
+      for (int f = 0; f < 2 * DIM; ++f) {
+        const int src = nsrc[j][f] >= 0 ? nsrc[j][f] : slot;
+        const double inb = (double)lane_take<TA>(aown[j], src);
+        sum += nsrc[j][f] >= 0 ? inb : across[j][f];
+      }
+      if (outr[j] < 0) continue;
+      double o = ALL ? coj[j] * sum : lap_out(cdj[j], uv[j], coj[j], sum);
+      if (gsum) o += gscale * gsum[r];
+      const TV ov = (TV)o;
+      v[r * ld + outr[j]] = ov;
+      if (DOT) {
+        d0 += yv[j] * (double)ov;
+        d1 += (double)ov * (double)ov;
+      }
+    }
+  }
+  if constexpr (DOT) wave_dot2(d0, d1, dpart, dnp, blockIdx.x * 4);
 }
 
 template <class TS, bool DOT = false>
@@ -475,7 +720,7 @@ __global__ void k_lap_rows(int nrows, int nf, const int* __restrict__ row_id,
         const int c = col[i * nf + f];
         if (c >= 0) s += a[r * ld + c];
       }
-      double out = cd * (double)u[r * ld + id] + co * s;
+      double out = lap_out(cd, (double)u[r * ld + id], co, s);
       if (gsum) out += gscale * gsum[r];
       const TS ov = (TS)out;
       v[r * ld + id] = ov;
@@ -838,8 +1083,21 @@ static const Tune& tune_of(const cpm_band* b) {
 
 template <class T, int DIM, int PAD>
 static void launch_gather_k(const cpm_band* b, int k, const T* ur, double* ar, int64_t ld,
-                            int xcd, bool ps, hipStream_t st) {
+                            int xcd, int ps, hipStream_t st) {
   const dim3 g(b->ntiles), t(64);
+  if (ps == 2 && !b->tile_inst) {
+    int64_t gp = ((int64_t)b->ntiles + 7) / 8 * 8;
+    if (gp > 8 * (int64_t)kPersistWavesPerXcd) gp = 8 * (int64_t)kPersistWavesPerXcd;
+    const dim3 gq((unsigned)gp);
+    switch (k) {
+      case 1: hipLaunchKernelGGL((k_gather_pp<T, DIM, 1, PAD>), gq, t, 0, st, bview(b), tview(b), b->N, ur, ar, ld, b->ntiles); break;
+      case 2: hipLaunchKernelGGL((k_gather_pp<T, DIM, 2, PAD>), gq, t, 0, st, bview(b), tview(b), b->N, ur, ar, ld, b->ntiles); break;
+      case 3: hipLaunchKernelGGL((k_gather_pp<T, DIM, 3, PAD>), gq, t, 0, st, bview(b), tview(b), b->N, ur, ar, ld, b->ntiles); break;
+      default: hipLaunchKernelGGL((k_gather_pp<T, DIM, 4, PAD>), gq, t, 0, st, bview(b), tview(b), b->N, ur, ar, ld, b->ntiles); break;
+    }
+    CPM_LAUNCH_CHECK();
+    return;
+  }
   if (ps && !b->tile_inst) {
     // a multiple of 8 wavefronts: every XCD gets the same number
     int64_t gp = ((int64_t)b->ntiles + 7) / 8 * 8;
@@ -874,8 +1132,8 @@ static void launch_gather(const cpm_band* b, int nrhs, const T* u, double* a, hi
     double* ar = a + r * ld;
     if (b->ntiles) {
       const Tune& tn = tune_of<T>(b);
-      if (tn.pad) launch_gather_k<T, DIM, 4>(b, k, ur, ar, ld, tn.xcd, tn.ps != 0, st);
-      else launch_gather_k<T, DIM, 1>(b, k, ur, ar, ld, tn.xcd, tn.ps != 0, st);
+      if (tn.pad) launch_gather_k<T, DIM, 4>(b, k, ur, ar, ld, tn.xcd, tn.ps, st);
+      else launch_gather_k<T, DIM, 1>(b, k, ur, ar, ld, tn.xcd, tn.ps, st);
     }
     r += k;
   }
@@ -890,18 +1148,36 @@ static void launch_gather(const cpm_band* b, int nrhs, const T* u, double* a, hi
   if (ev) CPM_HIP(hipEventRecord(ev[2], st));
 }
 
-static int lap_groups(const cpm_band* b) {
-  return (b->nb + 4 * kLapBlocksPerWave - 1) / (4 * kLapBlocksPerWave);
+static int lap_groups(const cpm_band* b, const Tune& tn) {
+  const int kb = tn.lap ? kLapShBlocksPerWave : kLapBlocksPerWave;
+  return (b->nb + 4 * kb - 1) / (4 * kb);
 }
 static int lap_row_groups(const cpm_band* b) {
   return b->n_lrows ? grid_for(b->n_lrows, 128) : 0;
 }
 
 // Number of partials a fused dot product of an apply writes (per value): one
-// per wavefront of the kernel that writes the output.
-int apply_dot_parts(const cpm_band* b, bool transpose) {
+// per wavefront of the kernel that writes the output, for the launch variant
+// the band is tuned to in that precision.
+int apply_dot_parts(const cpm_band* b, bool transpose, bool f32) {
   if (transpose) return 4 * grid_for(b->n, 256);
-  return 4 * lap_groups(b) + 2 * lap_row_groups(b);
+  return 4 * lap_groups(b, b->tune[f32 ? 1 : 0]) + 2 * lap_row_groups(b);
+}
+
+// The Laplacian pass in the band's tuned form (k_lap or k_lap_sh).
+template <class TU, class TA, class TV, int DIM, bool ALL, bool DOT>
+static void launch_lap(const cpm_band* b, const Tune& tn, hipStream_t st, const TU* u,
+                       const TA* a, TV* v, int64_t ld, int nrhs, double cd, double co,
+                       const double* gsum, double gscale, const double* coef, const int* skip,
+                       const TV* dy, double* dpart, int dnp) {
+  const dim3 g(lap_groups(b, tn)), t(256);
+  if (tn.lap)
+    hipLaunchKernelGGL((k_lap_sh<TU, TA, TV, DIM, ALL, DOT>), g, t, 0, st, bview(b), u, a, v, ld,
+                       nrhs, cd, co, gsum, gscale, tn.xcd, coef, skip, dy, dpart, dnp);
+  else
+    hipLaunchKernelGGL((k_lap<TU, TA, TV, DIM, ALL, DOT>), g, t, 0, st, bview(b), u, a, v, ld,
+                       nrhs, cd, co, gsum, gscale, tn.xcd, coef, skip, dy, dpart, dnp);
+  CPM_LAUNCH_CHECK();
 }
 
 // Bytes of scratch one forward apply of nrhs right-hand sides needs: the
@@ -924,16 +1200,15 @@ static void apply_dim(const cpm_band* b, double m, double n, int nrhs, const T* 
   const double cd = m + n * (-2.0 * DIM * N2);
   const double co = n * N2;
   const double gscale = gsum ? gamma / (double)b->n_s : 0.0;
-  const int g1 = lap_groups(b), g2 = lap_row_groups(b), np = 4 * g1 + 2 * g2;
+  const int g1 = lap_groups(b, tune_of<T>(b)), g2 = lap_row_groups(b), np = 4 * g1 + 2 * g2;
   if (dy)
-    hipLaunchKernelGGL((k_lap<T, double, T, DIM, false, true>), dim3(g1), dim3(256), 0, st,
-                       bview(b), u, a, v, ld, nrhs, cd, co, gsum, gscale, tune_of<T>(b).xcd,
-                       b->inst_coef, b->inst_skip, dy, dpart, np);
+    launch_lap<T, double, T, DIM, false, true>(b, tune_of<T>(b), st, u, a, v, ld, nrhs, cd, co,
+                                               gsum, gscale, b->inst_coef, b->inst_skip, dy,
+                                               dpart, np);
   else
-    hipLaunchKernelGGL((k_lap<T, double, T, DIM, false>), dim3(g1), dim3(256), 0, st, bview(b),
-                       u, a, v, ld, nrhs, cd, co, gsum, gscale, tune_of<T>(b).xcd, b->inst_coef,
-                       b->inst_skip, nullptr, nullptr, 0);
-  CPM_LAUNCH_CHECK();
+    launch_lap<T, double, T, DIM, false, false>(b, tune_of<T>(b), st, u, a, v, ld, nrhs, cd, co,
+                                                gsum, gscale, b->inst_coef, b->inst_skip,
+                                                nullptr, nullptr, 0);
   if (ev) CPM_HIP(hipEventRecord(ev[3], st));
   if (b->n_lrows) {
     if (dy)
@@ -994,10 +1269,8 @@ static void apply_T_dim(const cpm_band* b, double m, double n, int nrhs, const T
     for (int r = 0; r < nrhs; ++r)
       hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(b->n_c, 256, 4096)), dim3(256), 0, st,
                          c + r * ld + b->n_s, (int64_t)b->n_c, 0.0);
-  hipLaunchKernelGGL((k_lap<T, T, double, DIM, true>), dim3(lap_groups(b)), dim3(256), 0, st,
-                     bview(b), w, w, c, ld, nrhs, 0.0, co, nullptr, 0.0, tune_of<T>(b).xcd,
-                     nullptr, nullptr);
-  CPM_LAUNCH_CHECK();
+  launch_lap<T, T, double, DIM, true, false>(b, tune_of<T>(b), st, w, w, c, ld, nrhs, 0.0, co,
+                                             nullptr, 0.0, nullptr, nullptr, nullptr, nullptr, 0);
   if (b->lt_tgt) {
     if (b->n_lt) {
       hipLaunchKernelGGL(k_lt_pull<T>, dim3(grid_for(b->n_lt, 256)), dim3(256), 0, st, b->n_lt,
@@ -1144,9 +1417,7 @@ extern "C" cpm_status cpm_autotune(cpm_band* b, int dtype, int nrhs, const void*
     int arg = 0;
     try {
       for (int k = 0; k < kTuneVariants; ++k) {
-        tn.pad = k & 1;
-        tn.xcd = (k >> 1) != 0;
-        tn.ps = (k >> 1) == 2;
+        tn = tune_variant(k);
         if (tn.ps && b->tile_inst) {   // composites run the non-persistent gather
           t[k] = HUGE_VAL;
           continue;
@@ -1173,10 +1444,7 @@ extern "C" cpm_status cpm_autotune(cpm_band* b, int dtype, int nrhs, const void*
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    tn.pad = arg & 1;
-    tn.xcd = (arg >> 1) != 0;
-    tn.ps = (arg >> 1) == 2;
-    tn.tuned = 1;
+    tn = tune_variant(arg);
     if (ms)
       for (int k = 0; k < kTuneVariants; ++k) ms[k] = t[k];
     if (best) *best = arg;
@@ -1189,11 +1457,7 @@ extern "C" cpm_status cpm_tune_set(cpm_band* b, int dtype, int variant) {
     if (dtype != CPM_F64 && dtype != CPM_F32) CPM_FAIL(CPM_E_INVALID, "unknown dtype %d", dtype);
     if (variant < 0 || variant >= kTuneVariants)
       CPM_FAIL(CPM_E_INVALID, "launch variant %d out of range [0, %d)", variant, kTuneVariants);
-    Tune& tn = b->tune[dtype == CPM_F64 ? 0 : 1];
-    tn.pad = variant & 1;
-    tn.xcd = (variant >> 1) != 0;
-    tn.ps = (variant >> 1) == 2;
-    tn.tuned = 1;
+    b->tune[dtype == CPM_F64 ? 0 : 1] = tune_variant(variant);
   });
 }
 

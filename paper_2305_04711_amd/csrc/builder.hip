@@ -455,6 +455,44 @@ __global__ __launch_bounds__(256) void k_tile_fill(Blocks B, int nb, int N, int6
   lbase[pos] = lx | (ly << 8) | (lz << 16);
 }
 
+// Rows that share a tile and a stencil base land in their bucket in the
+// order k_tile_fill's atomics gave them; sort each bucket by DOF so that the
+// tile order (and with it the summation order of the transposed apply's
+// run sums) is the same on every build.  Buckets hold a few rows (the nodes
+// along one normal line), so one thread per bucket sorts by insertion.
+template <int DIM>
+__global__ void k_tile_sort_buckets(int64_t nbk, const int* cnt, const int* end, int ntr,
+                                    int* perm, double* frac64, float* frac32) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nbk;
+       k += (int64_t)gridDim.x * blockDim.x) {
+  if (cnt[k] < 2) continue;
+  const int e = end[k], s = e - cnt[k];
+  for (int i = s + 1; i < e; ++i) {
+    const int key = perm[i];
+    double f64[3];
+    float f32[3];
+    for (int a = 0; a < DIM; ++a) {
+      f64[a] = frac64[(int64_t)a * ntr + i];
+      f32[a] = frac32[(int64_t)a * ntr + i];
+    }
+    int j = i - 1;
+    while (j >= s && perm[j] > key) {
+      perm[j + 1] = perm[j];
+      for (int a = 0; a < DIM; ++a) {
+        frac64[(int64_t)a * ntr + j + 1] = frac64[(int64_t)a * ntr + j];
+        frac32[(int64_t)a * ntr + j + 1] = frac32[(int64_t)a * ntr + j];
+      }
+      --j;
+    }
+    perm[j + 1] = key;
+    for (int a = 0; a < DIM; ++a) {
+      frac64[(int64_t)a * ntr + j + 1] = f64[a];
+      frac32[(int64_t)a * ntr + j + 1] = f32[a];
+    }
+  }
+  }
+}
+
 __global__ void k_tile_compact(const int* cnt, const int* off, const int* tidx, int nb,
                                int* tile_blk, int* tile_start) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1280,6 +1318,10 @@ void build(cpm_band* b, hipStream_t st, const Filter& F) {
       hipLaunchKernelGGL(k_tile_fill<DIM>, gnode, dim3(256), 0, st, B, nb, N, n_s, b->cp,
                          eflag.p, tile_blk_of.p, pos2.p, ntr, b->perm, b->frac64, b->frac32,
                          b->lbase);
+      CPM_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_tile_sort_buckets<DIM>, dim3(grid_for((int64_t)nb * 64, 256)),
+                         dim3(256), 0, st, (int64_t)nb * 64, cnt2.p, pos2.p, ntr, b->perm,
+                         b->frac64, b->frac32);
       CPM_LAUNCH_CHECK();
       CPM_HIP(hipStreamSynchronize(st));
     }

@@ -103,10 +103,26 @@ struct QMeta {
 struct Tune {
   int pad = 1;     // LDS x-line stride of the staged cube: 0 -> E + 1, 1 -> E + 4
   int xcd = 1;     // map consecutive tiles / blocks to one XCD
-  int ps = 0;      // tile gather as persistent wavefronts (implies xcd)
+  int ps = 0;      // tile gather as persistent wavefronts (implies xcd): 1
+                   // prefetches the next tile's metadata, 2 also its staging
+  int lap = 0;     // Laplacian pass: 0 gathers every neighbour, 1 exchanges
+                   // in-block neighbours between lanes
   int tuned = 0;
 };
-constexpr int kTuneVariants = 6;
+// variant k: pad = k & 1, order mode = (k >> 1) & 3 (0 block order, 1
+// XCD-aware, 2 persistent XCD-aware gather, 3 persistent and pipelined),
+// lap = k >> 3
+constexpr int kTuneVariants = 16;
+inline Tune tune_variant(int k) {
+  Tune t;
+  t.pad = k & 1;
+  const int mode = (k >> 1) & 3;
+  t.xcd = mode != 0;
+  t.ps = mode >= 2 ? mode - 1 : 0;
+  t.lap = k >> 3;
+  t.tuned = 1;
+  return t;
+}
 // Persistent tile gather: wavefronts per XCD (8 per SIMD at most are resident)
 constexpr int kPersistWavesPerXcd = 4096;
 
@@ -251,7 +267,7 @@ void apply_transpose_impl(const cpm_band* b, double m, double n, int nrhs,
                           const T* w, T* z, hipStream_t s,
                           const double* gauge_sum = nullptr, double gamma = 0.0,
                           const T* dy = nullptr, double* dpart = nullptr);
-int apply_dot_parts(const cpm_band* b, bool transpose);
+int apply_dot_parts(const cpm_band* b, bool transpose, bool f32);
 // bytes of the forward apply's scratch vector (the FP64 intermediate a = E u)
 size_t apply_scratch_bytes(const cpm_band* b, int nrhs);
 // out -= n (L - diag L) e(g): the Dirichlet part of a right-hand side

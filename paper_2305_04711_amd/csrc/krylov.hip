@@ -426,7 +426,7 @@ struct Bicg {
     t = (T*)band_scratch(b, slot0 + 5, vb);
     part = (double*)band_scratch(b, slot0 + 6, sizeof(double) * 2 * kMaxParts);
     S = (Scal*)band_scratch(b, slot0 + 7, sizeof(Scal));
-    dnp = apply_dot_parts(b, tr);
+    dnp = apply_dot_parts(b, tr, sizeof(T) == 4);
     dpart = (double*)band_scratch(b, slot0 + 8, sizeof(double) * 2 * (size_t)dnp);
     fin_g = (int)std::max<int64_t>(1, std::min<int64_t>(256, (dnp + 1023) / 1024));
     CPM_HIP(hipMemsetAsync(S, 0, sizeof(Scal), st));
@@ -713,21 +713,28 @@ enum { RU_CONVERGED = 0, RU_STALLED = 1, RU_MAXIT = 2 };
 // residual reaches tol.  The recurrence solves A d = r / sigma and keeps its
 // partial solution d in TX (FP64 for the mixed solve).  An update happens
 // when the recursive residual has dropped by delta since the last one, when
-// the recurrence stops (converged or broken down), or after max_cycle
-// iterations without either.  It adds sigma d into x, recomputes r = b - A x
-// in FP64 and substitutes it for the recursive residual (k_replace), so the
-// recurrence goes on with the true residual and keeps its Krylov space.  The
-// run ends (RU_STALLED) at the first update that follows a breakdown or fails
-// to halve the FP64 residual of the previous update; an update that left the
-// FP64 residual above the previous one is taken back first, so x is the best
-// iterate of the run.
+// the recurrence stops (converged or broken down), when its residual has
+// grown kBlowup-fold over the last true one, or after max_cycle iterations
+// without any of these.  It adds sigma d into x and recomputes r = b - A x in
+// FP64.  An update that halves the FP64 residual of the previous one replaces
+// the recursive residual by the true one (k_replace): the recurrence goes on
+// and keeps its Krylov space.  An update that follows a breakdown or growth,
+// or does not halve the residual, restarts the recurrence from the current x
+// (a new shadow residual r_hat = r, as Eigen's BiCGSTAB restarts on a
+// vanishing rho); an update that raised the FP64 residual is taken back
+// first, so x is always the best iterate.  The run ends (RU_STALLED) when
+// max_restarts restarts are spent or a restart has not halved the residual
+// by the next one.  rT is the precision-T copy of the scaled residual a
+// restart starts from.
+constexpr double kBlowup = 1e3;
+
 template <class T, class TX>
-int ru_run(RU& c, Bicg<T, TX>& k, TX* d, double rn, int max_cycle) {
+int ru_run(RU& c, Bicg<T, TX>& k, TX* d, T* rT, double rn, int max_cycle, int max_restarts) {
   const int64_t n = c.b->n;
   const double inv = 1.0 / c.sigma;
   const int eg = grid_for(n, 256, 4096);
-  double maxr = rn * inv, prev = rn;
-  int last = k.read().it, cycle0 = last;
+  double maxr = rn * inv, base = maxr, prev = rn, at_restart = rn;
+  int last = k.read().it, cycle0 = last, restarts = 0;
   while (c.its < c.maxit) {
     const int kk = std::min(c.ce, c.maxit - c.its);
     k.run_iters(d, kk, c.graph && kk == c.ce);
@@ -735,37 +742,60 @@ int ru_run(RU& c, Bicg<T, TX>& k, TX* d, double rn, int max_cycle) {
     c.its += h.it - last;
     last = h.it;
     const double rrec = std::sqrt(h.rr);
-    const bool bad = !__builtin_isfinite(h.rr);
+    const bool bad = !std::isfinite(h.rr);
+    const bool blowup = !bad && rrec > kBlowup * base;
     if (!bad) maxr = std::max(maxr, rrec);
     const bool forced = h.it - cycle0 >= max_cycle;
-    if (!(h.done || bad || rrec < c.delta * maxr || forced)) continue;
-    const bool broken = h.breakdown || bad;
+    if (!(h.done || bad || blowup || rrec < c.delta * maxr || forced)) continue;
+    const bool broken = h.breakdown || bad || blowup;
     if (!bad) {   // a non-finite recursion leaves x as it was at the last update
       hipLaunchKernelGGL(k_addT<TX>, dim3(eg), dim3(256), 0, c.st, n, c.x, d, c.sigma);
       CPM_LAUNCH_CHECK();
     }
-    auto rb = c.residual();
-    rn = rb.first;
+    rn = c.residual().first;
     c.stt->relres = rn / c.bn;
     ++c.stt->outer_iters;
     if (trace_on())
-      std::fprintf(stderr, "[cpm] %s update %d: recursive %.3e true relres %.3e its %d%s%s\n",
+      std::fprintf(stderr, "[cpm] %s update %d: recursive %.3e true relres %.3e its %d%s%s%s\n",
                    sizeof(T) == 4 ? "FP32" : "FP64", c.stt->outer_iters, rrec * c.sigma / c.bn,
-                   c.stt->relres, c.its, broken ? " (breakdown)" : "", forced ? " (forced)" : "");
+                   c.stt->relres, c.its, h.breakdown ? " (breakdown)" : "",
+                   blowup || bad ? " (growth)" : "", forced ? " (forced)" : "");
     if (c.stt->relres <= c.tol) return RU_CONVERGED;
-    if (!__builtin_isfinite(rn) || !(rn <= prev)) {
+    bool stale = false;   // r64 no longer holds the residual of x
+    if (!std::isfinite(rn) || !(rn <= prev)) {
       if (!bad) {   // take the update back
         hipLaunchKernelGGL(k_addT<TX>, dim3(eg), dim3(256), 0, c.st, n, c.x, d, -c.sigma);
         CPM_LAUNCH_CHECK();
       }
+      rn = prev;
       c.stt->relres = prev / c.bn;
-      return RU_STALLED;
+      stale = true;
     }
-    if (broken || !(rn < 0.5 * prev)) return RU_STALLED;
-    prev = rn;
-    maxr = rn * inv;
-    cycle0 = h.it;
-    k.replace(c.r64, inv, d);
+    if (!broken && rn < 0.5 * prev) {   // reliable update: keep the recurrence
+      prev = rn;
+      maxr = base = rn * inv;
+      cycle0 = h.it;
+      k.replace(c.r64, inv, d);
+      continue;
+    }
+    // restart from the best x with a fresh recurrence (new shadow residual)
+    if (restarts >= max_restarts || !(rn < 0.5 * at_restart)) return RU_STALLED;
+    ++restarts;
+    ++c.stt->restarts;
+    prev = at_restart = rn;
+    if (stale) {
+      rn = c.residual().first;
+      c.stt->relres = rn / c.bn;
+    }
+    if (trace_on())
+      std::fprintf(stderr, "[cpm] %s restart %d from relres %.3e\n", sizeof(T) == 4 ? "FP32" : "FP64",
+                   restarts, rn / c.bn);
+    hipLaunchKernelGGL((k_scaleT<T, TX>), dim3(eg), dim3(256), 0, c.st, n, c.r64, inv, rT, d);
+    hipLaunchKernelGGL(k_zero_scal, dim3(1), dim3(64), 0, c.st, k.S);
+    CPM_LAUNCH_CHECK();
+    k.init(rT, nullptr, true, 0.5 * c.tol * c.bn / rn);
+    last = cycle0 = 0;
+    maxr = base = rn * inv;
   }
   return RU_MAXIT;
 }
@@ -863,7 +893,7 @@ void solve_one(const cpm_band* b, const cpm_solve_opts& o, const double* rhs, do
     hipLaunchKernelGGL(k_zero_scal, dim3(1), dim3(64), 0, st, k32.S);
     CPM_LAUNCH_CHECK();
     k32.init(r32, nullptr, true, 0.5 * tol * c.bn * inv);
-    const int status = ru_run<float, double>(c, k32, d64, rn, 1000);
+    const int status = ru_run<float, double>(c, k32, d64, r32, rn, 1000, 10);
     its += c.its;
     if (status == RU_CONVERGED) return true;
     if (status == RU_MAXIT) return false;

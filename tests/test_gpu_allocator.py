@@ -12,7 +12,12 @@ from paper_2305_04711_amd import capi, cpm
 
 pytestmark = pytest.mark.gpu
 
-ROUND = 512          # the torch caching allocator rounds blocks to 512 bytes
+
+def _slack(nbytes):
+    """Bytes the torch caching allocator may count above the requested ones:
+    blocks are rounded to 512 bytes, and a large block is not split when the
+    rest would be under 1 MiB, so the whole block counts."""
+    return 0.10 * nbytes + (4 << 20)
 
 
 @pytest.fixture(scope="module")
@@ -32,7 +37,7 @@ def test_band_memory_comes_from_torch_and_returns(torch_cuda):
     grown = torch.cuda.memory_allocated() - base
     print("band arrays", arrays, "torch growth", grown, flush=True)
     assert scratch == 0
-    assert arrays <= grown <= arrays + 128 * ROUND
+    assert arrays <= grown <= arrays + _slack(arrays)
     # an apply and a solve grow the band's scratch through the same pool
     u = torch.randn(band.n, dtype=torch.float64, device="cuda")
     v = cpm.apply(band, u, 0.0, -1.0)
@@ -41,7 +46,7 @@ def test_band_memory_comes_from_torch_and_returns(torch_cuda):
     arrays2, scratch2 = band.memory()
     assert arrays2 == arrays and scratch2 >= 8 * band.n
     held = torch.cuda.memory_allocated() - base - (u.numel() + v.numel() + x.numel()) * 8
-    assert arrays + scratch2 <= held <= arrays + scratch2 + 256 * ROUND
+    assert arrays + scratch2 <= held <= arrays + scratch2 + _slack(arrays + scratch2)
     del x, v, u
     band.close()
     torch.cuda.synchronize()

@@ -19,7 +19,7 @@ import pytest
 from closed_forms import latitude_harmonic
 from oracle import geometry as G
 from oracle import local as LO
-from paper_2305_04711_amd import inputs
+from paper_2305_04711_amd import capi, inputs
 
 pytestmark = pytest.mark.gpu
 
@@ -185,9 +185,10 @@ def test_fullsize_apply_sampled_rows(name):
 
 @pytest.mark.parametrize("name", ["sphere_lat_256", "torus_meridians_512"])
 def test_fullsize_apply_every_launch_variant(name):
-    """Each of the six launch variants (LDS padding x tile order, including
-    the persistent gather, whose wavefronts each take many tiles here) on the
-    sampled rows; the autotuned choice is restored afterwards."""
+    """Each of the launch variants (LDS padding x tile order, including the
+    persistent gather, whose wavefronts each take many tiles here, x the two
+    forms of the Laplacian pass) on the sampled rows; the autotuned choice is
+    restored afterwards."""
     import torch
     from paper_2305_04711_amd import cpm
     S, Cs, N, band, ix, loc = _setup(name)
@@ -204,7 +205,7 @@ def test_fullsize_apply_every_launch_variant(name):
     try:
         for td, tol in ((torch.float64, 1e-12), (torch.float32, 5e-6)):
             u = torch.tensor(u_np, dtype=td, device="cuda")
-            for k in range(6):
+            for k in range(capi.TUNE_VARIANTS):
                 cpm.tune_set(band, td, k)
                 v = cpm.apply(band, u, m, n).cpu().numpy().astype(np.float64)
                 err = np.max(np.abs(v[gpu_rows] - ref)) / scale

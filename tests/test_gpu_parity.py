@@ -7,7 +7,7 @@ import pytest
 
 from oracle import adjoint as AD
 from oracle import krylov as KR
-from paper_2305_04711_amd import inputs
+from paper_2305_04711_amd import capi, inputs
 from parity_helpers import NEUMANN_CASES, dof_map, oracle_and_gpu
 
 pytestmark = pytest.mark.gpu
@@ -113,7 +113,7 @@ def test_apply_matches_oracle(torch_cuda, cfg, N, dtype):
 
 @pytest.mark.parametrize("cfg,N", CASES)
 def test_launch_variants_bit_identical(torch_cuda, cfg, N):
-    """Every launch variant (cpm_tune_set 0..5) computes each entry with the
+    """Every launch variant (cpm_tune_set 0..11) computes each entry with the
     same arithmetic: outputs are equal bit for bit, forward with 1 and 3
     right-hand sides and transposed, FP64 and FP32."""
     torch = torch_cuda
@@ -124,16 +124,16 @@ def test_launch_variants_bit_identical(torch_cuda, cfg, N):
     for td in (torch.float64, torch.float32):
         u3 = torch.tensor(U, dtype=td, device="cuda").contiguous()
         outs = []
-        for k in range(6):
+        for k in range(capi.TUNE_VARIANTS):
             cpm.tune_set(band, td, k)
             outs.append([cpm.apply(band, u3, 0.7, -1.3).cpu().numpy(),
                          cpm.apply(band, u3[2].contiguous(), 0.7, -1.3).cpu().numpy(),
                          cpm.apply_transpose(band, u3, 0.5, -1.0).cpu().numpy()])
-        for k in range(1, 6):
+        for k in range(1, capi.TUNE_VARIANTS):
             for a, b in zip(outs[0], outs[k]):
                 assert np.array_equal(a, b), (td, k)
     with pytest.raises(Exception):
-        cpm.tune_set(band, torch.float64, 6)
+        cpm.tune_set(band, torch.float64, capi.TUNE_VARIANTS)
     cpm.tune_set(band, torch.float64, 3)
     cpm.tune_set(band, torch.float32, 3)
 
@@ -383,3 +383,22 @@ def test_equator_split_second_order_on_gpu(torch_cuda, bc):
         print("equator", bc, N, "Linf away from C", errs[-1], st, flush=True)
     assert np.log2(errs[0] / errs[1]) > 1.7, errs
     assert errs[1] < 1e-3, errs
+
+
+@pytest.mark.parametrize("cfg,N", [("sphere_lat", 27), ("torus_meridians", 16),
+                                   ("circle_jump", 64)])
+def test_two_builds_give_identical_operators(torch_cuda, cfg, N):
+    """The band build is deterministic: two builds of one configuration give
+    the same operator bit for bit, forward and transposed (the transposed
+    apply sums rows in tile order, which the builder fixes by DOF)."""
+    torch = torch_cuda
+    from paper_2305_04711_amd import cpm
+    sysm, b1 = oracle_and_gpu(cfg, N)
+    _, b2 = oracle_and_gpu(cfg, N)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(9)
+    u = torch.randn(b1.n, dtype=torch.float64, device="cuda", generator=gen)
+    for td in (torch.float64, torch.float32):
+        assert torch.equal(cpm.apply(b1, u.to(td), 0.3, -1.0), cpm.apply(b2, u.to(td), 0.3, -1.0))
+        assert torch.equal(cpm.apply_transpose(b1, u.to(td), 0.3, -1.0),
+                           cpm.apply_transpose(b2, u.to(td), 0.3, -1.0))

@@ -514,3 +514,23 @@ def test_latitude_closed_form_quadratic():
     assert errs[0] > errs[1] > errs[2], errs
     assert fit_slope(1.0 / np.array(Ns), errs) > 1.3, errs
     assert errs[-1] < 2e-3
+
+
+def test_config_golden_c1_is_the_oracle_solution():
+    """tests/golden/solve_c1_circle32.npz (written by make_config_golden.py)
+    holds the oracle's solution of C1: re-derived here by sparse LU."""
+    import os
+    import scipy.sparse.linalg as spl
+    from paper_2305_04711_amd import inputs
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "solve_c1_circle32.npz"),
+                allow_pickle=False)
+    sysm = O.CPMSystem(G.Circle(), 32, [G.PointC((1.0, 0.0), (0.0, 1.0))], order=2)
+    assert int(g["n_s"]) == sysm.n_s and int(g["n_c"]) == sysm.n_c
+    f, _ = inputs.circle_source(0, sysm.CP)
+    b = sysm.rhs(f, np.zeros(sysm.n_c), -1.0)
+    x = spl.spsolve(sysm.matrix(0.0, -1.0).tocsc(), b)
+    d = sysm.index(g["pde_coords"].astype(np.int64))
+    assert np.all(d >= 0)
+    assert np.max(np.abs(x[d] - g["pde_u"])) <= 1e-12 * np.max(np.abs(x))
+    db = sysm.alpha_of[0][sysm.index(g["bc_coords"].astype(np.int64))]
+    assert np.max(np.abs(x[db] - g["bc_u"])) <= 1e-12 * np.max(np.abs(x))
