@@ -216,6 +216,20 @@ enum { CPM_F64 = 0, CPM_F32 = 1 };
 cpm_status cpm_apply(const cpm_band* band, double m, double n, int dtype,
                      int nrhs, const void* u, void* v, void* hip_stream);
 
+/* cpm_apply without device allocation, for callers that cannot allocate:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, result (bit for bit) and precision as
+ * cpm_apply, through the same kernels.  The FP64 intermediate a = E u lives
+ * in a static device array of the library (32 MiB on each GPU it runs on,
+ * held until the process ends) instead of the band's scratch, so
+ * n * nrhs <= 4194304 is required: larger calls return CPM_E_INVALID with
+ * nothing enqueued.  The array's address is looked up on the first call on
+ * each device.  Every call on one GPU shares the array: calls that may
+ * overlap on one GPU (on different streams, or from several threads) race
+ * on it and must be serialised by the caller. */
+cpm_status cpm_apply_noalloc(const cpm_band* band, double m, double n, int dtype,
+                             int nrhs, const void* u, void* v, void* hip_stream);
+
 /* z = A^T w = m w + n diag(L) w + n E^T ((L - diag L)^T w): the transpose of
  * cpm_apply (derived from Sec. 5.4).  Every sum has a fixed order (per-tile
  * LDS cubes added class by class; explicit rows through pull lists), so the

@@ -79,7 +79,7 @@ class SolveStats(C.Structure):
 BAND_TUBE, BAND_STENCIL_SET = 0, 1
 
 EXPORTED = ["cpm_build_band", "cpm_band_free", "cpm_band_query", "cpm_band_export",
-            "cpm_apply", "cpm_apply_profile", "cpm_autotune", "cpm_apply_transpose", "cpm_rhs", "cpm_rhs_adjoint", "cpm_solve",
+            "cpm_apply", "cpm_apply_noalloc", "cpm_apply_profile", "cpm_autotune", "cpm_apply_transpose", "cpm_rhs", "cpm_rhs_adjoint", "cpm_solve",
             "cpm_solve_adjoint", "cpm_batch_create", "cpm_batch_free", "cpm_batch_offsets",
             "cpm_batch_apply", "cpm_batch_autotune", "cpm_batch_solve", "cpm_heat_cn",
             "cpm_tune_set", "cpm_last_error"]
@@ -111,6 +111,7 @@ def load(path=LIB_PATH):
     lib.cpm_band_query.argtypes = [vp, C.POINTER(BandInfo)]
     lib.cpm_band_export.argtypes = [vp, i, vp, C.c_size_t]
     lib.cpm_apply.argtypes = [vp, d, d, i, i, vp, vp, vp]
+    lib.cpm_apply_noalloc.argtypes = [vp, d, d, i, i, vp, vp, vp]
     lib.cpm_apply_transpose.argtypes = [vp, d, d, i, i, vp, vp, vp]
     lib.cpm_apply_profile.argtypes = [vp, d, d, i, i, vp, vp, i, vp, C.POINTER(C.c_double)]
     lib.cpm_autotune.argtypes = [vp, i, i, vp, vp, i, vp, C.POINTER(C.c_double),

@@ -11,6 +11,8 @@
 // columns and weights.  Pass 2 maps one wavefront to one block of 64 nodes
 // and finds face neighbours through the block neighbour table; rows with
 // swapped FD neighbours (and BC rows) are explicit.
+#include <mutex>
+
 #include "cpm_internal.hpp"
 #include "lagrange.hpp"
 
@@ -1366,6 +1368,59 @@ extern "C" cpm_status cpm_apply(const cpm_band* b, double m, double n, int dtype
       apply_impl<double>(b, m, n, nrhs, (const double*)u, (double*)v, st);
     else
       apply_impl<float>(b, m, n, nrhs, (const float*)u, (float*)v, st);
+  });
+}
+
+// ---------------------------------------------------------------- no-alloc
+// cpm_apply for callers that cannot allocate device memory.  The scratch the
+// apply needs (the FP64 intermediate a = E u) lives in a file-scope device
+// array of kNoAllocScratchBytes, one copy per GPU the library runs on, held
+// until the process ends.  Host code never passes the array's name to a
+// kernel (on the host it only stands in for the symbol): its device address
+// is looked up once per device with hipGetSymbolAddress and kept in
+// g_noalloc_ptr.  Calls on one GPU share the array, so calls that overlap on
+// one GPU (different streams, or threads) race on it.  Every entry of a the
+// apply reads is written by the same apply first, so nothing needs clearing.
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;   // 32 MiB
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices] = {};
+
+void* noalloc_scratch() {
+  int dev = 0;
+  CPM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) CPM_FAIL(CPM_E_INVALID, "device ordinal %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* ptr = nullptr;
+    CPM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) CPM_FAIL(CPM_E_HIP, "hipGetSymbolAddress returned a null scratch address");
+    g_noalloc_ptr[dev] = ptr;
+  }
+  return g_noalloc_ptr[dev];
+}
+}  // namespace
+
+extern "C" cpm_status cpm_apply_noalloc(const cpm_band* b, double m, double n, int dtype,
+                                        int nrhs, const void* u, void* v, void* hip_stream) {
+  return guard([&] {
+    check_vec_args(b, dtype, nrhs, u, v);
+    const size_t need = apply_scratch_bytes(b, nrhs);
+    if (need > kNoAllocScratchBytes)
+      CPM_FAIL(CPM_E_INVALID,
+               "cpm_apply_noalloc: n * nrhs = %lld needs %zu bytes of scratch, above the "
+               "%zu-byte static limit (n * nrhs <= %zu); use cpm_apply",
+               (long long)(b->n * nrhs), need, kNoAllocScratchBytes,
+               kNoAllocScratchBytes / sizeof(double));
+    double* a = static_cast<double*>(noalloc_scratch());
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (dtype == CPM_F64)
+      apply_with_scratch<double>(b, m, n, nrhs, (const double*)u, (double*)v, st, a, nullptr);
+    else
+      apply_with_scratch<float>(b, m, n, nrhs, (const float*)u, (float*)v, st, a, nullptr);
   });
 }
 
