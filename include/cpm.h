@@ -269,9 +269,9 @@ typedef struct {
   int maxit;          /* cap on Krylov iterations in total (0 = 20000)       */
   double inner_tol;   /* mixed: reliable-update factor delta (0 = 0.1): once
                          the FP32 recursive residual has dropped by delta
-                         since the last update, the FP32 partial solution is
-                         added into x in FP64 and the FP64 true residual
-                         replaces the recursive one                         */
+                         since the last update, the partial solution is
+                         added into x in FP64 and the FP32 recurrence
+                         restarts from the FP64 true residual               */
   int check_every;    /* iterations between convergence read-backs (0 = 16)  */
   int use_graph;      /* 1: replay the check_every iterations as a hipGraph  */
   double gauge;       /* >0: solve (A + gauge 1 w^T) x = b, w = 1/n_s on PDE
@@ -353,8 +353,10 @@ cpm_status cpm_batch_autotune(cpm_batch* batch, int dtype, int reps,
 /* Solve every system (instance, right-hand side) with its own BiCGSTAB
  * scalars and convergence flag; opts->m, n and gauge are not used (the batch
  * holds m, n per instance; the gauge is not supported).  Mixed mode refines
- * in FP64 per system and finishes in FP64 any system whose FP32 inner solve
- * fails.  rhs and x are device [nrhs][total] double; x holds x0 on entry.
+ * in FP64 per system with FP32 steps (FP32 recurrence, the CPM_F32 apply,
+ * FP64 partial solution) to the relative tolerance inner_tol (0 = 1e-2) and
+ * finishes in FP64 any system whose FP64 residual did not halve over a
+ * step.  rhs and x are device [nrhs][total] double; x holds x0 on entry.
  * stats (may be NULL): nrhs * nbands entries, system s = r * nbands + i. */
 cpm_status cpm_batch_solve(cpm_batch* batch, const cpm_solve_opts* opts,
                            const double* rhs, double* x, cpm_solve_stats* stats,
@@ -362,7 +364,7 @@ cpm_status cpm_batch_solve(cpm_batch* batch, const cpm_solve_opts* opts,
 
 /* Autotuner: time every launch variant of cpm_apply for this band, dtype and
  * nrhs with HIP events, `reps` calls each, and keep the fastest for later
- * calls with this dtype.  Variant k = 8 lap + 2 mode + pad (0 <= k < 16):
+ * calls with this dtype.  Variant k = 8 lap + 2 mode + pad (0 <= k < 24):
  * pad is the LDS line padding of the staged cube (0: 1 element, 1: 4
  * elements); mode 0 visits tiles and blocks in block order, mode 1 gives each
  * XCD a contiguous range of them, mode 2 runs the tile gather as persistent
@@ -370,14 +372,17 @@ cpm_status cpm_batch_solve(cpm_batch* batch, const cpm_solve_opts* opts,
  * mode 3 also its staged values (modes 2 and 3 are for bands only: a batch's
  * composite skips them and reports HUGE_VAL); lap 0 gathers every FD
  * neighbour of the Laplacian pass from memory, lap 1 exchanges in-block
- * neighbours between lanes.  u and v are scratch device arrays [nrhs][n] of
- * that dtype.  ms (may be NULL) receives the 16 mean times per call; *best
- * (may be NULL) the chosen variant.  Synchronises the stream. */
+ * neighbours between lanes, lap 2 does the same in persistent wavefronts
+ * that request the next block's data while finishing the current one (one
+ * right-hand side; with several the pass runs as lap 1).  u and v are
+ * scratch device arrays [nrhs][n] of that dtype.  ms (may be NULL) receives
+ * the 24 mean times per call; *best (may be NULL) the chosen variant.
+ * Synchronises the stream. */
 cpm_status cpm_autotune(cpm_band* band, int dtype, int nrhs, const void* u,
                         void* v, int reps, void* hip_stream, double* ms,
                         int* best);
 
-/* Select launch variant k (numbered as by cpm_autotune, 0 <= k < 16) for
+/* Select launch variant k (numbered as by cpm_autotune, 0 <= k < 24) for
  * later calls on this band with this dtype, without timing anything; every
  * variant computes each output entry with the same arithmetic.  Returns
  * CPM_E_INVALID for a k out of range.  Touches no device memory. */

@@ -267,8 +267,8 @@ def autotune(band, dtype=torch.float64, nrhs=1, reps=10):
     """Pick the fastest apply launch variant for this band and dtype (kept in
     the band).  Returns (times_ms[capi.TUNE_VARIANTS], best): variant
     k = 8 lap + 2 mode + pad (mode 0 block order, 1 XCD-aware order, 2
-    persistent XCD-aware tile gather, 3 persistent and pipelined; lap 0 or 1
-    the two forms of the Laplacian pass)."""
+    persistent XCD-aware tile gather, 3 persistent and pipelined; lap 0, 1, 2
+    the three forms of the Laplacian pass)."""
     shape = (band.n,) if nrhs == 1 else (nrhs, band.n)
     u = torch.randn(shape, dtype=dtype, device="cuda")
     v = torch.empty_like(u)

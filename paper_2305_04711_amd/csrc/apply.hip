@@ -700,6 +700,139 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   if constexpr (DOT) wave_dot2(d0, d1, dpart, dnp, blockIdx.x * 4);
 }
 
+// Persistent and pipelined form of k_lap_sh for one right-hand side: each
+// XCD takes a contiguous range of blocks and its wavefronts take every W-th
+// block of it.  While block j is finished (cross-lane exchange, sums,
+// store), the metadata of block j + 2 and the data of block j + 1 are
+// already requested, so a wavefront keeps a block's loads in flight at all
+// times.  (A wave's vector memory requests complete in issue order: each
+// block's metadata is requested before the previous block's data, so
+// waiting for it never waits for that data.)
+template <int DIM>
+struct LapIdx {
+  int own, outr;    // DOF of the lane's slot (-1 absent); output DOF (-1 none)
+  int xdof[DIM];    // per axis: DOF of the neighbour across the block face the
+                    // lane lies on (-1 none, or the lane is on no face of it)
+  int inst;         // instance of the block (composites), else 0
+};
+template <class TA, int DIM>
+struct LapData {
+  TA aown;
+  double uv, yv;
+  double across[DIM];
+};
+
+template <class TU, class TA, class TV, int DIM, bool ALL, bool DOT = false>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_lap_pp(
+    BlockView B, const TU* __restrict__ u, const TA* __restrict__ a, TV* __restrict__ v,
+    double cd, double co, const double* __restrict__ gsum, double gscale,
+    const double* __restrict__ coef, const int* __restrict__ skip,
+    const TV* __restrict__ dy = nullptr, double* __restrict__ dpart = nullptr, int dnp = 0) {
+  using G = Geo<DIM>;
+  const int slot = threadIdx.x & 63;
+  const int x = blockIdx.x & 7, W = (gridDim.x >> 3) * 4;
+  const int wk = (blockIdx.x >> 3) * 4 + (threadIdx.x >> 6);
+  const int q8 = B.nb >> 3, r8 = B.nb & 7;
+  const int lo = x * q8 + (x < r8 ? x : r8), hi = lo + q8 + (x < r8 ? 1 : 0);
+  const int l[3] = {G::lx(slot), G::ly(slot), G::lz(slot)};
+  constexpr int step[3] = {1, G::BX, G::BX * G::BX};
+  auto meta = [&](int blk, unsigned long long& lm, int& loff, int& lpad) {
+    lm = 0ull;
+    loff = lpad = 0;
+    if (blk < hi && slot < 8) {
+      const QMeta q = B.face[(int64_t)blk * 8 + slot];
+      lm = q.mask;
+      loff = q.off;
+      lpad = q.pad;
+    }
+  };
+  auto index = [&](unsigned long long lm, int loff, int lpad, LapIdx<DIM>& ix) {
+    ix.inst = 0;
+    bool skipj = false;
+    if (coef) {
+      const int inst = lane_i32(lpad, 7);
+      ix.inst = inst > 0 ? inst : 0;
+      skipj = skip && skip[ix.inst];
+    }
+    const unsigned long long m = lane_u64(lm, 0);
+    const int off0 = lane_i32(loff, 0);
+    const unsigned long long xm = lane_u64(lm, 7);
+    const bool present = ((m >> slot) & 1ull) && !skipj;
+    ix.own = present ? off0 + __popcll(m & ((1ull << slot) - 1ull)) : -1;
+    ix.outr = (present && (ALL || !((xm >> slot) & 1ull))) ? ix.own : -1;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      // the lane lies on at most one face per axis: low (f = 2d) or high
+      const bool low = l[d] == 0, high = l[d] == G::BX - 1;
+      const int f = low ? 2 * d : 2 * d + 1;
+      int q[3] = {l[0], l[1], l[2]};
+      q[d] = low ? G::BX - 1 : 0;
+      const int s2 = G::slot(q[0], q[1], q[2]);
+      const unsigned long long fmk = lane_u64(lm, f + 1);
+      const int fof = lane_i32(loff, f + 1);
+      ix.xdof[d] = ((low || high) && ((fmk >> s2) & 1ull))
+                       ? fof + __popcll(fmk & ((1ull << s2) - 1ull)) : -1;
+    }
+  };
+  auto load = [&](const LapIdx<DIM>& ix, LapData<TA, DIM>& dt) {
+    dt.aown = ix.own >= 0 ? a[ix.own] : TA(0);
+    dt.uv = (!ALL && ix.outr >= 0) ? (double)u[ix.outr] : 0.0;
+    dt.yv = (DOT && ix.outr >= 0) ? (double)dy[ix.outr] : 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d)
+      dt.across[d] = (ix.outr >= 0 && ix.xdof[d] >= 0) ? (double)a[ix.xdof[d]] : 0.0;
+  };
+  double d0 = 0.0, d1 = 0.0;
+  auto finish = [&](const LapIdx<DIM>& ix, const LapData<TA, DIM>& dt) {
+    double sum = 0.0;
+#pragma unroll
+    for (int f = 0; f < 2 * DIM; ++f) {
+      const int d = f >> 1;
+      const bool out = (f & 1) ? l[d] == G::BX - 1 : l[d] == 0;
+      const int src = out ? slot : slot + ((f & 1) ? step[d] : -step[d]);
+      const double inb = (double)lane_take<TA>(dt.aown, src);
+      sum += out ? dt.across[d] : inb;
+    }
+    if (ix.outr < 0) return;
+    const double cdi = coef ? coef[2 * ix.inst] : cd;
+    const double coi = coef ? coef[2 * ix.inst + 1] : co;
+    double o = ALL ? coi * sum : lap_out(cdi, dt.uv, coi, sum);
+    if (gsum) o += gscale * gsum[0];
+    const TV ov = (TV)o;
+    v[ix.outr] = ov;
+    if (DOT) {
+      d0 += dt.yv * (double)ov;
+      d1 += (double)ov * (double)ov;
+    }
+  };
+  int blk = lo + wk;
+  if (blk < hi) {
+    unsigned long long lm, lmn;
+    int loff, lpad, loffn, lpadn;
+    LapIdx<DIM> ic, in;
+    LapData<TA, DIM> dc, dn;
+    meta(blk, lm, loff, lpad);
+    index(lm, loff, lpad, ic);
+    meta(blk + W, lmn, loffn, lpadn);
+    load(ic, dc);
+    while (true) {
+      const int nb = blk + W;
+      const bool more = nb < hi;
+      if (more) {
+        index(lmn, loffn, lpadn, in);
+        meta(nb + W, lmn, loffn, lpadn);
+        load(in, dn);
+      }
+      finish(ic, dc);
+      if (!more) break;
+      ic = in;
+      dc = dn;
+      blk = nb;
+    }
+  }
+  if constexpr (DOT) wave_dot2(d0, d1, dpart, dnp, blockIdx.x * 4);
+}
+
 template <class TS, bool DOT = false>
 __global__ void k_lap_rows(int nrows, int nf, const int* __restrict__ row_id,
                            const int* __restrict__ col, const TS* __restrict__ u,
@@ -770,38 +903,17 @@ __global__ void k_sum_final(const double* part, int np, double* out) {
 
 // ---------------------------------------------------------------- transpose
 // E^T c for the tile rows of one parity class, one wavefront per tile.  Each
-// lane first puts the stencil base of one row into LDS, with the row's
-// fractions and c_i (3-D) or its 1-D weights, c_i folded in (2-D); then the
-// wave walks the rows with one lane per stencil member (4 rows at a time in
-// 2-D, where a stencil has 16 members), adding w c_i into the tile's (2 BX)^d
-// cube in LDS.  In 3-D each lane evaluates its member's three 1-D weights as
-// cubics in Horner form (less LDS per wave, so more waves per SIMD) and sums
-// over runs of rows with the same stencil base; 2-D uses LDS atomic adds
-// (rows past the last one carry zero weights).  The cube is accumulated in
-// FP64 for both precisions.  The cube is then added into z
-// with plain loads and stores: tiles of one parity class stage disjoint
-// blocks and the classes run as successive launches, so no two waves of a
-// launch touch the same entry of z.
-// Coefficients (c3, c2, c1, c0) of the 1-D Lagrange weight of stencil node a
-// as a cubic in the fraction t (Horner form), for degree p = 3 or 2.
-template <class T>
-__device__ __forceinline__ void member_poly(int p, int a, T c[4]) {
-  const T s6 = T(1) / T(6), s3 = T(1) / T(3);
-  if (p == 3) {
-    const T k[4][4] = {{-s6, T(0.5), -s3, T(0)}, {T(0.5), T(-1), T(-0.5), T(1)},
-                       {T(-0.5), T(0.5), T(1), T(0)}, {s6, T(0), -s6, T(0)}};
-    for (int i = 0; i < 4; ++i) c[i] = k[a][i];
-  } else {
-    const T k[4][4] = {{T(0), T(0.5), T(-0.5), T(0)}, {T(0), T(-1), T(0), T(1)},
-                       {T(0), T(0.5), T(0.5), T(0)}, {T(0), T(0), T(0), T(0)}};
-    for (int i = 0; i < 4; ++i) c[i] = k[a][i];
-  }
-}
-template <class T>
-__device__ __forceinline__ T horner3(const T c[4], T t) {
-  return ((c[0] * t + c[1]) * t + c[2]) * t + c[3];
-}
-
+// lane first puts the stencil base of one row into LDS with the row's 1-D
+// weights (the forward gather's FP64 weights), c_i folded into the last
+// factor; then the wave walks the rows with one lane per stencil member (4
+// rows at a time in 2-D, where a stencil has 16 members), adding w c_i into
+// the tile's (2 BX)^d cube in LDS.  A 3-D member's weight is the product of
+// three 1-D weights read from LDS, and each lane sums over runs of rows with
+// the same stencil base; 2-D uses LDS atomic adds (rows past the last one
+// carry zero weights).  The cube is accumulated in FP64 for both precisions.
+// The cube is then added into z with plain loads and stores: tiles of one
+// parity class stage disjoint blocks and the classes run as successive
+// launches, so no two waves of a launch touch the same entry of z.
 template <class TS, int DIM>
 __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const int* __restrict__ list,
                                                  int N, const double* __restrict__ c,
@@ -814,7 +926,7 @@ __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const
   constexpr int RPI = 64 / M;                 // rows per wave instruction
   constexpr int NW = DIM == 3 ? 12 : 8;       // 1-D weights per row
   __shared__ double s_z[CS];
-  __shared__ double s_w[DIM == 3 ? 4 : NW][64];   // per-row 1-D weights, component major
+  __shared__ double s_w[NW][64];              // per-row 1-D weights, component major
   __shared__ int s_b[64];                     // per-row cube offset of member 0
   const int t = list[xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x];
   const int lane = threadIdx.x;
@@ -844,12 +956,7 @@ __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const
   const int mo = lane & (M - 1), sub = lane / M;
   const int ma = mo & 3, mb = (mo >> 2) & 3, mc = DIM == 3 ? (mo >> 4) : 0;
   const int moff = DIM == 3 ? (mc * E + mb) * EP + ma : mb * EP + ma;
-  double ca[4], cb[4], cc[4];
-  member_poly<double>(tv.p, ma, ca);
-  member_poly<double>(tv.p, mb, cb);
-  member_poly<double>(tv.p, mc, cc);
   for (int p0 = beg; p0 < end; p0 += 64) {
-    double tq[3] = {0.0, 0.0, 0.0}, cq = 0.0;
     const int nrow = min(64, end - p0);
     double wx[4] = {0.0, 0.0, 0.0, 0.0}, wy[4] = {0.0, 0.0, 0.0, 0.0};
     double wz[4] = {0.0, 0.0, 0.0, 0.0};
@@ -860,10 +967,6 @@ __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const
       int lb[3];
       double tt[3];
       row_stencil<TS, DIM>(tv, pos, lb, tt);
-      tq[0] = tt[0];
-      tq[1] = tt[1];
-      tq[2] = tt[2];
-      cq = ci;
       lagrange_p<double>(tv.p, tt[0], wx);
       lagrange_p<double>(tv.p, tt[1], wy);
       if (DIM == 3) {
@@ -876,17 +979,11 @@ __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const
       }
       bs = DIM == 3 ? (lb[2] * E + lb[1]) * EP + lb[0] : lb[1] * EP + lb[0];
     }
-    if constexpr (DIM == 3) {
-      s_w[0][lane] = tq[0];
-      s_w[1][lane] = tq[1];
-      s_w[2][lane] = tq[2];
-      s_w[3][lane] = cq;
-    } else {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        s_w[k][lane] = wx[k];
-        s_w[4 + k][lane] = wy[k];
-      }
+    for (int k = 0; k < 4; ++k) {
+      s_w[k][lane] = wx[k];
+      s_w[4 + k][lane] = wy[k];
+      if constexpr (DIM == 3) s_w[8 + k][lane] = wz[k];
     }
     s_b[lane] = bs;
     __syncthreads();
@@ -905,8 +1002,7 @@ __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           bq[u] = __builtin_amdgcn_readfirstlane(s_b[j + u]);
-          wq[u] = horner3<double>(ca, s_w[0][j + u]) * horner3<double>(cb, s_w[1][j + u]) *
-                  horner3<double>(cc, s_w[2][j + u]) * s_w[3][j + u];
+          wq[u] = (s_w[ma][j + u] * s_w[4 + mb][j + u]) * s_w[8 + mc][j + u];
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -1150,7 +1246,15 @@ static void launch_gather(const cpm_band* b, int nrhs, const T* u, double* a, hi
   if (ev) CPM_HIP(hipEventRecord(ev[2], st));
 }
 
+// Workgroups (4 wavefronts each) of the Laplacian pass in the tuned form; the
+// persistent form (lap 2) launches at most kLapPersistWGsPerXcd per XCD.
+constexpr int kLapPersistWGsPerXcd = 384;
 static int lap_groups(const cpm_band* b, const Tune& tn) {
+  if (tn.lap == 2) {
+    int g = (b->nb + 31) / 32 * 8;   // a multiple of 8: every XCD gets as many
+    if (g > 8 * kLapPersistWGsPerXcd) g = 8 * kLapPersistWGsPerXcd;
+    return g < 8 ? 8 : g;
+  }
   const int kb = tn.lap ? kLapShBlocksPerWave : kLapBlocksPerWave;
   return (b->nb + 4 * kb - 1) / (4 * kb);
 }
@@ -1172,8 +1276,18 @@ static void launch_lap(const cpm_band* b, const Tune& tn, hipStream_t st, const 
                        const TA* a, TV* v, int64_t ld, int nrhs, double cd, double co,
                        const double* gsum, double gscale, const double* coef, const int* skip,
                        const TV* dy, double* dpart, int dnp) {
+  if (tn.lap == 2 && nrhs > 1) {   // the persistent form takes one right-hand side
+    Tune t1 = tn;
+    t1.lap = 1;
+    launch_lap<TU, TA, TV, DIM, ALL, DOT>(b, t1, st, u, a, v, ld, nrhs, cd, co, gsum, gscale,
+                                          coef, skip, dy, dpart, dnp);
+    return;
+  }
   const dim3 g(lap_groups(b, tn)), t(256);
-  if (tn.lap)
+  if (tn.lap == 2)
+    hipLaunchKernelGGL((k_lap_pp<TU, TA, TV, DIM, ALL, DOT>), g, t, 0, st, bview(b), u, a, v, cd,
+                       co, gsum, gscale, coef, skip, dy, dpart, dnp);
+  else if (tn.lap)
     hipLaunchKernelGGL((k_lap_sh<TU, TA, TV, DIM, ALL, DOT>), g, t, 0, st, bview(b), u, a, v, ld,
                        nrhs, cd, co, gsum, gscale, tn.xcd, coef, skip, dy, dpart, dnp);
   else

@@ -184,18 +184,19 @@ __global__ __launch_bounds__(256) void k_bdot_ts(int nchunks, Seg g, const T* __
     S[s].omega = (tot[1] == 0.0 || !__builtin_isfinite(tot[1])) ? 0.0 : tot[0] / tot[1];
 }
 
-template <class T>
-__global__ __launch_bounds__(256) void k_bxr(int nchunks, Seg g, T* __restrict__ x,
+template <class T, class TX>
+__global__ __launch_bounds__(256) void k_bxr(int nchunks, Seg g, TX* __restrict__ x,
                                              const T* __restrict__ p, const T* __restrict__ sv,
                                              const T* __restrict__ t, T* __restrict__ r,
                                              const T* __restrict__ rh, double* part, BScal* S) {
   SEG_PROLOGUE;
   if (S[s].done) return;
-  const T al = (T)S[s].alpha, om = (T)S[s].omega;
+  const T om = (T)S[s].omega;
+  const TX alx = (TX)S[s].alpha, omx = (TX)S[s].omega;
   double acc[2] = {0.0, 0.0};
   for (int64_t i = lo + threadIdx.x; i < hi; i += kBT) {
     const T si = sv[i];
-    x[i] = x[i] + al * p[i] + om * si;
+    x[i] = x[i] + alx * (TX)p[i] + omx * (TX)si;
     const T ri = si - om * t[i];
     r[i] = ri;
     acc[0] += (double)rh[i] * (double)ri;
@@ -251,20 +252,20 @@ __global__ __launch_bounds__(256) void k_bres64(int nchunks, Seg g, const double
   }
 }
 
-// r32 = r / ||r|| (0 for systems not active), d32 = 0
+// r32 = r / ||r|| (0 for systems not active), d = 0 (FP64 partial solution)
 __global__ __launch_bounds__(256) void k_bto32(int nchunks, Seg g, const double* __restrict__ r,
                                                const double* __restrict__ scale,
-                                               float* __restrict__ r32, float* __restrict__ d32) {
+                                               float* __restrict__ r32, double* __restrict__ d32) {
   SEG_PROLOGUE;
   const double inv = scale[s] > 0.0 ? 1.0 / scale[s] : 0.0;
   for (int64_t i = lo + threadIdx.x; i < hi; i += kBT) {
     r32[i] = (float)(r[i] * inv);
-    d32[i] = 0.0f;
+    d32[i] = 0.0;
   }
 }
 
 __global__ __launch_bounds__(256) void k_badd32(int nchunks, Seg g, double* __restrict__ x,
-                                                const float* __restrict__ d,
+                                                const double* __restrict__ d,
                                                 const double* __restrict__ scale) {
   SEG_PROLOGUE;
   const double sc = scale[s];
@@ -478,8 +479,9 @@ struct PinnedB {
   ~PinnedB() { if (h) (void)hipHostFree(h); }
 };
 
-// Segmented BiCGSTAB over every system of the batch (vectors [nrhs][total]).
-template <class T>
+// Segmented BiCGSTAB over every system of the batch (vectors [nrhs][total]);
+// the iterate is of type TX (FP64 for the FP32 recurrence of mixed mode).
+template <class T, class TX = T>
 struct BBicg {
   cpm_batch* B;
   hipStream_t st;
@@ -492,7 +494,7 @@ struct BBicg {
   std::vector<int> hact;
   hipGraphExec_t gexec = nullptr;
   int giters = 0;
-  T* gx = nullptr;
+  TX* gx = nullptr;
 
   BBicg(cpm_batch* b_, hipStream_t st_, int slot0)
       : B(b_), st(st_), len(b_->total * b_->nrhs), pin(b_->nsys), hact(b_->nsys, 1) {
@@ -520,14 +522,17 @@ struct BBicg {
     CPM_HIP(hipMemcpyAsync(act, hact.data(), sizeof(int) * B->nsys, hipMemcpyHostToDevice, st));
     CPM_HIP(hipStreamSynchronize(st));
   }
-  void init(const T* rhs, const T* x, bool x_zero, double tol) {
+  void init(const T* rhs, const TX* x, bool x_zero, double tol) {
     hipLaunchKernelGGL(k_bscal_reset, dim3((B->nsys + 127) / 128), dim3(128), 0, st, S, B->nsys, act);
-    if (!x_zero) apply(x, v);
+    if (!x_zero) {
+      if constexpr (std::is_same<T, TX>::value) apply(x, v);
+      else CPM_FAIL(CPM_E_INVALID, "internal: warm start of a mixed-type recurrence");
+    }
     hipLaunchKernelGGL(k_binit<T>, dim3(B->nchunks), dim3(kBT), 0, st, B->nchunks, seg_of(B), rhs,
                        v, x_zero ? 0 : 1, r, rh, p, part, S, tol);
     CPM_LAUNCH_CHECK();
   }
-  void iteration(T* x) {
+  void iteration(TX* x) {
     const Seg g = seg_of(B);
     const int nc = B->nchunks;
     apply(p, v);
@@ -535,11 +540,12 @@ struct BBicg {
     hipLaunchKernelGGL(k_bs<T>, dim3(nc), dim3(kBT), 0, st, nc, g, r, v, s, S);
     apply(s, t);
     hipLaunchKernelGGL(k_bdot_ts<T>, dim3(nc), dim3(kBT), 0, st, nc, g, t, s, part, S);
-    hipLaunchKernelGGL(k_bxr<T>, dim3(nc), dim3(kBT), 0, st, nc, g, x, p, s, t, r, rh, part, S);
+    hipLaunchKernelGGL((k_bxr<T, TX>), dim3(nc), dim3(kBT), 0, st, nc, g, x, p, s, t, r, rh, part,
+                       S);
     hipLaunchKernelGGL(k_bp<T>, dim3(nc), dim3(kBT), 0, st, nc, g, r, p, v, S);
     CPM_LAUNCH_CHECK();
   }
-  void run(T* x, int k, bool graph) {
+  void run(TX* x, int k, bool graph) {
     if (!graph) {
       for (int i = 0; i < k; ++i) iteration(x);
       return;
@@ -572,7 +578,7 @@ struct BBicg {
     return pin.h;
   }
   // Returns the largest iteration count over the systems.
-  int solve(const T* rhs, T* x, bool x_zero, double tol, int maxit, int ce, bool graph) {
+  int solve(const T* rhs, TX* x, bool x_zero, double tol, int maxit, int ce, bool graph) {
     init(rhs, x, x_zero, tol);
     const BScal* h = read();
     int it = 0;
@@ -586,9 +592,11 @@ struct BBicg {
         any_rs |= rs[q] != 0;
         it = std::max(it, h[q].it);
       }
-      if (any_rs && restarts < 50) {
-        // restart the broken-down systems from their current iterate; the
-        // others keep their recurrences (k_binit only touches active ones)
+      // restart the broken-down systems from their current iterate; the
+      // others keep their recurrences (k_binit only touches active ones).
+      // A mixed-type recurrence (an FP32 refinement step) ends instead: the
+      // refinement loop restarts it from the FP64 residual.
+      if constexpr (std::is_same<T, TX>::value) if (any_rs && restarts < 50) {
         ++restarts;
         clear_skip();   // the restart's apply must cover every instance
         const std::vector<int> keep = hact;
@@ -767,42 +775,44 @@ extern "C" cpm_status cpm_batch_solve(cpm_batch* b, const cpm_solve_opts* o, con
     if (o->mode == CPM_SOLVE_F64) {
       plain64(std::vector<int>(ns, 1));
     } else {
+      // FP32 refinement steps: each system's step solves A d = r / ||r|| with
+      // an FP32 recurrence (the FP32 apply computes in FP64) to the relative
+      // tolerance itol or kStepIters iterations, then x += ||r|| d in FP64.  A
+      // system whose FP64 residual did not halve over a step finishes in FP64.
       const double itol = o->inner_tol > 0 ? o->inner_tol : 1e-2;
-      BBicg<float> k(b, st, 50);
+      constexpr int kStepIters = 1000;
+      BBicg<float, double> k(b, st, 50);
       float* r32 = (float*)band_scratch(c, 45, sizeof(float) * len);
-      float* d32 = (float*)band_scratch(c, 46, sizeof(float) * len);
-      std::vector<double> h_scale(ns);
+      double* d64 = (double*)band_scratch(c, 46, sizeof(double) * len);
+      std::vector<double> h_scale(ns), prev(ns, HUGE_VAL);
       std::vector<int> active(ns, 1), failed(ns, 0);
       for (int step = 0; step < 100; ++step) {
         residual();
         bool any = false;
         for (int q = 0; q < ns; ++q) {
+          if (active[q] && !conv[q] && !(relres[q] < 0.5 * prev[q])) failed[q] = 1;
           active[q] = active[q] && !conv[q] && !failed[q];
+          prev[q] = relres[q];
           h_scale[q] = active[q] ? std::sqrt(pin.h[q].rr) : 0.0;
           any |= active[q] != 0;
         }
         if (!any) break;
         CPM_HIP(hipMemcpyAsync(scale, h_scale.data(), sizeof(double) * ns, hipMemcpyHostToDevice, st));
         hipLaunchKernelGGL(k_bto32, dim3(b->nchunks), dim3(kBT), 0, st, b->nchunks, seg_of(b), r64,
-                           scale, r32, d32);
+                           scale, r32, d64);
         CPM_LAUNCH_CHECK();
         k.set_active(active);
-        // FP32 resolves a few decades at most on these systems; a step that
-        // has not reached itol within 250 iterations hands its system over
-        k.solve(r32, d32, true, itol, 250, ce, graph);
+        k.solve(r32, d64, true, itol, kStepIters, ce, graph);
         const BScal* h = k.read();
         for (int q = 0; q < ns; ++q) {
           if (!active[q]) continue;
           iters[q] += h[q].it;
           ++outer[q];
-          if (!(h[q].done && h[q].rr <= h[q].tol2)) {
-            failed[q] = 1;     // beyond FP32 accuracy: finish in FP64
-            if (!(h[q].rr <= h[q].bb)) h_scale[q] = 0.0;   // diverged: drop the update
-          }
+          if (!(h[q].rr <= h[q].bb)) h_scale[q] = 0.0;   // diverged: drop the update
         }
         CPM_HIP(hipMemcpyAsync(scale, h_scale.data(), sizeof(double) * ns, hipMemcpyHostToDevice, st));
         hipLaunchKernelGGL(k_badd32, dim3(b->nchunks), dim3(kBT), 0, st, b->nchunks, seg_of(b), x,
-                           d32, scale);
+                           d64, scale);
         CPM_LAUNCH_CHECK();
       }
       std::vector<int> rest(ns, 0);
