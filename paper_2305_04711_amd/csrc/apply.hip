@@ -764,12 +764,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     for (int d = 0; d < DIM; ++d) {
       // the lane lies on at most one face per axis: low (f = 2d) or high
       const bool low = l[d] == 0, high = l[d] == G::BX - 1;
-      const int f = low ? 2 * d : 2 * d + 1;
       int q[3] = {l[0], l[1], l[2]};
       q[d] = low ? G::BX - 1 : 0;
       const int s2 = G::slot(q[0], q[1], q[2]);
-      const unsigned long long fmk = lane_u64(lm, f + 1);
-      const int fof = lane_i32(loff, f + 1);
+      // readlane takes a wave-uniform lane: read both faces, select per lane
+      const unsigned long long fm_lo = lane_u64(lm, 2 * d + 1), fm_hi = lane_u64(lm, 2 * d + 2);
+      const int fo_lo = lane_i32(loff, 2 * d + 1), fo_hi = lane_i32(loff, 2 * d + 2);
+      const unsigned long long fmk = low ? fm_lo : fm_hi;
+      const int fof = low ? fo_lo : fo_hi;
       ix.xdof[d] = ((low || high) && ((fmk >> s2) & 1ull))
                        ? fof + __popcll(fmk & ((1ull << s2) - 1ull)) : -1;
     }
