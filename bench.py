@@ -741,7 +741,7 @@ def main():
                                      "explicit L rows"]},
         "time_to_1e-8": solves,
         "configs": configs,
-        "autotune": {"variants": "k = 2 * mode + pad (mode 0 block order, 1 XCD-aware, 2 persistent XCD-aware gather)", "f64_ms": tune64[0], "f64_best": tune64[1],
+        "autotune": {"variants": "k = 8 * lap + 2 * mode + pad (mode 0 block order, 1 XCD-aware, 2 persistent XCD-aware gather, 3 persistent pipelined gather; lap 0..3 the forms of the Laplacian pass, 3 = two blocks per wave with scalar metadata)", "f64_ms": tune64[0], "f64_best": tune64[1],
                      "f32_ms": tune32[0], "f32_best": tune32[1]},
         "build_band_s": build_s,
         "adjoint": adjoint,

@@ -364,7 +364,7 @@ cpm_status cpm_batch_solve(cpm_batch* batch, const cpm_solve_opts* opts,
 
 /* Autotuner: time every launch variant of cpm_apply for this band, dtype and
  * nrhs with HIP events, `reps` calls each, and keep the fastest for later
- * calls with this dtype.  Variant k = 8 lap + 2 mode + pad (0 <= k < 24):
+ * calls with this dtype.  Variant k = 8 lap + 2 mode + pad (0 <= k < 32):
  * pad is the LDS line padding of the staged cube (0: 1 element, 1: 4
  * elements); mode 0 visits tiles and blocks in block order, mode 1 gives each
  * XCD a contiguous range of them, mode 2 runs the tile gather as persistent
@@ -374,15 +374,17 @@ cpm_status cpm_batch_solve(cpm_batch* batch, const cpm_solve_opts* opts,
  * neighbour of the Laplacian pass from memory, lap 1 exchanges in-block
  * neighbours between lanes, lap 2 does the same in persistent wavefronts
  * that request the next block's data while finishing the current one (one
- * right-hand side; with several the pass runs as lap 1).  u and v are
+ * right-hand side; with several the pass runs as lap 1), lap 3 takes two
+ * blocks per wavefront with their metadata in scalar registers and exchanges
+ * in-block neighbours with row moves and lane permutes.  u and v are
  * scratch device arrays [nrhs][n] of that dtype.  ms (may be NULL) receives
- * the 24 mean times per call; *best (may be NULL) the chosen variant.
+ * the 32 mean times per call; *best (may be NULL) the chosen variant.
  * Synchronises the stream. */
 cpm_status cpm_autotune(cpm_band* band, int dtype, int nrhs, const void* u,
                         void* v, int reps, void* hip_stream, double* ms,
                         int* best);
 
-/* Select launch variant k (numbered as by cpm_autotune, 0 <= k < 24) for
+/* Select launch variant k (numbered as by cpm_autotune, 0 <= k < 32) for
  * later calls on this band with this dtype, without timing anything; every
  * variant computes each output entry with the same arithmetic.  Returns
  * CPM_E_INVALID for a k out of range.  Touches no device memory. */

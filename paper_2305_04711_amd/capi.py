@@ -23,7 +23,7 @@ IBC_POINT, IBC_LATITUDE, IBC_MERIDIAN, IBC_LATITUDE_ARC = 1, 2, 3, 4
 EXPORT_COORDS, EXPORT_CP, EXPORT_BC_NODE, EXPORT_BC_CPC, EXPORT_BC_SIDE, EXPORT_BC_CURVE, \
     EXPORT_ECOLS, EXPORT_LCOLS, EXPORT_BASE = range(1, 10)
 F64, F32 = 0, 1
-TUNE_VARIANTS = 24          # launch variants of cpm_autotune / cpm_tune_set
+TUNE_VARIANTS = 32          # launch variants of cpm_autotune / cpm_tune_set
 SOLVE_MIXED, SOLVE_F64, SOLVE_GMRES = 0, 1, 2
 
 

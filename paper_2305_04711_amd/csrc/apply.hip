@@ -39,6 +39,17 @@ __device__ __forceinline__ unsigned long long lane_u64(unsigned long long v, int
   return ((unsigned long long)hi << 32) | lo;
 }
 
+// With a wave-uniform mask m (in scalar registers): base + the number of
+// bits of m below the lane (masked bit counts, two vector instructions), and
+// whether the lane's own bit is set (the mask used as an execution mask).
+__device__ __forceinline__ int lane_count_below(unsigned long long m, int base) {
+  return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((unsigned)m, (unsigned)base));
+}
+__device__ __forceinline__ bool lane_in(unsigned long long m) {
+  return __builtin_amdgcn_inverse_ballot_w64(m);
+}
+
 // Workgroups are dispatched to the 8 XCDs round robin; this bijection on
 // [0, g) gives each XCD a contiguous range of work items so that neighbouring
 // tiles, which stage the same blocks, share one L2.
@@ -144,9 +155,12 @@ __device__ __forceinline__ void interp_row(const TL (&s_u)[NR][CSZ], int p, cons
 
 // One wavefront per tile: stage the (2 BX)^d cube of u into LDS (x lines
 // padded by PAD elements to spread LDS banks), then each lane interpolates
-// rows of the tile.  The staged blocks' masks and first DOFs come from the
-// tile's metadata in one load.  u is stored and staged in TS (FP64 or FP32:
-// an FP32 value is staged exactly); weights, products and sums are FP64 and
+// rows of the tile.  The staged blocks' masks and first DOFs are
+// wave-uniform: scalar loads, and a staged node's DOF and presence come from
+// masked bit counts and an execution mask instead of per-lane 64-bit mask
+// arithmetic (the kernel is limited by instruction issue as much as by
+// memory).  u is stored and staged in TS (FP64 or FP32: an FP32 value is
+// staged exactly); weights, products and sums are FP64 and
 // a is written in FP64 for both storage precisions: the Laplacian pass differences neighbouring
 // values of a and scales the difference by N^2, so a rounding of a to FP32
 // would be amplified by N^2 (on the smooth modes that converge last, a
@@ -165,13 +179,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void k_
   const int t = xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
   const int lane = threadIdx.x;
   if (tv.skip && tv.skip[tv.tile_inst[t]]) return;   // converged batch instance
-  unsigned long long qm = 0ull;
-  int qoff = 0;
-  if (lane < NQ) {
-    const QMeta q = tv.meta[(int64_t)t * 8 + lane];
-    qm = q.mask;
-    qoff = q.off;
-  }
+  // the staged blocks' masks and first DOFs: wave-uniform, scalar loads
+  const QMeta* tm = tv.meta + (int64_t)t * 8;
   const int cx0 = G::lx(lane), cy0 = G::ly(lane), cz0 = G::lz(lane);
   // the first pass's row data is requested before the staging loads, and
   // every pass requests the next pass's before interpolating
@@ -181,15 +190,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void k_
   if (beg + lane < end) row_stencil<TS, DIM>(tv, beg + lane, lb, tt);
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
-    const unsigned long long m = lane_u64(qm, q);
-    const int off = lane_i32(qoff, q);
+    const unsigned long long m = tm[q].mask;
     const int qx = q & 1, qy = (q >> 1) & 1, qz = DIM == 3 ? (q >> 2) : 0;
     const int cx = qx * G::BX + cx0, cy = qy * G::BX + cy0, cz = qz * G::BX + cz0;
     const int ci = DIM == 3 ? (cz * E + cy) * EP + cx : cy * EP + cx;
-    const bool on = (m >> lane) & 1ull;
-    const int dof = off + __popcll(m & ((1ull << lane) - 1ull));
+    const int dof = lane_count_below(m, tm[q].off);
 #pragma unroll
-    for (int r = 0; r < NR; ++r) s_u[r][ci] = on ? u[r * ld + dof] : TS(0);
+    for (int r = 0; r < NR; ++r) {
+      TS x = TS(0);
+      if (lane_in(m)) x = u[r * ld + dof];
+      s_u[r][ci] = x;
+    }
   }
   __syncthreads();
   for (int pos = beg + lane; pos < end; pos += 64) {
@@ -835,6 +846,190 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   if constexpr (DOT) wave_dot2(d0, d1, dpart, dnp, blockIdx.x * 4);
 }
 
+// The Laplacian pass with its index arithmetic moved off the vector unit.
+// Profiles of the pass forms above show them bound by vector-instruction
+// issue, not by memory: about 250 vector instructions per block, almost all
+// of them integer work on 64-bit masks (broadcasts of the metadata, prefix
+// popcounts, bit tests).  Here a wavefront still handles one block, lane =
+// slot, but
+//   * the block's metadata (its own and its face neighbours' masks and first
+//     DOFs, the explicit-row mask) is read with scalar loads: every mask is
+//     wave-uniform and stays in scalar registers;
+//   * lane sets (present slots, output rows, the lanes on a face whose
+//     neighbour across it is present) are built with scalar mask arithmetic
+//     and applied as execution masks (inverse ballot);
+//   * a DOF is first DOF + the count of mask bits below the lane (two
+//     masked-bit-count instructions), for the neighbour across a face on the
+//     mask shifted by the face's slot offset;
+//   * in-block neighbours' values come from other lanes: data-parallel
+//     primitive moves inside 16-lane rows (x, and y in 3-D), lane permutes
+//     across rows (z in 3-D, y in 2-D).
+// The arithmetic and its order are those of k_lap_sh, so the outputs agree
+// bit for bit.
+template <class T>
+__device__ __forceinline__ T lane_perm(T v, int addr) {
+  if constexpr (sizeof(T) == 8) {
+    const long long b = __double_as_longlong((double)v);
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(unsigned)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(b >> 32));
+    return (T)__longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+  } else {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int((float)v)));
+  }
+}
+// value of lane (lane - k) (SHR) or (lane + k) (SHL) within a 16-lane row;
+// lanes whose source lies outside their row get an unspecified value
+template <class T, int CTRL>
+__device__ __forceinline__ T lane_dpp(T v) {
+  if constexpr (sizeof(T) == 8) {
+    const long long b = __double_as_longlong((double)v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return (T)__longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+  } else {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int((float)v), CTRL, 0xf, 0xf, false));
+  }
+}
+template <int K> constexpr int dpp_shr() { return 0x110 + K; }   // from lane - K
+template <int K> constexpr int dpp_shl() { return 0x100 + K; }   // from lane + K
+
+
+// lanes on the low and high face of the block along each axis (slots with
+// local coordinate 0, or BX - 1, along it), evaluated at compile time
+template <int DIM>
+struct FaceLanes {
+  unsigned long long lo[3], hi[3];
+};
+template <int DIM>
+constexpr FaceLanes<DIM> face_lanes() {
+  FaceLanes<DIM> f{{0ull, 0ull, 0ull}, {0ull, 0ull, 0ull}};
+  constexpr int BX = DIM == 3 ? 4 : 8;
+  for (int d = 0; d < DIM; ++d)
+    for (int s = 0; s < 64; ++s) {
+      const int l = DIM == 3 ? (d == 0 ? s & 3 : d == 1 ? (s >> 2) & 3 : s >> 4)
+                             : (d == 0 ? s & 7 : s >> 3);
+      if (l == 0) f.lo[d] |= 1ull << s;
+      if (l == BX - 1) f.hi[d] |= 1ull << s;
+    }
+  return f;
+}
+
+constexpr int kLapWBlocksPerWave = 2;
+
+template <class TU, class TA, class TV, int DIM, bool ALL, bool DOT = false>
+__global__ __launch_bounds__(256) void k_lap_w(
+    const QMeta* __restrict__ face, int nb, const TU* __restrict__ u, const TA* __restrict__ a,
+    TV* __restrict__ v, int64_t ld, int nrhs, double cd, double co,
+    const double* __restrict__ gsum, double gscale, int xcd, const double* __restrict__ coef,
+    const int* __restrict__ skip, const TV* __restrict__ dy = nullptr,
+    double* __restrict__ dpart = nullptr, int dnp = 0) {
+  using G = Geo<DIM>;
+  constexpr int BX = G::BX, KB = kLapWBlocksPerWave;
+  constexpr int step[3] = {1, BX, BX * BX};
+  constexpr FaceLanes<DIM> FL = face_lanes<DIM>();
+  const int wg = xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int blk0 = (wg * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) * KB;
+  const int lane = threadIdx.x & 63;
+  if (!DOT && blk0 >= nb) return;
+  // per block j of the wave: coefficients, lane sets, DOFs (all but the DOFs
+  // wave-uniform)
+  double cdi[KB], coi[KB];
+  unsigned long long present[KB], outm[KB], xload[KB][DIM];
+  int own[KB], xdof[KB][DIM];
+#pragma unroll
+  for (int j = 0; j < KB; ++j) {
+    const int blk = blk0 + j;
+    cdi[j] = cd;
+    coi[j] = co;
+    present[j] = outm[j] = 0ull;
+    own[j] = 0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      xload[j][d] = 0ull;
+      xdof[j][d] = 0;
+    }
+    if (blk >= nb) continue;
+    const QMeta* fb = face + (int64_t)blk * 8;
+    const unsigned long long m = fb[0].mask;
+    bool skipped = false;
+    if (coef) {
+      const int inst = fb[7].pad > 0 ? fb[7].pad : 0;
+      cdi[j] = coef[2 * inst];
+      coi[j] = coef[2 * inst + 1];
+      skipped = skip && skip[inst];
+    }
+    present[j] = skipped ? 0ull : m;
+    outm[j] = ALL ? present[j] : (present[j] & ~fb[7].mask);
+    own[j] = lane_count_below(m, fb[0].off);
+    // per axis: the DOF of the neighbour across the face the lane lies on,
+    // and the lanes that load it (on that face, neighbour present, output row)
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const int K = (BX - 1) * step[d];
+      const unsigned long long mlo = fb[2 * d + 1].mask, mhi = fb[2 * d + 2].mask;
+      // low face: neighbour slot lane + K; high face: lane - K
+      const unsigned long long slo = mlo >> K, shi = mhi << K;
+      const int blo = fb[2 * d + 1].off + __popcll(mlo & ((1ull << K) - 1ull));
+      const int dlo = lane_count_below(slo, blo), dhi = lane_count_below(shi, fb[2 * d + 2].off);
+      xdof[j][d] = lane_in(FL.lo[d]) ? dlo : dhi;
+      xload[j][d] = ((FL.lo[d] & slo) | (FL.hi[d] & shi)) & outm[j];
+    }
+  }
+  const int zl = ((lane + step[DIM - 1]) & 63) << 2, zh = ((lane - step[DIM - 1]) & 63) << 2;
+  double d0 = 0.0, d1 = 0.0;
+  for (int r = 0; r < (DOT ? 1 : nrhs); ++r) {
+    const TA* ar = a + r * ld;
+    // every load of the wave's blocks first, then the exchanges and sums
+    TA aown[KB];
+    double uv[KB], yv[KB], across[KB][DIM];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      aown[j] = TA(0);
+      uv[j] = yv[j] = 0.0;
+      if (lane_in(present[j])) aown[j] = ar[own[j]];
+      if (lane_in(outm[j])) {
+        if (!ALL) uv[j] = (double)u[r * ld + own[j]];
+        if (DOT) yv[j] = (double)dy[own[j]];
+      }
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        across[j][d] = 0.0;
+        if (lane_in(xload[j][d])) across[j][d] = (double)ar[xdof[j][d]];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      // in-block neighbours: low (-) and high (+) along each axis
+      double lo[DIM], hi[DIM];
+      lo[0] = (double)lane_dpp<TA, dpp_shr<1>()>(aown[j]);
+      hi[0] = (double)lane_dpp<TA, dpp_shl<1>()>(aown[j]);
+      if constexpr (DIM == 3) {
+        lo[1] = (double)lane_dpp<TA, dpp_shr<4>()>(aown[j]);
+        hi[1] = (double)lane_dpp<TA, dpp_shl<4>()>(aown[j]);
+      }
+      lo[DIM - 1] = (double)lane_perm<TA>(aown[j], zh);
+      hi[DIM - 1] = (double)lane_perm<TA>(aown[j], zl);
+      double sum = 0.0;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        sum += lane_in(FL.lo[d]) ? across[j][d] : lo[d];
+        sum += lane_in(FL.hi[d]) ? across[j][d] : hi[d];
+      }
+      if (lane_in(outm[j])) {
+        double o = ALL ? coi[j] * sum : lap_out(cdi[j], uv[j], coi[j], sum);
+        if (gsum) o += gscale * gsum[r];
+        const TV ov = (TV)o;
+        v[r * ld + own[j]] = ov;
+        if (DOT) {
+          d0 += yv[j] * (double)ov;
+          d1 += (double)ov * (double)ov;
+        }
+      }
+    }
+  }
+  if constexpr (DOT) wave_dot2(d0, d1, dpart, dnp, blockIdx.x * 4);
+}
+
 template <class TS, bool DOT = false>
 __global__ void k_lap_rows(int nrows, int nf, const int* __restrict__ row_id,
                            const int* __restrict__ col, const TS* __restrict__ u,
@@ -1257,7 +1452,7 @@ static int lap_groups(const cpm_band* b, const Tune& tn) {
     if (g > 8 * kLapPersistWGsPerXcd) g = 8 * kLapPersistWGsPerXcd;
     return g < 8 ? 8 : g;
   }
-  const int kb = tn.lap ? kLapShBlocksPerWave : kLapBlocksPerWave;
+  const int kb = tn.lap == 3 ? kLapWBlocksPerWave : tn.lap ? kLapShBlocksPerWave : kLapBlocksPerWave;
   return (b->nb + 4 * kb - 1) / (4 * kb);
 }
 static int lap_row_groups(const cpm_band* b) {
@@ -1286,7 +1481,10 @@ static void launch_lap(const cpm_band* b, const Tune& tn, hipStream_t st, const 
     return;
   }
   const dim3 g(lap_groups(b, tn)), t(256);
-  if (tn.lap == 2)
+  if (tn.lap == 3)
+    hipLaunchKernelGGL((k_lap_w<TU, TA, TV, DIM, ALL, DOT>), g, t, 0, st, b->blk_face, b->nb, u,
+                       a, v, ld, nrhs, cd, co, gsum, gscale, tn.xcd, coef, skip, dy, dpart, dnp);
+  else if (tn.lap == 2)
     hipLaunchKernelGGL((k_lap_pp<TU, TA, TV, DIM, ALL, DOT>), g, t, 0, st, bview(b), u, a, v, cd,
                        co, gsum, gscale, coef, skip, dy, dpart, dnp);
   else if (tn.lap)

@@ -107,13 +107,15 @@ struct Tune {
                    // prefetches the next tile's metadata, 2 also its staging
   int lap = 0;     // Laplacian pass: 0 gathers every neighbour, 1 exchanges
                    // in-block neighbours between lanes, 2 does so in
-                   // persistent wavefronts that request the next block early
+                   // persistent wavefronts that request the next block early,
+                   // 3 keeps the metadata in scalar registers and exchanges
+                   // with row moves and lane permutes (k_lap_w)
   int tuned = 0;
 };
 // variant k: pad = k & 1, order mode = (k >> 1) & 3 (0 block order, 1
 // XCD-aware, 2 persistent XCD-aware gather, 3 persistent and pipelined),
 // lap = k >> 3
-constexpr int kTuneVariants = 24;
+constexpr int kTuneVariants = 32;
 inline Tune tune_variant(int k) {
   Tune t;
   t.pad = k & 1;

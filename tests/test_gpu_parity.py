@@ -113,7 +113,7 @@ def test_apply_matches_oracle(torch_cuda, cfg, N, dtype):
 
 @pytest.mark.parametrize("cfg,N", CASES)
 def test_launch_variants_bit_identical(torch_cuda, cfg, N):
-    """Every launch variant (cpm_tune_set 0..11) computes each entry with the
+    """Every launch variant (cpm_tune_set 0 .. TUNE_VARIANTS - 1) computes each entry with the
     same arithmetic: outputs are equal bit for bit, forward with 1 and 3
     right-hand sides and transposed, FP64 and FP32."""
     torch = torch_cuda
