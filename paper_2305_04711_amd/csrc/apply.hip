@@ -976,7 +976,9 @@ __global__ __launch_bounds__(256) void k_lap_w(
     }
   }
   const int zl = ((lane + step[DIM - 1]) & 63) << 2, zh = ((lane - step[DIM - 1]) & 63) << 2;
-  double d0 = 0.0, d1 = 0.0;
+  double d0[KB], d1[KB];
+#pragma unroll
+  for (int j = 0; j < KB; ++j) d0[j] = d1[j] = 0.0;
   for (int r = 0; r < (DOT ? 1 : nrhs); ++r) {
     const TA* ar = a + r * ld;
     // every load of the wave's blocks first, then the exchanges and sums
@@ -1021,13 +1023,25 @@ __global__ __launch_bounds__(256) void k_lap_w(
         const TV ov = (TV)o;
         v[r * ld + own[j]] = ov;
         if (DOT) {
-          d0 += yv[j] * (double)ov;
-          d1 += (double)ov * (double)ov;
+          d0[j] += yv[j] * (double)ov;
+          d1[j] += (double)ov * (double)ov;
         }
       }
     }
   }
-  if constexpr (DOT) wave_dot2(d0, d1, dpart, dnp, blockIdx.x * 4);
+  // one partial per block (partial k = block k; slots past the last block
+  // get zeros), so that the partials of a batch instance are the contiguous
+  // range of its blocks
+  if constexpr (DOT) {
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const double s0 = wave_sum(d0[j], 64), s1 = wave_sum(d1[j], 64);
+      if (lane == 0) {
+        dpart[blk0 + j] = s0;
+        dpart[dnp + blk0 + j] = s1;
+      }
+    }
+  }
 }
 
 template <class TS, bool DOT = false>
@@ -1062,7 +1076,12 @@ __global__ void k_lap_rows(int nrows, int nf, const int* __restrict__ row_id,
       }
     }
   }
-  if (DOT) wave_dot2(d0, d1, dpart, dnp, doff + blockIdx.x * 2);
+  // one partial per row (rows past the last one give zeros): a batch
+  // instance's partials are the contiguous range of its explicit rows
+  if (DOT) {
+    dpart[doff + i] = d0;
+    dpart[dnp + doff + i] = d1;
+  }
 }
 
 // ---------------------------------------------------------------- gauge
@@ -1378,8 +1397,10 @@ static const Tune& tune_of(const cpm_band* b) {
 
 template <class T, int DIM, int PAD>
 static void launch_gather_k(const cpm_band* b, int k, const T* ur, double* ar, int64_t ld,
-                            int xcd, int ps, hipStream_t st) {
+                            int xcd, int ps, hipStream_t st, const int* skip) {
   const dim3 g(b->ntiles), t(64);
+  TileView tvs = tview(b);
+  tvs.skip = skip;
   if (ps == 2 && !b->tile_inst) {
     int64_t gp = ((int64_t)b->ntiles + 7) / 8 * 8;
     if (gp > 8 * (int64_t)kPersistWavesPerXcd) gp = 8 * (int64_t)kPersistWavesPerXcd;
@@ -1408,17 +1429,17 @@ static void launch_gather_k(const cpm_band* b, int k, const T* ur, double* ar, i
     return;
   }
   switch (k) {
-    case 1: hipLaunchKernelGGL((k_gather<T, DIM, 1, PAD>), g, t, 0, st, bview(b), tview(b), b->N, ur, ar, ld, xcd); break;
-    case 2: hipLaunchKernelGGL((k_gather<T, DIM, 2, PAD>), g, t, 0, st, bview(b), tview(b), b->N, ur, ar, ld, xcd); break;
-    case 3: hipLaunchKernelGGL((k_gather<T, DIM, 3, PAD>), g, t, 0, st, bview(b), tview(b), b->N, ur, ar, ld, xcd); break;
-    default: hipLaunchKernelGGL((k_gather<T, DIM, 4, PAD>), g, t, 0, st, bview(b), tview(b), b->N, ur, ar, ld, xcd); break;
+    case 1: hipLaunchKernelGGL((k_gather<T, DIM, 1, PAD>), g, t, 0, st, bview(b), tvs, b->N, ur, ar, ld, xcd); break;
+    case 2: hipLaunchKernelGGL((k_gather<T, DIM, 2, PAD>), g, t, 0, st, bview(b), tvs, b->N, ur, ar, ld, xcd); break;
+    case 3: hipLaunchKernelGGL((k_gather<T, DIM, 3, PAD>), g, t, 0, st, bview(b), tvs, b->N, ur, ar, ld, xcd); break;
+    default: hipLaunchKernelGGL((k_gather<T, DIM, 4, PAD>), g, t, 0, st, bview(b), tvs, b->N, ur, ar, ld, xcd); break;
   }
   CPM_LAUNCH_CHECK();
 }
 
 template <class T, int DIM>
 static void launch_gather(const cpm_band* b, int nrhs, const T* u, double* a, hipStream_t st,
-                          hipEvent_t* ev = nullptr) {
+                          hipEvent_t* ev, const int* skip) {
   const int64_t ld = b->n;
   int r = 0;
   while (r < nrhs) {
@@ -1427,8 +1448,8 @@ static void launch_gather(const cpm_band* b, int nrhs, const T* u, double* a, hi
     double* ar = a + r * ld;
     if (b->ntiles) {
       const Tune& tn = tune_of<T>(b);
-      if (tn.pad) launch_gather_k<T, DIM, 4>(b, k, ur, ar, ld, tn.xcd, tn.ps, st);
-      else launch_gather_k<T, DIM, 1>(b, k, ur, ar, ld, tn.xcd, tn.ps, st);
+      if (tn.pad) launch_gather_k<T, DIM, 4>(b, k, ur, ar, ld, tn.xcd, tn.ps, st, skip);
+      else launch_gather_k<T, DIM, 1>(b, k, ur, ar, ld, tn.xcd, tn.ps, st, skip);
     }
     r += k;
   }
@@ -1437,7 +1458,7 @@ static void launch_gather(const cpm_band* b, int nrhs, const T* u, double* a, hi
     const int nm = DIM == 3 ? 64 : 16;
     hipLaunchKernelGGL(k_gather_rows<T>, dim3(grid_for((int64_t)b->n_erows * nm, 256)), dim3(256),
                        0, st, b->n_erows, nm, b->erow_id, b->ecol, b->ew, u, a, ld, nrhs,
-                       b->erow_inst, b->inst_skip);
+                       b->erow_inst, skip);
     CPM_LAUNCH_CHECK();
   }
   if (ev) CPM_HIP(hipEventRecord(ev[2], st));
@@ -1459,12 +1480,23 @@ static int lap_row_groups(const cpm_band* b) {
   return b->n_lrows ? grid_for(b->n_lrows, 128) : 0;
 }
 
-// Number of partials a fused dot product of an apply writes (per value): one
-// per wavefront of the kernel that writes the output, for the launch variant
-// the band is tuned to in that precision.
+// Partials of a fused dot product written by the Laplacian pass (per value):
+// one per wavefront, or one per block slot for k_lap_w (lap 3).
+static int lap_dot_parts(const cpm_band* b, const Tune& tn) {
+  if (b->composite && tn.lap != 3) {   // composites take fused dots in lap 3 only
+    Tune t3 = tn;
+    t3.lap = 3;
+    return lap_dot_parts(b, t3);
+  }
+  return 4 * lap_groups(b, tn) * (tn.lap == 3 ? kLapWBlocksPerWave : 1);
+}
+
+// Number of partials a fused dot product of an apply writes (per value): those
+// of the Laplacian pass, for the launch variant the band is tuned to in that
+// precision, then one per thread of the explicit FD rows' kernel.
 int apply_dot_parts(const cpm_band* b, bool transpose, bool f32) {
   if (transpose) return 4 * grid_for(b->n, 256);
-  return 4 * lap_groups(b, b->tune[f32 ? 1 : 0]) + 2 * lap_row_groups(b);
+  return lap_dot_parts(b, b->tune[f32 ? 1 : 0]) + 128 * lap_row_groups(b);
 }
 
 // The Laplacian pass in the band's tuned form (k_lap or k_lap_sh).
@@ -1473,6 +1505,15 @@ static void launch_lap(const cpm_band* b, const Tune& tn, hipStream_t st, const 
                        const TA* a, TV* v, int64_t ld, int nrhs, double cd, double co,
                        const double* gsum, double gscale, const double* coef, const int* skip,
                        const TV* dy, double* dpart, int dnp) {
+  if (DOT && b->composite && tn.lap != 3) {
+    // a batch finishes each system's dot products over its own blocks'
+    // partials, which only k_lap_w writes per block
+    Tune t3 = tn;
+    t3.lap = 3;
+    launch_lap<TU, TA, TV, DIM, ALL, DOT>(b, t3, st, u, a, v, ld, nrhs, cd, co, gsum, gscale,
+                                          coef, skip, dy, dpart, dnp);
+    return;
+  }
   if (tn.lap == 2 && nrhs > 1) {   // the persistent form takes one right-hand side
     Tune t1 = tn;
     t1.lap = 1;
@@ -1506,35 +1547,63 @@ size_t apply_scratch_bytes(const cpm_band* b, int nrhs) {
 // least apply_scratch_bytes).  ev (optional): five events recorded between
 // the four phases.
 template <class T, int DIM>
+static void apply_dim_one(const cpm_band* b, double m, double n, const T* u, T* v, hipStream_t st,
+                          double* a, const int* skip, int nrhs = 1, const double* gsum = nullptr,
+                          double gamma = 0.0, hipEvent_t* ev = nullptr, const T* dy = nullptr,
+                          double* dpart = nullptr);
+
+template <class T, int DIM>
 static void apply_dim(const cpm_band* b, double m, double n, int nrhs, const T* u, T* v,
                       hipStream_t st, const double* gsum, double gamma, double* a,
                       hipEvent_t* ev = nullptr, const T* dy = nullptr, double* dpart = nullptr) {
   const int64_t ld = b->n;
+  // A batch composite applies each right-hand side in launches of its own,
+  // so that the kernels skip every converged system, not only instances
+  // whose systems have all converged (skip flags [nrhs][instances]).
+  // With fused dot products, right-hand side r writes its partials to
+  // dpart + 2 r apply_dot_parts.
+  if (b->composite && nrhs > 1 && !ev && !gsum) {
+    const int np = apply_dot_parts(b, false, sizeof(T) == 4);
+    for (int r = 0; r < nrhs; ++r)
+      apply_dim_one<T, DIM>(b, m, n, u + r * ld, v + r * ld, st, a + r * ld,
+                            b->inst_skip ? b->inst_skip + (size_t)r * b->skip_stride : nullptr,
+                            1, nullptr, 0.0, nullptr, dy ? dy + r * ld : nullptr,
+                            dy ? dpart + (size_t)2 * r * np : nullptr);
+    return;
+  }
+  apply_dim_one<T, DIM>(b, m, n, u, v, st, a, b->inst_skip, nrhs, gsum, gamma, ev, dy, dpart);
+}
+
+template <class T, int DIM>
+static void apply_dim_one(const cpm_band* b, double m, double n, const T* u, T* v, hipStream_t st,
+                          double* a, const int* skip, int nrhs, const double* gsum, double gamma,
+                          hipEvent_t* ev, const T* dy, double* dpart) {
+  const int64_t ld = b->n;
   if (ev) CPM_HIP(hipEventRecord(ev[0], st));
-  launch_gather<T, DIM>(b, nrhs, u, a, st, ev);
+  launch_gather<T, DIM>(b, nrhs, u, a, st, ev, skip);
   const double N2 = (double)b->N * (double)b->N;
   const double cd = m + n * (-2.0 * DIM * N2);
   const double co = n * N2;
   const double gscale = gsum ? gamma / (double)b->n_s : 0.0;
-  const int g1 = lap_groups(b, tune_of<T>(b)), g2 = lap_row_groups(b), np = 4 * g1 + 2 * g2;
+  const int g1 = lap_dot_parts(b, tune_of<T>(b)), g2 = lap_row_groups(b), np = g1 + 128 * g2;
   if (dy)
     launch_lap<T, double, T, DIM, false, true>(b, tune_of<T>(b), st, u, a, v, ld, nrhs, cd, co,
-                                               gsum, gscale, b->inst_coef, b->inst_skip, dy,
+                                               gsum, gscale, b->inst_coef, skip, dy,
                                                dpart, np);
   else
     launch_lap<T, double, T, DIM, false, false>(b, tune_of<T>(b), st, u, a, v, ld, nrhs, cd, co,
-                                                gsum, gscale, b->inst_coef, b->inst_skip,
+                                                gsum, gscale, b->inst_coef, skip,
                                                 nullptr, nullptr, 0);
   if (ev) CPM_HIP(hipEventRecord(ev[3], st));
   if (b->n_lrows) {
     if (dy)
       hipLaunchKernelGGL((k_lap_rows<T, true>), dim3(g2), dim3(128), 0, st, b->n_lrows, 2 * DIM,
                          b->lrow_id, b->lcol, u, a, v, ld, nrhs, cd, co, gsum, gscale,
-                         b->inst_coef, b->lrow_inst, b->inst_skip, dy, dpart, np, 4 * g1);
+                         b->inst_coef, b->lrow_inst, skip, dy, dpart, np, g1);
     else
       hipLaunchKernelGGL((k_lap_rows<T>), dim3(g2), dim3(128), 0, st, b->n_lrows, 2 * DIM,
                          b->lrow_id, b->lcol, u, a, v, ld, nrhs, cd, co, gsum, gscale,
-                         b->inst_coef, b->lrow_inst, b->inst_skip, nullptr, nullptr, 0, 0);
+                         b->inst_coef, b->lrow_inst, skip, nullptr, nullptr, 0, 0);
     CPM_LAUNCH_CHECK();
   }
   if (ev) CPM_HIP(hipEventRecord(ev[4], st));

@@ -139,25 +139,6 @@ __global__ __launch_bounds__(256) void k_binit(int nchunks, Seg g, const T* __re
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_bdot_rv(int nchunks, Seg g, const T* __restrict__ rh,
-                                                 const T* __restrict__ v, double* part,
-                                                 BScal* S) {
-  SEG_PROLOGUE;
-  if (S[s].done) return;
-  double acc[1] = {0.0};
-  for (int64_t i = lo + threadIdx.x; i < hi; i += kBT) acc[0] += (double)rh[i] * (double)v[i];
-  double tot[1];
-  if (seg_finish<1>(acc, part, nchunks, g, s, S, tot) && threadIdx.x == 0) {
-    if (tot[0] == 0.0 || !__builtin_isfinite(tot[0])) {
-      S[s].breakdown = 1;
-      S[s].done = 1;
-    } else {
-      S[s].alpha = S[s].rho / tot[0];
-    }
-  }
-}
-
-template <class T>
 __global__ __launch_bounds__(256) void k_bs(int nchunks, Seg g, const T* __restrict__ r,
                                             const T* __restrict__ v, T* __restrict__ sv,
                                             const BScal* S) {
@@ -167,21 +148,41 @@ __global__ __launch_bounds__(256) void k_bs(int nchunks, Seg g, const T* __restr
   for (int64_t i = lo + threadIdx.x; i < hi; i += kBT) sv[i] = r[i] - al * v[i];
 }
 
-template <class T>
-__global__ __launch_bounds__(256) void k_bdot_ts(int nchunks, Seg g, const T* __restrict__ t,
-                                                 const T* __restrict__ sv, double* part,
-                                                 BScal* S) {
-  SEG_PROLOGUE;
+// Finishes a dot product fused into the composite apply, one workgroup per
+// system s = r * ninst + i: the partials of right-hand side r lie at dp + 2 r
+// np (first value) and + np (second value); instance i owns the Laplacian
+// pass's block partials [boff[i], boff[i + 1]) and the explicit rows'
+// partials lp0 + [loff[i], loff[i + 1]).  Summed in a fixed order.  MODE 0:
+// alpha = rho / (rh, v); MODE 1: omega = (t, s) / (t, t).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_bdot_fin(int ninst, const double* __restrict__ dp,
+                                                  int np, int lp0, const int* __restrict__ boff,
+                                                  const int* __restrict__ loff, BScal* S) {
+  __shared__ double sh[2][kBT];
+  const int s = blockIdx.x, r = s / ninst, i = s % ninst;
   if (S[s].done) return;
-  double acc[2] = {0.0, 0.0};
-  for (int64_t i = lo + threadIdx.x; i < hi; i += kBT) {
-    const double ti = (double)t[i];
-    acc[0] += ti * (double)sv[i];
-    acc[1] += ti * ti;
+  const double* d = dp + (size_t)2 * r * np;
+  double v[2] = {0.0, 0.0};
+  for (int k = boff[i] + threadIdx.x; k < boff[i + 1]; k += kBT) {
+    v[0] += d[k];
+    v[1] += d[np + k];
   }
-  double tot[2];
-  if (seg_finish<2>(acc, part, nchunks, g, s, S, tot) && threadIdx.x == 0)
-    S[s].omega = (tot[1] == 0.0 || !__builtin_isfinite(tot[1])) ? 0.0 : tot[0] / tot[1];
+  for (int k = lp0 + loff[i] + threadIdx.x; k < lp0 + loff[i + 1]; k += kBT) {
+    v[0] += d[k];
+    v[1] += d[np + k];
+  }
+  bwg_sum<2>(v, sh);
+  if (threadIdx.x != 0) return;
+  if (MODE == 0) {
+    if (v[0] == 0.0 || !__builtin_isfinite(v[0])) {
+      S[s].breakdown = 1;
+      S[s].done = 1;
+    } else {
+      S[s].alpha = S[s].rho / v[0];
+    }
+  } else {
+    S[s].omega = (v[1] == 0.0 || !__builtin_isfinite(v[1])) ? 0.0 : v[0] / v[1];
+  }
 }
 
 template <class T, class TX>
@@ -305,6 +306,12 @@ struct cpm_batch {
   int* sfirst = nullptr;
   int* snch = nullptr;
   std::vector<int> h_csys;
+  // per instance, the range of the composite's blocks and of its explicit FD
+  // rows ([ninst + 1] each): the partials of a dot product fused into the
+  // composite apply that belong to the instance
+  std::vector<int> h_boff, h_loff;
+  int* boff = nullptr;
+  int* loff = nullptr;
   std::vector<double> m, n;
   cpm::DevAlloc da;                       // provider of the batch's device memory
   std::vector<std::pair<void*, size_t>> allocs;
@@ -374,10 +381,13 @@ void build_composite(cpm_batch* B, hipStream_t st) {
   c->lrow_inst = c->alloc<int>(nl);
   c->erow_inst = c->alloc<int>(ne);
   c->tile_inst = c->alloc<int>(nt);
-  c->inst_skip = c->alloc<int>(ni);
-  CPM_HIP(hipMemsetAsync(c->inst_skip, 0, sizeof(int) * ni, st));
+  c->inst_skip = c->alloc<int>((size_t)ni * B->nrhs);
+  c->skip_stride = ni;
+  CPM_HIP(hipMemsetAsync(c->inst_skip, 0, sizeof(int) * ni * B->nrhs, st));
   c->inst_coef = c->alloc<double>((size_t)2 * ni);
   int64_t ob = 0, ot = 0, otr = 0, oe = 0, ol = 0;
+  B->h_boff.assign(ni + 1, 0);
+  B->h_loff.assign(ni + 1, 0);
   auto g = [](int64_t n) { return dim3(grid_for(n, 256)); };
   for (int i = 0; i < ni; ++i) {
     const cpm_band* b = B->bands[i];
@@ -417,6 +427,8 @@ void build_composite(cpm_batch* B, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_int, g(b->ntiles), dim3(256), 0, st, c->tile_inst + ot,
                        (int64_t)b->ntiles, i);
     CPM_LAUNCH_CHECK();
+    B->h_boff[i] = (int)ob;
+    B->h_loff[i] = (int)ol;
     ob += b->nb;
     ot += b->ntiles;
     otr += b->n_tile_rows;
@@ -432,6 +444,14 @@ void build_composite(cpm_batch* B, hipStream_t st) {
     coef[2 * i + 1] = B->n[i] * N2;
   }
   CPM_HIP(hipMemcpyAsync(c->inst_coef, coef.data(), sizeof(double) * 2 * ni,
+                         hipMemcpyHostToDevice, st));
+  B->h_boff[ni] = (int)ob;
+  B->h_loff[ni] = (int)ol;
+  B->boff = dalloc<int>(B, ni + 1);
+  B->loff = dalloc<int>(B, ni + 1);
+  CPM_HIP(hipMemcpyAsync(B->boff, B->h_boff.data(), sizeof(int) * (ni + 1),
+                         hipMemcpyHostToDevice, st));
+  CPM_HIP(hipMemcpyAsync(B->loff, B->h_loff.data(), sizeof(int) * (ni + 1),
                          hipMemcpyHostToDevice, st));
   CPM_HIP(hipStreamSynchronize(st));
   c->tune[0] = b0->tune[0];
@@ -488,6 +508,8 @@ struct BBicg {
   int64_t len;
   T *r, *rh, *p, *v, *s, *t;
   double* part;
+  double* dpart;   // partials of the dot products fused into the applies
+  int dnp = 0, lp0 = 0;
   BScal* S;
   int* act;
   PinnedB pin;
@@ -509,6 +531,9 @@ struct BBicg {
     part = (double*)band_scratch(c, slot0 + 6, sizeof(double) * 2 * B->nchunks);
     S = (BScal*)band_scratch(c, slot0 + 7, sizeof(BScal) * B->nsys);
     act = (int*)band_scratch(c, slot0 + 8, sizeof(int) * B->nsys);
+    dnp = apply_dot_parts(c, false, sizeof(T) == 4);
+    lp0 = dnp - 128 * (c->n_lrows ? grid_for(c->n_lrows, 128) : 0);
+    dpart = (double*)band_scratch(c, slot0 + 9, sizeof(double) * 2 * (size_t)dnp * B->nrhs);
     CPM_HIP(hipMemsetAsync(S, 0, sizeof(BScal) * B->nsys, st));
     band_scratch(c, 0, apply_scratch_bytes(c, B->nrhs));
     set_active(hact);
@@ -516,7 +541,11 @@ struct BBicg {
   ~BBicg() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
   }
-  void apply(const T* in, T* out) { apply_impl<T>(B->comp.get(), 0.0, 0.0, B->nrhs, in, out, st); }
+  // out = A in; with dy, also the partials of (dy, out) and (out, out)
+  void apply(const T* in, T* out, const T* dy = nullptr) {
+    apply_impl<T>(B->comp.get(), 0.0, 0.0, B->nrhs, in, out, st, nullptr, 0.0, dy,
+                  dy ? dpart : nullptr);
+  }
   void set_active(const std::vector<int>& a) {
     hact = a;
     CPM_HIP(hipMemcpyAsync(act, hact.data(), sizeof(int) * B->nsys, hipMemcpyHostToDevice, st));
@@ -535,11 +564,15 @@ struct BBicg {
   void iteration(TX* x) {
     const Seg g = seg_of(B);
     const int nc = B->nchunks;
-    apply(p, v);
-    hipLaunchKernelGGL(k_bdot_rv<T>, dim3(nc), dim3(kBT), 0, st, nc, g, rh, v, part, S);
+    const int ns = B->nsys, ni = B->ninst;
+    // the dot products (rh, v) and (s, t), (t, t) are fused into the applies
+    apply(p, v, rh);
+    hipLaunchKernelGGL(k_bdot_fin<0>, dim3(ns), dim3(kBT), 0, st, ni, dpart, dnp, lp0, B->boff,
+                       B->loff, S);
     hipLaunchKernelGGL(k_bs<T>, dim3(nc), dim3(kBT), 0, st, nc, g, r, v, s, S);
-    apply(s, t);
-    hipLaunchKernelGGL(k_bdot_ts<T>, dim3(nc), dim3(kBT), 0, st, nc, g, t, s, part, S);
+    apply(s, t, s);
+    hipLaunchKernelGGL(k_bdot_fin<1>, dim3(ns), dim3(kBT), 0, st, ni, dpart, dnp, lp0, B->boff,
+                       B->loff, S);
     hipLaunchKernelGGL((k_bxr<T, TX>), dim3(nc), dim3(kBT), 0, st, nc, g, x, p, s, t, r, rh, part,
                        S);
     hipLaunchKernelGGL(k_bp<T>, dim3(nc), dim3(kBT), 0, st, nc, g, r, p, v, S);
@@ -621,21 +654,23 @@ struct BBicg {
     clear_skip();
     return it;
   }
-  // instances whose systems are all done are skipped by the apply kernels
+  // converged systems (instance, right-hand side) are skipped by the apply
+  // kernels, which run one launch per right-hand side (system q = r * ninst
+  // + i is flag q)
   void update_skip(const BScal* h) {
-    std::vector<int> sk(B->ninst, 1);
+    std::vector<int> sk(B->nsys, 1);
     for (int q = 0; q < B->nsys; ++q)
-      if (!h[q].done) sk[q % B->ninst] = 0;
+      if (!h[q].done) sk[q] = 0;
     if (sk != hskip) {
       hskip = sk;
-      CPM_HIP(hipMemcpyAsync(B->comp->inst_skip, hskip.data(), sizeof(int) * B->ninst,
+      CPM_HIP(hipMemcpyAsync(B->comp->inst_skip, hskip.data(), sizeof(int) * B->nsys,
                              hipMemcpyHostToDevice, st));
       CPM_HIP(hipStreamSynchronize(st));
     }
   }
   void clear_skip() {
-    hskip.assign(B->ninst, 0);
-    CPM_HIP(hipMemsetAsync(B->comp->inst_skip, 0, sizeof(int) * B->ninst, st));
+    hskip.assign(B->nsys, 0);
+    CPM_HIP(hipMemsetAsync(B->comp->inst_skip, 0, sizeof(int) * B->nsys, st));
     CPM_HIP(hipStreamSynchronize(st));
   }
   std::vector<int> hskip;

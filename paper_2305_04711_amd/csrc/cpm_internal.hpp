@@ -215,7 +215,8 @@ struct cpm_band {
   int* lrow_inst = nullptr;
   int* erow_inst = nullptr;           // instance of each explicit E row
   int* tile_inst = nullptr;           // instance of each tile
-  int* inst_skip = nullptr;           // [instances] 1: skip (all its systems done)
+  int* inst_skip = nullptr;           // [nrhs][instances] 1: skip (that system is done)
+  int skip_stride = 0;                // instances (row length of inst_skip)
   bool composite = false;
 
   int64_t on_c_nodes = 0, no_bc_dof_swaps = 0;
