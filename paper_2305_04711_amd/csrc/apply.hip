@@ -1142,7 +1142,10 @@ __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const
   constexpr int RPI = 64 / M;                 // rows per wave instruction
   constexpr int NW = DIM == 3 ? 12 : 8;       // 1-D weights per row
   __shared__ double s_z[CS];
-  __shared__ double s_w[NW][64];              // per-row 1-D weights, component major
+  // per-row 1-D weights, component major; rows padded to 65 entries so that
+  // the four values of one component a wave reads for a row lie in distinct
+  // LDS banks (a 64-entry stride maps them all to one bank)
+  __shared__ double s_w[NW][65];
   __shared__ int s_b[64];                     // per-row cube offset of member 0
   const int t = list[xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x];
   const int lane = threadIdx.x;
