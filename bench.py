@@ -44,8 +44,14 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 # profiles/gather_torus512_pmc.md), each scaled by the same counter's reading
 # for a plain device copy of known size.  They hold only for the kernel
 # source they were taken on: `traffic` is null when its hash differs.
-GATHER_PMC = {"sources_sha1": "b1c8cb90e7a9f14f5b26e931871ddf54e1f24d66",
-              "fetch_bytes": 1.49399e+09, "write_bytes": 2.96511e+08}
+GATHER_PMC = {"sources_sha1": "c47fc547390d68e6e1bd09f5f46c57e16715f910",
+              "fetch_bytes": 1.55929e+09, "write_bytes": 2.95454e+08}
+# The same runs for the whole FP64 apply (tile gather, explicit E rows,
+# Laplacian pass, explicit L rows; profiles/*_torus512_pmc.md), valid while
+# the hash of apply.hip, lagrange.hpp and builder.hip is the one below.
+APPLY_PMC = {"sources_sha1": "37ce87f05d8af8532e63f043a2e759261363ee9c",
+             "bytes": {"tile gather": 1.85475e+09, "explicit E rows": 2.07574e+08,
+                       "block Laplacian": 1.05250e+09, "explicit L rows": 1.61e+07}}
 
 
 def gather_sources_sha1():
@@ -58,6 +64,15 @@ def gather_sources_sha1():
     b = src.index("template <class T>\n__device__ __forceinline__ T wave_sum")
     h = hashlib.sha1(src[a:b].encode())
     for f in ("lagrange.hpp", "builder.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2305_04711_amd/csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def apply_sources_sha1():
+    """Hash of every source that sets the whole apply's traffic."""
+    import hashlib
+    h = hashlib.sha1()
+    for f in ("apply.hip", "lagrange.hpp", "builder.hip"):
         h.update(open(os.path.join(ROOT, "paper_2305_04711_amd/csrc", f), "rb").read())
     return h.hexdigest()
 
@@ -588,6 +603,9 @@ def main():
     traffic = None
     if GATHER_PMC["sources_sha1"] is not None and GATHER_PMC["sources_sha1"] == gather_sources_sha1():
         traffic = GATHER_PMC["fetch_bytes"] + GATHER_PMC["write_bytes"]
+    apply_traffic = None
+    if APPLY_PMC["sources_sha1"] == apply_sources_sha1():
+        apply_traffic = sum(APPLY_PMC["bytes"].values())
     del u32, v32
 
     solves = None
@@ -723,7 +741,10 @@ def main():
                      "launch_ms": ph64[0]},
         "apply_roofline": {"f64": {"gnodes_per_s": gn64, "bytes_per_row": BYTES_PER_ROW_F64,
                                    "achieved_gbs": gn64 * BYTES_PER_ROW_F64,
-                                   "frac": gn64 * BYTES_PER_ROW_F64 / HBM_PEAK_GBS},
+                                   "frac": gn64 * BYTES_PER_ROW_F64 / HBM_PEAK_GBS,
+                                   "traffic": apply_traffic,
+                                   "traffic_vs_algorithmic": None if apply_traffic is None else
+                                   apply_traffic / (BYTES_PER_ROW_F64 * dofs)},
                            "f32": {"gnodes_per_s": gn32, "bytes_per_row": BYTES_PER_ROW_F32,
                                    "achieved_gbs": gn32 * BYTES_PER_ROW_F32,
                                    "frac": gn32 * BYTES_PER_ROW_F32 / HBM_PEAK_GBS}},

@@ -385,9 +385,10 @@ def solve(band, b, m, n, tol=1e-8, mode="mixed", x0=None, maxit=0, inner_tol=0.0
 
 
 def solve_adjoint(band, rhs_, m, n, tol=1e-8, mode="mixed", x0=None, maxit=0, inner_tol=0.0,
-                  check_every=0, use_graph=True, raise_noconv=True):
+                  check_every=0, use_graph=True, raise_noconv=True, restart=0):
+    """Solve A^T lam = rhs_ (the adjoint system), modes as for solve."""
     return _solve(band._lib.cpm_solve_adjoint, band, rhs_, m, n, tol, mode, x0, maxit,
-                  inner_tol, check_every, use_graph, 0.0, raise_noconv)
+                  inner_tol, check_every, use_graph, 0.0, raise_noconv, restart)
 
 
 def _check_attained(stats, tol, what):

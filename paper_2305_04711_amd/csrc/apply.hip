@@ -108,30 +108,28 @@ __device__ __forceinline__ void row_stencil(const TileView& tv, int pos, int lb[
 // ---------------------------------------------------------------- pass 1
 // Interpolation of one row from the staged cube (sum-factorised tensor
 // product): x lines first, then y, then z.  FP64 arithmetic.
-template <int DIM, int NR, int CSZ, int E, int EP, class TL>
-__device__ __forceinline__ void interp_row(const TL (&s_u)[NR][CSZ], int p, const int lb[3],
-                                           const double tt[3], double acc[NR]) {
-  double wx[4], wy[4], wz[4];
-  lagrange_p<double>(p, tt[0], wx);
-  lagrange_p<double>(p, tt[1], wy);
-  if (DIM == 3) lagrange_p<double>(p, tt[2], wz);
+// NP = p + 1 stencil nodes per axis (4 cubic, 3 quadratic).
+template <int DIM, int NR, int CSZ, int E, int EP, class TL, int NP>
+__device__ __forceinline__ void interp_row_np(const TL (&s_u)[NR][CSZ], const double wx[4],
+                                              const double wy[4], const double wz[4],
+                                              const int lb[3], double acc[NR]) {
   const int lx = lb[0], ly = lb[1], lz = lb[2];
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = 0.0;
   if (DIM == 3) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < NP; ++c) {
       double accz[NR];
 #pragma unroll
       for (int r = 0; r < NR; ++r) accz[r] = 0.0;
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
+      for (int b = 0; b < NP; ++b) {
         const int base = ((lz + c) * E + (ly + b)) * EP + lx;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
           const TL* row = &s_u[r][base];
-          const double x = wx[0] * (double)row[0] + wx[1] * (double)row[1] +
-                           wx[2] * (double)row[2] + wx[3] * (double)row[3];
+          double x = wx[0] * (double)row[0] + wx[1] * (double)row[1] + wx[2] * (double)row[2];
+          if (NP == 4) x += wx[3] * (double)row[3];
           accz[r] += wy[b] * x;
         }
       }
@@ -140,17 +138,31 @@ __device__ __forceinline__ void interp_row(const TL (&s_u)[NR][CSZ], int p, cons
     }
   } else {
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < NP; ++b) {
       const int base = (ly + b) * EP + lx;
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         const TL* row = &s_u[r][base];
-        const double x = wx[0] * (double)row[0] + wx[1] * (double)row[1] +
-                         wx[2] * (double)row[2] + wx[3] * (double)row[3];
+        double x = wx[0] * (double)row[0] + wx[1] * (double)row[1] + wx[2] * (double)row[2];
+        if (NP == 4) x += wx[3] * (double)row[3];
         acc[r] += wy[b] * x;
       }
     }
   }
+}
+
+// NP = 4 serves cubic rows and quadratic rows in the padded layout (fourth
+// weight 0); NP = 3 is the quadratic form of the non-persistent tile gather:
+// 27 members and 39 multiply-adds instead of 64 and 84 (both forms give the
+// same sums up to the sign of a zero).
+template <int DIM, int NR, int CSZ, int E, int EP, class TL, int NP = 4>
+__device__ __forceinline__ void interp_row(const TL (&s_u)[NR][CSZ], int p, const int lb[3],
+                                           const double tt[3], double acc[NR]) {
+  double wx[4], wy[4], wz[4] = {0.0, 0.0, 0.0, 0.0};
+  lagrange_p<double>(NP == 3 ? 2 : p, tt[0], wx);
+  lagrange_p<double>(NP == 3 ? 2 : p, tt[1], wy);
+  if (DIM == 3) lagrange_p<double>(NP == 3 ? 2 : p, tt[2], wz);
+  interp_row_np<DIM, NR, CSZ, E, EP, TL, NP>(s_u, wx, wy, wz, lb, acc);
 }
 
 // One wavefront per tile: stage the (2 BX)^d cube of u into LDS (x lines
@@ -168,7 +180,7 @@ __device__ __forceinline__ void interp_row(const TL (&s_u)[NR][CSZ], int p, cons
 // At most 6 waves per SIMD keeps the register use in check (left to itself
 // the compiler hoists every LDS read of a row and the occupancy drops to 4
 // waves per SIMD, about 1.5x slower).
-template <class TS, int DIM, int NR, int PAD>
+template <class TS, int DIM, int NR, int PAD, int NP = 4>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void k_gather(
     BlockView B, TileView tv, int N, const TS* __restrict__ u, double* __restrict__ a, int64_t ld,
     int xcd) {
@@ -209,7 +221,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void k_
     const int dof = tv.perm[pos];
     if (pos + 64 < end) row_stencil<TS, DIM>(tv, pos + 64, lb, tt);
     double acc[NR];
-    interp_row<DIM, NR, CS, E, EP, TS>(s_u, tv.p, lbc, tc, acc);
+    interp_row<DIM, NR, CS, E, EP, TS, NP>(s_u, tv.p, lbc, tc, acc);
 #pragma unroll
     for (int r = 0; r < NR; ++r) a[r * ld + dof] = acc[r];
   }
@@ -1427,6 +1439,16 @@ static void launch_gather_k(const cpm_band* b, int k, const T* ur, double* ar, i
       case 2: hipLaunchKernelGGL((k_gather_ps<T, DIM, 2, PAD>), gq, t, 0, st, bview(b), tview(b), b->N, ur, ar, ld, b->ntiles); break;
       case 3: hipLaunchKernelGGL((k_gather_ps<T, DIM, 3, PAD>), gq, t, 0, st, bview(b), tview(b), b->N, ur, ar, ld, b->ntiles); break;
       default: hipLaunchKernelGGL((k_gather_ps<T, DIM, 4, PAD>), gq, t, 0, st, bview(b), tview(b), b->N, ur, ar, ld, b->ntiles); break;
+    }
+    CPM_LAUNCH_CHECK();
+    return;
+  }
+  if (b->p == 2) {
+    switch (k) {
+      case 1: hipLaunchKernelGGL((k_gather<T, DIM, 1, PAD, 3>), g, t, 0, st, bview(b), tvs, b->N, ur, ar, ld, xcd); break;
+      case 2: hipLaunchKernelGGL((k_gather<T, DIM, 2, PAD, 3>), g, t, 0, st, bview(b), tvs, b->N, ur, ar, ld, xcd); break;
+      case 3: hipLaunchKernelGGL((k_gather<T, DIM, 3, PAD, 3>), g, t, 0, st, bview(b), tvs, b->N, ur, ar, ld, xcd); break;
+      default: hipLaunchKernelGGL((k_gather<T, DIM, 4, PAD, 3>), g, t, 0, st, bview(b), tvs, b->N, ur, ar, ld, xcd); break;
     }
     CPM_LAUNCH_CHECK();
     return;
