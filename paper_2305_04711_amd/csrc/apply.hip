@@ -1130,20 +1130,27 @@ __global__ void k_sum_final(const double* part, int np, double* out) {
 }
 
 // ---------------------------------------------------------------- transpose
-// E^T c for the tile rows of one parity class, one wavefront per tile.  Each
-// lane first puts the stencil base of one row into LDS with the row's 1-D
-// weights (the forward gather's FP64 weights), c_i folded into the last
-// factor; then the wave walks the rows with one lane per stencil member (4
-// rows at a time in 2-D, where a stencil has 16 members), adding w c_i into
-// the tile's (2 BX)^d cube in LDS.  A 3-D member's weight is the product of
-// three 1-D weights read from LDS, and each lane sums over runs of rows with
-// the same stencil base; 2-D uses LDS atomic adds (rows past the last one
-// carry zero weights).  The cube is accumulated in FP64 for both precisions.
-// The cube is then added into z with plain loads and stores: tiles of one
-// parity class stage disjoint blocks and the classes run as successive
-// launches, so no two waves of a launch touch the same entry of z.
+// E^T c for the tile rows of one parity class, one wavefront per tile.  The
+// wave takes its tile and row range from one entry of the class table, so the
+// tile's metadata, row data and old z entries are requested in one round
+// trip.  Rows go in chunks of kTRows: each lane of a chunk puts the stencil
+// base of one row into LDS with the row's 1-D weights (the forward gather's
+// FP64 weights), c_i folded into the last factor; then the wave walks the
+// chunk's rows with one lane per stencil member (4 rows at a time in 2-D,
+// where a stencil has 16 members), adding w c_i into the tile's (2 BX)^d cube
+// in LDS.  A 3-D member's weight is the product of three 1-D weights read
+// from LDS, and each lane sums over runs of rows with the same stencil base;
+// 2-D uses LDS atomic adds (rows past the last one carry zero weights).  The
+// cube is accumulated in FP64 for both precisions.  It is then added into z
+// with plain loads and stores: tiles of one parity class stage disjoint
+// blocks and the classes run as successive launches, so no two waves of a
+// launch touch the same entry of z.  Chunks of 32 rows keep the LDS of a wave
+// at 7.9 KB (5 waves per SIMD with the cube) where whole 64-row passes took
+// 11.1 KB (3).
+constexpr int kTRows = 32;
+constexpr int kTGroup = 4;
 template <class TS, int DIM>
-__global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const int* __restrict__ list,
+__global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const int4* __restrict__ tbl,
                                                  int N, const double* __restrict__ c,
                                                  double* __restrict__ z, int64_t ld, int r,
                                                  int xcd) {
@@ -1153,17 +1160,19 @@ __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const
   constexpr int M = DIM == 3 ? 64 : 16;       // stencil members
   constexpr int RPI = 64 / M;                 // rows per wave instruction
   constexpr int NW = DIM == 3 ? 12 : 8;       // 1-D weights per row
+  constexpr int RC = kTRows;
+  constexpr int RG = kTGroup;                 // rows whose LDS reads go out together
+  static_assert(RC % 16 == 0 && RC <= 64 && RC % RG == 0, "chunk rows: a multiple of 16 and RG");
   __shared__ double s_z[CS];
-  // per-row 1-D weights, component major; rows padded to 65 entries so that
-  // the four values of one component a wave reads for a row lie in distinct
-  // LDS banks (a 64-entry stride maps them all to one bank)
-  __shared__ double s_w[NW][65];
-  __shared__ int s_b[64];                     // per-row cube offset of member 0
-  const int t = list[xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x];
-  const int lane = threadIdx.x;
-  const int beg = tv.tile_start[t], end = tv.tile_start[t + 1];
+  // per-row 1-D weights, component major; rows padded to RC + 1 entries so
+  // that the four values of one component a wave reads for a row lie in
+  // distinct LDS banks
+  __shared__ double s_w[NW][RC + 1];
+  __shared__ int s_b[RC];                     // per-row cube offset of member 0
+  const int4 te = tbl[xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x];
+  const int t = te.x, beg = te.y, end = te.z;
   if (beg == end) return;
-  for (int idx = lane; idx < CS; idx += 64) s_z[idx] = 0.0;
+  const int lane = threadIdx.x;
   unsigned long long qm = 0ull;
   int qoff = 0;
   if (lane < NQ) {
@@ -1171,33 +1180,57 @@ __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const
     qm = q.mask;
     qoff = q.off;
   }
-  // the old entries of z under the staged blocks, requested now so that the
-  // loads overlap the row work (no other wave of this launch writes them)
+  // entry of z (or -1) of this lane's node in staged block q, and its cube cell
   const int cx0 = G::lx(lane), cy0 = G::ly(lane), cz0 = G::lz(lane);
-  int zi[NQ];
+  auto zidx = [&](int q) {
+    const unsigned long long m = lane_u64(qm, q);
+    const int off = lane_i32(qoff, q);
+    return ((m >> lane) & 1ull) ? off + __popcll(m & ((1ull << lane) - 1ull)) : -1;
+  };
+  auto cell = [&](int q) {
+    const int qx = q & 1, qy = (q >> 1) & 1, qz = DIM == 3 ? (q >> 2) : 0;
+    const int cx = qx * G::BX + cx0, cy = qy * G::BX + cy0, cz = qz * G::BX + cz0;
+    return DIM == 3 ? (cz * E + cy) * EP + cx : cy * EP + cx;
+  };
+  // the old entries of z under the staged blocks, requested now so that the
+  // loads overlap the row work (no other wave of this launch touches them);
+  // the cube starts at zero and is added to them at the end
   double old[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
-    const unsigned long long m = lane_u64(qm, q);
-    const int off = lane_i32(qoff, q);
-    zi[q] = ((m >> lane) & 1ull) ? off + __popcll(m & ((1ull << lane) - 1ull)) : -1;
-    old[q] = zi[q] >= 0 ? z[r * ld + zi[q]] : 0.0;
+    const int zi = zidx(q);
+    old[q] = zi >= 0 ? z[r * ld + zi] : 0.0;
   }
+  for (int idx = lane; idx < CS; idx += 64) s_z[idx] = 0.0;
   // this lane's stencil member and row slot within an instruction
   const int mo = lane & (M - 1), sub = lane / M;
   const int ma = mo & 3, mb = (mo >> 2) & 3, mc = DIM == 3 ? (mo >> 4) : 0;
   const int moff = DIM == 3 ? (mc * E + mb) * EP + ma : mb * EP + ma;
-  for (int p0 = beg; p0 < end; p0 += 64) {
-    const int nrow = min(64, end - p0);
+  // Row data of a chunk (lane < RC: row p0 + lane): local base, fraction
+  // and c.  The next chunk's is requested before the current chunk's rows
+  // are walked, and the DOFs (which c is read through) one chunk further
+  // ahead, so only the first chunk waits for its loads.
+  int lbn[3] = {0, 0, 0}, pmn = 0;
+  double ttn[3] = {0.0, 0.0, 0.0}, cn = 0.0;
+  if (lane < RC && beg + lane < end) {
+    row_stencil<TS, DIM>(tv, beg + lane, lbn, ttn);
+    cn = c[r * ld + tv.perm[beg + lane]];
+  }
+  if (lane < RC && beg + RC + lane < end) pmn = tv.perm[beg + RC + lane];
+  for (int p0 = beg; p0 < end; p0 += RC) {
+    const int nrow = min(RC, end - p0);
+    const int lb[3] = {lbn[0], lbn[1], lbn[2]};
+    const double tt[3] = {ttn[0], ttn[1], ttn[2]}, ci = cn;
+    const int p1 = p0 + RC;
+    if (lane < RC && p1 + lane < end) {
+      row_stencil<TS, DIM>(tv, p1 + lane, lbn, ttn);
+      cn = c[r * ld + pmn];
+    }
+    if (lane < RC && p1 + RC + lane < end) pmn = tv.perm[p1 + RC + lane];
     double wx[4] = {0.0, 0.0, 0.0, 0.0}, wy[4] = {0.0, 0.0, 0.0, 0.0};
     double wz[4] = {0.0, 0.0, 0.0, 0.0};
     int bs = 0;
     if (lane < nrow) {
-      const int pos = p0 + lane;
-      const double ci = c[r * ld + tv.perm[pos]];
-      int lb[3];
-      double tt[3];
-      row_stencil<TS, DIM>(tv, pos, lb, tt);
       lagrange_p<double>(tv.p, tt[0], wx);
       lagrange_p<double>(tv.p, tt[1], wy);
       if (DIM == 3) {
@@ -1210,13 +1243,15 @@ __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const
       }
       bs = DIM == 3 ? (lb[2] * E + lb[1]) * EP + lb[0] : lb[1] * EP + lb[0];
     }
+    if (lane < RC) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      s_w[k][lane] = wx[k];
-      s_w[4 + k][lane] = wy[k];
-      if constexpr (DIM == 3) s_w[8 + k][lane] = wz[k];
+      for (int k = 0; k < 4; ++k) {
+        s_w[k][lane] = wx[k];
+        s_w[4 + k][lane] = wy[k];
+        if constexpr (DIM == 3) s_w[8 + k][lane] = wz[k];
+      }
+      s_b[lane] = bs;
     }
-    s_b[lane] = bs;
     __syncthreads();
     if constexpr (DIM == 3) {
       // Rows are sorted by stencil base, and runs of rows share one: each
@@ -1226,17 +1261,17 @@ __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const
       // complete in order, so these read-add-writes need no atomics.
       double acc = 0.0;
       int cur = __builtin_amdgcn_readfirstlane(s_b[0]);
-      for (int j = 0; j < nrow; j += 8) {
-        // eight rows' bases and weights read at once (indices stay below 64)
-        int bq[8];
-        double wq[8];
+      for (int j = 0; j < nrow; j += RG) {
+        // RG rows' bases and weights read at once (indices stay below RC)
+        int bq[RG];
+        double wq[RG];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < RG; ++u) {
           bq[u] = __builtin_amdgcn_readfirstlane(s_b[j + u]);
           wq[u] = (s_w[ma][j + u] * s_w[4 + mb][j + u]) * s_w[8 + mc][j + u];
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < RG; ++u) {
           if (j + u >= nrow) break;
           if (bq[u] != cur) {
             s_z[cur + moff] += acc;
@@ -1267,30 +1302,31 @@ __global__ __launch_bounds__(64) void k_gather_T(BlockView B, TileView tv, const
   }
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
-    const int qx = q & 1, qy = (q >> 1) & 1, qz = DIM == 3 ? (q >> 2) : 0;
-    const int cx = qx * G::BX + cx0, cy = qy * G::BX + cy0, cz = qz * G::BX + cz0;
-    const int ci = DIM == 3 ? (cz * E + cy) * EP + cx : cy * EP + cx;
-    if (zi[q] >= 0) z[r * ld + zi[q]] = old[q] + s_z[ci];
+    const int zi = zidx(q);
+    if (zi >= 0) z[r * ld + zi] = old[q] + s_z[cell(q)];
   }
 }
 
-// E^T c over the explicit rows by pull lists, in two balanced passes: every
-// entry's product w c_i (FP64 weights and c), then one thread per target DOF
-// sums its contiguous segment in ascending source order and adds it to z
-// once: the same value on every run, with no atomics.
-__global__ void k_et_prod(int total, const int* __restrict__ row, const double* __restrict__ w,
-                          const double* __restrict__ c, double* __restrict__ prod) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < total) prod[e] = w[e] * c[row[e]];
-}
-
-__global__ void k_et_sum(int n_tgt, const int* __restrict__ tgt, const int* __restrict__ start,
-                         const double* __restrict__ prod, double* __restrict__ z) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n_tgt) return;
+// E^T c over the explicit rows by pull lists: one wavefront per target DOF
+// (four per workgroup).  The lanes take the target's contiguous segment of
+// entries 64 at a time (entry e: weight w[e] of source row src[e], FP64 for
+// both precisions), sum the products w c_src in their own order and the wave
+// adds the tree sum of its lanes into z once: the same value on every run,
+// with no atomics.
+__global__ __launch_bounds__(256) void k_et_pull(int n_tgt, const int* __restrict__ tgt,
+                                                 const int* __restrict__ start,
+                                                 const int* __restrict__ src,
+                                                 const double* __restrict__ w,
+                                                 const double* __restrict__ c,
+                                                 double* __restrict__ z) {
+  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (k >= n_tgt) return;                     // whole waves leave together
+  const int lane = threadIdx.x & 63;
+  const int b0 = start[k], b1 = start[k + 1];
   double acc = 0.0;
-  for (int e = start[k]; e < start[k + 1]; ++e) acc += prod[e];
-  z[tgt[k]] += acc;
+  for (int e = b0 + lane; e < b1; e += 64) acc += w[e] * c[src[e]];
+  acc = wave_sum(acc, 64);
+  if (lane == 0) z[tgt[k]] += acc;
 }
 
 // The corrections of (L - diag L)^T w for explicit FD rows by pull lists:
@@ -1706,14 +1742,9 @@ static void apply_T_dim(const cpm_band* b, double m, double n, int nrhs, const T
   }
   if (b->et_tgt) {
     if (b->n_et) {
-      double* prod = static_cast<double*>(
-          band_scratch(b, kEtProdSlot, sizeof(double) * (size_t)b->n_et_entries));
-      for (int r = 0; r < nrhs; ++r) {
-        hipLaunchKernelGGL(k_et_prod, dim3(grid_for(b->n_et_entries, 256)), dim3(256), 0, st,
-                           b->n_et_entries, b->et_src, b->et_w, c + r * ld, prod);
-        hipLaunchKernelGGL(k_et_sum, dim3(grid_for(b->n_et, 256)), dim3(256), 0, st, b->n_et,
-                           b->et_tgt, b->et_start, prod, e + r * ld);
-      }
+      for (int r = 0; r < nrhs; ++r)
+        hipLaunchKernelGGL(k_et_pull, dim3((b->n_et + 3) / 4), dim3(256), 0, st, b->n_et,
+                           b->et_tgt, b->et_start, b->et_src, b->et_w, c + r * ld, e + r * ld);
       CPM_LAUNCH_CHECK();
     }
   } else if (b->n_erows) {

@@ -1391,23 +1391,27 @@ void build(cpm_band* b, hipStream_t st, const Filter& F) {
                        B, b->ntiles, 1 << DIM, G::NNBR, b->tile_blk, b->tile_meta);
   CPM_LAUNCH_CHECK();
   // transpose schedule: tiles grouped by parity class (stable in tile order)
-  b->tile_col = b->alloc<int>(b->ntiles);
+  b->tile_col = b->alloc<int4>(b->ntiles);
   std::fill(b->col_start, b->col_start + 9, 0);
   if (b->ntiles) {
     Tmp<int> colour(b, b->ntiles);
     hipLaunchKernelGGL(k_tile_colour, dim3(grid_for(b->ntiles, 256)), dim3(256), 0, st, b->ntiles,
                        b->tile_blk, b->blk_coord, colour.p);
     CPM_LAUNCH_CHECK();
-    std::vector<int> hcol(b->ntiles), order(b->ntiles);
+    std::vector<int> hcol(b->ntiles), hstart(b->ntiles + 1);
+    std::vector<int4> order(b->ntiles);
     CPM_HIP(hipMemcpyAsync(hcol.data(), colour.p, sizeof(int) * b->ntiles, hipMemcpyDeviceToHost,
                            st));
+    CPM_HIP(hipMemcpyAsync(hstart.data(), b->tile_start, sizeof(int) * (b->ntiles + 1),
+                           hipMemcpyDeviceToHost, st));
     CPM_HIP(hipStreamSynchronize(st));
     for (int t = 0; t < b->ntiles; ++t) ++b->col_start[hcol[t] + 1];
     for (int k = 0; k < 8; ++k) b->col_start[k + 1] += b->col_start[k];
     int next[8];
     std::copy(b->col_start, b->col_start + 8, next);
-    for (int t = 0; t < b->ntiles; ++t) order[next[hcol[t]]++] = t;
-    CPM_HIP(hipMemcpyAsync(b->tile_col, order.data(), sizeof(int) * b->ntiles,
+    for (int t = 0; t < b->ntiles; ++t)
+      order[next[hcol[t]]++] = make_int4(t, hstart[t], hstart[t + 1], 0);
+    CPM_HIP(hipMemcpyAsync(b->tile_col, order.data(), sizeof(int4) * b->ntiles,
                            hipMemcpyHostToDevice, st));
     CPM_HIP(hipStreamSynchronize(st));
   }

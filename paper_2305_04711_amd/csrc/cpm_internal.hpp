@@ -171,8 +171,9 @@ struct cpm_band {
   float* frac32 = nullptr;            // [dim][n_tile_rows] FP32 fractions
   unsigned int* lbase = nullptr;      // [n_tile_rows] packed local base
   // tiles grouped by the parity class of their block (k_tile_colour): class
-  // k is tile_col[col_start[k] .. col_start[k + 1])
-  int* tile_col = nullptr;            // [ntiles]
+  // k is tile_col[col_start[k] .. col_start[k + 1]), each entry {tile, first
+  // row, end row, 0} (the tile's range in the tile-row arrays)
+  int4* tile_col = nullptr;           // [ntiles]
   int col_start[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 
   // rows with explicit interpolation stencils (swapped PDE rows, BC rows)
@@ -252,8 +253,6 @@ struct Workspace {
 };
 void* band_scratch(const cpm_band* b, int slot, size_t bytes);
 size_t band_scratch_bytes(const cpm_band* b);
-// scratch slot of the transposed apply's per-entry products (E pull lists)
-constexpr int kEtProdSlot = 6;
 
 // Device-wide exclusive scan; returns the total (synchronises the stream).
 // Its temporaries come from da.

@@ -406,8 +406,6 @@ struct Bicg {
     if (transpose) {
       band_scratch(b, 1, sizeof(double) * (size_t)n);
       band_scratch(b, 2, sizeof(double) * (size_t)n);
-      if (b->n_et_entries)
-        band_scratch(b, kEtProdSlot, sizeof(double) * (size_t)b->n_et_entries);
     }
   }
   ~Bicg() {
