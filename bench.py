@@ -44,14 +44,14 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 # profiles/gather_torus512_pmc.md), each scaled by the same counter's reading
 # for a plain device copy of known size.  They hold only for the kernel
 # source they were taken on: `traffic` is null when its hash differs.
-GATHER_PMC = {"sources_sha1": "c47fc547390d68e6e1bd09f5f46c57e16715f910",
-              "fetch_bytes": 1.55929e+09, "write_bytes": 2.95454e+08}
+GATHER_PMC = {"sources_sha1": "e4066e88c4830d6513d724d3a62b3e3b3cc9c63c",
+              "fetch_bytes": 1.56062e+09, "write_bytes": 2.96609e+08}
 # The same runs for the whole FP64 apply (tile gather, explicit E rows,
 # Laplacian pass, explicit L rows; profiles/*_torus512_pmc.md), valid while
 # the hash of apply.hip, lagrange.hpp and builder.hip is the one below.
-APPLY_PMC = {"sources_sha1": "37ce87f05d8af8532e63f043a2e759261363ee9c",
-             "bytes": {"tile gather": 1.85475e+09, "explicit E rows": 2.07574e+08,
-                       "block Laplacian": 1.05250e+09, "explicit L rows": 1.61e+07}}
+APPLY_PMC = {"sources_sha1": "7234960834313fefb6193fa1cfdd625264541978",
+             "bytes": {"tile gather": 1.85723e+09, "explicit E rows": 2.07567e+08,
+                       "block Laplacian": 1.05252e+09, "explicit L rows": 1.61315e+07}}
 
 
 def gather_sources_sha1():
