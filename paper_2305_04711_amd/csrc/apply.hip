@@ -1132,8 +1132,8 @@ __global__ void k_sum_final(const double* part, int np, double* out) {
 // ---------------------------------------------------------------- transpose
 // E^T c for the tile rows of one parity class, one wavefront per tile.  The
 // wave takes its tile and row range from one entry of the class table, so the
-// tile's metadata, row data and old z entries are requested in one round
-// trip.  Rows go in chunks of kTRows: each lane of a chunk puts the stencil
+// tile's metadata and first row data are requested together, one load after
+// it.  Rows go in chunks of kTRows: each lane of a chunk puts the stencil
 // base of one row into LDS with the row's 1-D weights (the forward gather's
 // FP64 weights), c_i folded into the last factor; then the wave walks the
 // chunk's rows with one lane per stencil member (4 rows at a time in 2-D,
@@ -1145,8 +1145,7 @@ __global__ void k_sum_final(const double* part, int np, double* out) {
 // with plain loads and stores: tiles of one parity class stage disjoint
 // blocks and the classes run as successive launches, so no two waves of a
 // launch touch the same entry of z.  Chunks of 32 rows keep the LDS of a wave
-// at 7.9 KB (5 waves per SIMD with the cube) where whole 64-row passes took
-// 11.1 KB (3).
+// at 7.9 KB (20 waves per CU) where whole 64-row passes took 11.1 KB (14).
 constexpr int kTRows = 32;
 constexpr int kTGroup = 4;
 template <class TS, int DIM>

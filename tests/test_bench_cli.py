@@ -32,3 +32,16 @@ def test_batch_needs_one_coefficient_pair_per_band():
                               ([object()], [1.0], [-1.0], 0)):
         with pytest.raises(ValueError):
             cpm.Batch(bands, m, n, nrhs)
+
+
+def test_counter_hash_ignores_comments_but_not_code():
+    # the counters bench.py reports as `traffic` stay valid across comment
+    # edits and are dropped when the code itself changes
+    sys.path.insert(0, ROOT)
+    import bench
+    src = 'int f(int a) { // one\n  /* two\n three */ return a + 1; }\nconst char* s = "x//y";\n'
+    same = 'int f(int a) {\n  return a + 1;   // other words\n}\nconst char* s = "x//y";'
+    other = 'int f(int a) { return a + 2; }\nconst char* s = "x//y";'
+    assert bench._code(src) == bench._code(same)
+    assert bench._code(src) != bench._code(other)
+    assert '"x//y"' in bench._code(src)
